@@ -1,0 +1,656 @@
+/*
+ * Plain FP64 CPU oracle for one implicit-Euler step of a plastic network of
+ * multi-compartment neurons (Plastic Arbor, arXiv 2411.16445).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the HIP library is checked against.  It is called only by
+ * the test-suite, by the smoke check and by the CPU-baseline leg of the
+ * benchmark; the product path never links, loads or executes it, and it
+ * shares no source, header or helper with the HIP library.
+ *
+ * What one step n -> n+1 (t_n = n dt) computes, in this order:
+ *  1. deliver every queued event whose delivery step is n, ordered by
+ *     (t_e, source, connection, port): conductance port g += w (h + h0 z)/h0
+ *     for tagging-and-capture synapses (total weight, Eq. 16, normalised to
+ *     its baseline) or g += w for plain exponential synapses; calcium port
+ *     c += c_pre (Eq. 19).  Then the post-synaptic hook: every synapse of a
+ *     cell that fired in step n-1 gets c += c_post (Sec. 2.1, Eq. 19).
+ *  2. membrane current I and conductance G = dI/dV at V^n per CV, summed in
+ *     a fixed order: Hodgkin-Huxley, synapses by (CV, id), clamps (the
+ *     ohmic current sum of Sec. 2.4).
+ *  3. assembly of the cable system, linearised backward Euler on the
+ *     finite-volume discretisation of the cable equation (Eq. 4),
+ *  4. Hines elimination over the tree (descending index, then forward
+ *     substitution),
+ *  5. HH gates by exact exponential integration at V^{n+1}; exponential
+ *     decay of every synaptic conductance,
+ *  6. plasticity (Eqs. 17, 18, 20, 21): per cell S = sum |h - h0| over its
+ *     tagging synapses from step-start h; Euler-Maruyama step of h (Sec. 2.3)
+ *     with Threefry-4x64-12 + Box-Muller noise; z; calcium decay; then p,
+ *  7. threshold detection V^n < theta <= V^{n+1}, linear interpolation of
+ *     the crossing time, and one queued event per outgoing connection and
+ *     port (delay d, calcium port a further t_c,delay later), delivered at
+ *     step floor(t_e / dt).
+ *
+ * The event queue is a single binary min-heap; there are no epochs.
+ * Functions whose result no test pins against an independent fact are
+ * marked "parity unpinned" below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------ input layout */
+typedef struct {
+    double dt, theta;
+    uint64_t seed;
+    /* STC parameters, Table 5 */
+    double tau_c, tau_h, tau_p, tau_z, gamma_p, gamma_d, theta_p, theta_d;
+    double sigma_pl, p_max, f_int, t_cd, h0, theta_pro, theta_tag, c_pre, c_post;
+
+    int64_t n_cells;
+    const int64_t *cv_off;      /* n_cells + 1 */
+    const int32_t *parent;      /* local index, -1 for the root */
+    const double *length, *diam;
+    const uint8_t *mech;        /* 0 passive, 1 HH */
+    const int32_t *detector;    /* local CV */
+    const double *cell_params;  /* n_cells x 11 */
+
+    int64_t n_syn;
+    const int32_t *syn_cell, *syn_cv;
+    const uint8_t *syn_kind;
+    const double *syn_tau, *syn_erev;
+
+    int64_t n_conn;
+    const int32_t *conn_src, *conn_dst;
+    const uint8_t *conn_ports;
+    const double *conn_w, *conn_d;
+
+    int64_t n_trains;
+    const int32_t *train_dst;
+    const uint8_t *train_ports;
+    const double *train_w;
+    const int64_t *train_off;
+    const double *train_times;
+
+    int64_t n_clamps;
+    const int32_t *clamp_cell, *clamp_cv;
+    const double *clamp_t0, *clamp_dur, *clamp_amp;
+} orc_net;
+
+/* ------------------------------------------------------------ event heap */
+typedef struct {
+    int64_t step;
+    double t;
+    int64_t src, conn;
+    int32_t port;   /* 1 conductance, 2 calcium */
+    int32_t syn;
+    double w;
+} orc_event;
+
+static int ev_less(const orc_event *a, const orc_event *b) {
+    if (a->step != b->step) return a->step < b->step;
+    if (a->t != b->t) return a->t < b->t;
+    if (a->src != b->src) return a->src < b->src;
+    if (a->conn != b->conn) return a->conn < b->conn;
+    return a->port < b->port;
+}
+
+typedef struct {
+    orc_event *v;
+    int64_t n, cap;
+} heap;
+
+static int heap_push(heap *h, orc_event e) {
+    if (h->n == h->cap) {
+        int64_t nc = h->cap ? 2 * h->cap : 1024;
+        orc_event *nv = (orc_event *)realloc(h->v, (size_t)nc * sizeof(orc_event));
+        if (!nv) return -1;
+        h->v = nv;
+        h->cap = nc;
+    }
+    int64_t i = h->n++;
+    h->v[i] = e;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!ev_less(&h->v[i], &h->v[p])) break;
+        orc_event t = h->v[i]; h->v[i] = h->v[p]; h->v[p] = t;
+        i = p;
+    }
+    return 0;
+}
+
+static orc_event heap_pop(heap *h) {
+    orc_event top = h->v[0];
+    h->v[0] = h->v[--h->n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < h->n && ev_less(&h->v[l], &h->v[m])) m = l;
+        if (r < h->n && ev_less(&h->v[r], &h->v[m])) m = r;
+        if (m == i) break;
+        orc_event t = h->v[i]; h->v[i] = h->v[m]; h->v[m] = t;
+        i = m;
+    }
+    return top;
+}
+
+/* ------------------------------------------------------------ Threefry */
+/* Threefry-4x64 with 12 rounds (Salmon et al. 2011): the Threefish-256 round
+ * function (two add/rotate/xor mixes, then the word permutation that swaps
+ * words 1 and 3) with a key injection every four rounds; key-schedule parity
+ * constant and rotation table of Threefish-256.  Parity unpinned against the
+ * original library (no known-answer vectors available); the tests check its
+ * uniformity and independence statistically. */
+static uint64_t rotl64(uint64_t x, int r) { return (x << r) | (x >> (64 - r)); }
+
+void orc_threefry4x64_12(const uint64_t ctr[4], const uint64_t key[4], uint64_t out[4]) {
+    static const int rot[8][2] = {{14, 16}, {52, 57}, {23, 40}, {5, 37},
+                                  {25, 33}, {46, 12}, {58, 22}, {32, 32}};
+    uint64_t ks[5];
+    ks[4] = 0x1BD11BDAA9FC1A22ULL;
+    for (int i = 0; i < 4; i++) { ks[i] = key[i]; ks[4] ^= key[i]; }
+    uint64_t x0 = ctr[0] + ks[0], x1 = ctr[1] + ks[1], x2 = ctr[2] + ks[2], x3 = ctr[3] + ks[3];
+    for (int r = 0; r < 12; r++) {
+        x0 += x1; x1 = rotl64(x1, rot[r % 8][0]); x1 ^= x0;
+        x2 += x3; x3 = rotl64(x3, rot[r % 8][1]); x3 ^= x2;
+        uint64_t t = x1; x1 = x3; x3 = t;
+        if (r % 4 == 3) {
+            uint64_t s = (uint64_t)(r + 1) / 4;
+            x0 += ks[s % 5]; x1 += ks[(s + 1) % 5]; x2 += ks[(s + 2) % 5]; x3 += ks[(s + 3) % 5] + s;
+        }
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+#define ORC_NOISE_TAG 0x5354432d6e6f6973ULL /* domain tag of the early-phase noise */
+
+/* uniform in (0,1): top 53 bits, offset by half an ulp so 0 never occurs */
+static double to_unit(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+/* Standard normal of synapse `sid` at step n: one Threefry call per four
+ * steps (counter n/4), Box-Muller on output pairs (0,1) and (2,3), cosine
+ * branch for even n mod 4, sine for odd. */
+double orc_normal(uint64_t seed, uint64_t sid, uint64_t n) {
+    uint64_t key[4] = {seed, sid, ORC_NOISE_TAG, 0};
+    uint64_t ctr[4] = {n >> 2, 0, 0, 0};
+    uint64_t x[4];
+    orc_threefry4x64_12(ctr, key, x);
+    int lane = (int)(n & 3);
+    int pair = lane >> 1;
+    double ua = to_unit(x[2 * pair]), ub = to_unit(x[2 * pair + 1]);
+    double r = sqrt(-2.0 * log(ua));
+    double ang = 6.283185307179586 * ub;
+    return (lane & 1) ? r * sin(ang) : r * cos(ang);
+}
+
+/* ------------------------------------------------------------ HH rates */
+/* x / (exp(x) - 1), equal to 1 at x = 0 */
+static double exprelr(double x) { return (x == 0.0) ? 1.0 : x / expm1(x); }
+
+/* Hodgkin-Huxley 1952 rates (ms^-1), resting potential shifted to -65 mV */
+void orc_hh_rates(double v, double r[6]) {
+    r[0] = exprelr(-(v + 40.0) / 10.0);              /* alpha_m */
+    r[1] = 4.0 * exp(-(v + 65.0) / 18.0);            /* beta_m  */
+    r[2] = 0.07 * exp(-(v + 65.0) / 20.0);           /* alpha_h */
+    r[3] = 1.0 / (exp(-(v + 35.0) / 10.0) + 1.0);    /* beta_h  */
+    r[4] = 0.1 * exprelr(-(v + 55.0) / 10.0);        /* alpha_n */
+    r[5] = 0.125 * exp(-(v + 65.0) / 80.0);          /* beta_n  */
+}
+
+/* ------------------------------------------------------------ state */
+typedef struct {
+    orc_net net;       /* shallow copy; arrays owned by the caller */
+    int64_t n_cv;
+    int64_t step;
+    char err[256];
+    /* per CV */
+    double *V, *Vold, *I, *G, *D, *b;
+    double *cdt, *gpas, *gpas_e, *axial, *d0, *scale;
+    int64_t *gparent;  /* global parent CV or -1 */
+    int64_t *hh_of;    /* HH gate slot or -1 */
+    int64_t *cv_cell;  /* owning cell of each CV */
+    int64_t n_hh;
+    double *gm, *gh, *gn;
+    /* per synapse */
+    double *g, *c, *h, *z, *decay;
+    int64_t *syn_order; /* synapses sorted by (global CV, id) */
+    int64_t *cv_syn_off; /* n_cv + 1 into syn_order */
+    uint64_t *ev_count, *ev_stepsum; /* per synapse x 2 ports */
+    /* per cell */
+    double *p, *S;
+    uint8_t *post;
+    int64_t *out_off, *out_conn; /* outgoing connections per cell */
+    /* spikes */
+    int64_t n_spikes, cap_spikes;
+    int64_t *sp_gid, *sp_step;
+    double *sp_t;
+    heap q;
+    double r_c;
+} orc;
+
+static void *xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
+
+static int cmp_i64_pair(const void *a, const void *b) {
+    const int64_t *x = (const int64_t *)a, *y = (const int64_t *)b;
+    if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+    if (x[1] != y[1]) return x[1] < y[1] ? -1 : 1;
+    return 0;
+}
+
+void orc_destroy(orc *o);
+
+/* Builds the oracle state from a network description; returns NULL and
+ * writes a message into err on invalid input. */
+orc *orc_create(const orc_net *net, char *err, int errlen) {
+    orc *o = (orc *)calloc(1, sizeof(orc));
+    if (!o) return NULL;
+    o->net = *net;
+    const orc_net *N = &o->net;
+#define FAIL(...) do { snprintf(err, (size_t)errlen, __VA_ARGS__); orc_destroy(o); return NULL; } while (0)
+    if (!(N->dt > 0)) FAIL("dt must be positive");
+    int64_t nc = N->n_cells;
+    o->n_cv = N->cv_off[nc];
+    int64_t ncv = o->n_cv;
+    o->V = xcalloc(ncv, 8); o->Vold = xcalloc(ncv, 8); o->I = xcalloc(ncv, 8);
+    o->G = xcalloc(ncv, 8); o->D = xcalloc(ncv, 8); o->b = xcalloc(ncv, 8);
+    o->cdt = xcalloc(ncv, 8); o->gpas = xcalloc(ncv, 8); o->gpas_e = xcalloc(ncv, 8);
+    o->axial = xcalloc(ncv, 8); o->d0 = xcalloc(ncv, 8); o->scale = xcalloc(ncv, 8);
+    o->gparent = xcalloc(ncv, 8); o->hh_of = xcalloc(ncv, 8); o->cv_cell = xcalloc(ncv, 8);
+    const double pi = 3.14159265358979323846;
+    int64_t nhh = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        const double *P = N->cell_params + 11 * c;
+        int64_t b0 = N->cv_off[c], b1 = N->cv_off[c + 1];
+        if (b1 <= b0) FAIL("cell %lld has no CV", (long long)c);
+        if (N->detector[c] < 0 || N->detector[c] >= b1 - b0) FAIL("bad detector CV");
+        for (int64_t i = b0; i < b1; i++) {
+            int32_t pl = N->parent[i];
+            if (i == b0 ? pl != -1 : (pl < 0 || pl >= i - b0)) FAIL("cell %lld: parent must satisfy parent[0]=-1, 0<=parent[i]<i", (long long)c);
+            if (!(N->length[i] > 0) || !(N->diam[i] > 0)) FAIL("non-positive CV geometry");
+            o->gparent[i] = (i == b0) ? -1 : b0 + pl;
+            o->cv_cell[i] = c;
+            /* finite-volume CV: a cylinder, lateral area only */
+            double area = pi * N->diam[i] * N->length[i];          /* um^2 */
+            o->cdt[i] = (1e-5 * P[0] * area) / N->dt;              /* C/dt, nF/ms = uS */
+            if (N->mech[i] == 1) {
+                o->hh_of[i] = nhh++;
+                o->scale[i] = 1e-2 * area;                          /* S/cm^2 -> uS */
+                o->gpas[i] = 0.0;
+                o->gpas_e[i] = 0.0;
+            } else {
+                o->hh_of[i] = -1;
+                o->scale[i] = 0.0;
+                o->gpas[i] = 1e-2 * P[3] * area;
+                o->gpas_e[i] = o->gpas[i] * P[4];
+            }
+            o->V[i] = P[2];
+        }
+        for (int64_t i = b0 + 1; i < b1; i++) {
+            int64_t k = o->gparent[i];
+            double ri = 0.5 * N->diam[i], rk = 0.5 * N->diam[k];
+            /* series resistance of the two half-cylinders between the nodes */
+            double rsum = N->length[i] / (2.0 * pi * ri * ri) + N->length[k] / (2.0 * pi * rk * rk);
+            o->axial[i] = 1e2 / (P[1] * rsum);                     /* uS */
+        }
+    }
+    /* diagonal invariant: C/dt + g_pas + (own axial + children's axial) */
+    double *axsum = xcalloc(ncv, 8);
+    for (int64_t i = 0; i < ncv; i++) axsum[i] = o->axial[i];
+    for (int64_t i = 0; i < ncv; i++) if (o->gparent[i] >= 0) axsum[o->gparent[i]] += o->axial[i];
+    for (int64_t i = 0; i < ncv; i++) o->d0[i] = (o->cdt[i] + o->gpas[i]) + axsum[i];
+    free(axsum);
+    o->n_hh = nhh;
+    o->gm = xcalloc(nhh, 8); o->gh = xcalloc(nhh, 8); o->gn = xcalloc(nhh, 8);
+    for (int64_t i = 0; i < ncv; i++) {
+        if (o->hh_of[i] < 0) continue;
+        double r[6];
+        orc_hh_rates(o->V[i], r);
+        int64_t k = o->hh_of[i];
+        o->gm[k] = r[0] / (r[0] + r[1]);
+        o->gh[k] = r[2] / (r[2] + r[3]);
+        o->gn[k] = r[4] / (r[4] + r[5]);
+    }
+    /* synapses */
+    int64_t ns = N->n_syn;
+    o->g = xcalloc(ns, 8); o->c = xcalloc(ns, 8); o->h = xcalloc(ns, 8); o->z = xcalloc(ns, 8);
+    o->decay = xcalloc(ns, 8);
+    o->ev_count = xcalloc(2 * ns, 8); o->ev_stepsum = xcalloc(2 * ns, 8);
+    int64_t *pairs = xcalloc(2 * ns, 8);
+    for (int64_t s = 0; s < ns; s++) {
+        int32_t cell = N->syn_cell[s];
+        if (cell < 0 || cell >= nc) FAIL("synapse %lld: bad cell", (long long)s);
+        if (N->syn_cv[s] < 0 || N->syn_cv[s] >= N->cv_off[cell + 1] - N->cv_off[cell]) FAIL("synapse %lld: bad CV", (long long)s);
+        if (!(N->syn_tau[s] > 0)) FAIL("synapse %lld: tau must be positive", (long long)s);
+        if (N->syn_kind[s] > 1) FAIL("synapse %lld: bad kind", (long long)s);
+        o->decay[s] = exp(-N->dt / N->syn_tau[s]);
+        o->h[s] = (N->syn_kind[s] == 1) ? N->h0 : 0.0;
+        pairs[2 * s] = N->cv_off[cell] + N->syn_cv[s];
+        pairs[2 * s + 1] = s;
+    }
+    qsort(pairs, (size_t)ns, 16, cmp_i64_pair);
+    o->syn_order = xcalloc(ns, 8);
+    o->cv_syn_off = xcalloc(ncv + 1, 8);
+    for (int64_t k = 0; k < ns; k++) { o->syn_order[k] = pairs[2 * k + 1]; o->cv_syn_off[pairs[2 * k] + 1]++; }
+    for (int64_t i = 0; i < ncv; i++) o->cv_syn_off[i + 1] += o->cv_syn_off[i];
+    free(pairs);
+    /* cells */
+    o->p = xcalloc(nc, 8); o->S = xcalloc(nc, 8); o->post = xcalloc(nc, 1);
+    o->out_off = xcalloc(nc + 1, 8); o->out_conn = xcalloc(N->n_conn, 8);
+    for (int64_t k = 0; k < N->n_conn; k++) {
+        if (N->conn_src[k] < 0 || N->conn_src[k] >= nc) FAIL("connection %lld: bad source", (long long)k);
+        if (N->conn_dst[k] < 0 || N->conn_dst[k] >= ns) FAIL("connection %lld: bad target", (long long)k);
+        if ((N->conn_ports[k] & 2) && N->syn_kind[N->conn_dst[k]] != 1) FAIL("calcium port needs a plasticity synapse");
+        if (N->conn_ports[k] == 0 || N->conn_ports[k] > 3) FAIL("bad ports");
+        if (!(N->conn_d[k] >= N->dt)) FAIL("connection %lld: delay below dt", (long long)k);
+        o->out_off[N->conn_src[k] + 1]++;
+    }
+    for (int64_t c = 0; c < nc; c++) o->out_off[c + 1] += o->out_off[c];
+    int64_t *fill = xcalloc(nc, 8);
+    for (int64_t k = 0; k < N->n_conn; k++) {
+        int64_t sc = N->conn_src[k];
+        o->out_conn[o->out_off[sc] + fill[sc]++] = k;
+    }
+    free(fill);
+    o->r_c = exp(-N->dt / N->tau_c);
+    /* explicit presynaptic trains enter the queue up front */
+    for (int64_t tr = 0; tr < N->n_trains; tr++) {
+        int32_t s = N->train_dst[tr];
+        if (s < 0 || s >= ns) FAIL("train %lld: bad target", (long long)tr);
+        if ((N->train_ports[tr] & 2) && N->syn_kind[s] != 1) FAIL("calcium port needs a plasticity synapse");
+        for (int64_t j = N->train_off[tr]; j < N->train_off[tr + 1]; j++) {
+            double t = N->train_times[j];
+            if (!(t >= 0)) FAIL("negative train time");
+            orc_event e = {0};
+            e.src = nc + tr; e.conn = 0; e.syn = s; e.w = N->train_w[tr];
+            if (N->train_ports[tr] & 1) {
+                e.t = t; e.step = (int64_t)floor(e.t / N->dt); e.port = 1;
+                if (heap_push(&o->q, e)) FAIL("out of memory");
+            }
+            if (N->train_ports[tr] & 2) {
+                e.t = t + N->t_cd; e.step = (int64_t)floor(e.t / N->dt); e.port = 2;
+                if (heap_push(&o->q, e)) FAIL("out of memory");
+            }
+        }
+    }
+    for (int64_t k = 0; k < N->n_clamps; k++) {
+        int32_t cell = N->clamp_cell[k];
+        if (cell < 0 || cell >= nc || N->clamp_cv[k] < 0 || N->clamp_cv[k] >= N->cv_off[cell + 1] - N->cv_off[cell]) FAIL("bad clamp");
+    }
+#undef FAIL
+    return o;
+}
+
+static int record_spike(orc *o, int64_t gid, int64_t step, double t) {
+    if (o->n_spikes == o->cap_spikes) {
+        int64_t nc = o->cap_spikes ? 2 * o->cap_spikes : 1024;
+        int64_t *a = realloc(o->sp_gid, (size_t)nc * 8), *b;
+        if (!a) return -1;
+        o->sp_gid = a;
+        b = realloc(o->sp_step, (size_t)nc * 8);
+        if (!b) return -1;
+        o->sp_step = b;
+        double *t2 = realloc(o->sp_t, (size_t)nc * 8);
+        if (!t2) return -1;
+        o->sp_t = t2;
+        o->cap_spikes = nc;
+    }
+    o->sp_gid[o->n_spikes] = gid; o->sp_step[o->n_spikes] = step; o->sp_t[o->n_spikes] = t;
+    o->n_spikes++;
+    return 0;
+}
+
+/* Membrane current I (nA, outward positive) and its voltage derivative G
+ * (uS) per CV at the present voltage: HH first, then synapses in (CV, id)
+ * order, then the clamps active at time tn. */
+static void currents(orc *o, double tn) {
+    const orc_net *N = &o->net;
+    for (int64_t i = 0; i < o->n_cv; i++) {
+        double I = 0.0, G = 0.0, v = o->V[i];
+        if (o->hh_of[i] >= 0) {
+            int64_t k = o->hh_of[i];
+            const double *P = N->cell_params + 11 * o->cv_cell[i];
+            double gna = P[5] * o->gm[k] * o->gm[k] * o->gm[k] * o->gh[k];
+            double gk = P[6] * o->gn[k] * o->gn[k] * o->gn[k] * o->gn[k];
+            double idens = gna * (v - P[8]) + gk * (v - P[9]) + P[7] * (v - P[10]);
+            I = o->scale[i] * idens;
+            G = o->scale[i] * (gna + gk + P[7]);
+        }
+        for (int64_t q = o->cv_syn_off[i]; q < o->cv_syn_off[i + 1]; q++) {
+            int64_t s = o->syn_order[q];
+            I += o->g[s] * (v - N->syn_erev[s]);
+            G += o->g[s];
+        }
+        o->I[i] = I;
+        o->G[i] = G;
+    }
+    for (int64_t k = 0; k < N->n_clamps; k++) {
+        if (N->clamp_t0[k] <= tn && tn < N->clamp_t0[k] + N->clamp_dur[k])
+            o->I[N->cv_off[N->clamp_cell[k]] + N->clamp_cv[k]] -= N->clamp_amp[k];
+    }
+}
+
+/* One step n -> n+1.  Returns 0, or -1 with a message. */
+static int orc_step(orc *o) {
+    const orc_net *N = &o->net;
+    const int64_t n = o->step, nc = N->n_cells, ncv = o->n_cv;
+    const double dt = N->dt, tn = (double)n * dt, h0 = N->h0;
+
+    /* 1. event delivery, then the post-synaptic hook */
+    while (o->q.n > 0 && o->q.v[0].step <= n) {
+        orc_event e = heap_pop(&o->q);
+        if (e.step < n) { snprintf(o->err, sizeof o->err, "event for step %lld found at step %lld", (long long)e.step, (long long)n); return -1; }
+        int32_t s = e.syn;
+        if (e.port == 1) {
+            if (N->syn_kind[s] == 1) o->g[s] += e.w * ((o->h[s] + h0 * o->z[s]) / h0);
+            else o->g[s] += e.w;
+        } else {
+            o->c[s] += N->c_pre;
+        }
+        o->ev_count[2 * s + e.port - 1] += 1;
+        o->ev_stepsum[2 * s + e.port - 1] += (uint64_t)n;
+    }
+    for (int64_t s = 0; s < N->n_syn; s++)
+        if (N->syn_kind[s] == 1 && o->post[N->syn_cell[s]]) o->c[s] += N->c_post;
+    memset(o->post, 0, (size_t)nc);
+
+    /* 2. currents and conductances at V^n */
+    currents(o, tn);
+
+    /* 3. assembly and 4. Hines solve, cell by cell */
+    for (int64_t i = 0; i < ncv; i++) o->Vold[i] = o->V[i];
+    for (int64_t cell = 0; cell < nc; cell++) {
+        int64_t b0 = N->cv_off[cell], b1 = N->cv_off[cell + 1];
+        for (int64_t i = b0; i < b1; i++) {
+            double v = o->V[i];
+            o->D[i] = o->d0[i] + o->G[i];
+            o->b[i] = ((o->cdt[i] * v + o->gpas_e[i]) - o->I[i]) + o->G[i] * v;
+        }
+        for (int64_t i = b1 - 1; i > b0; i--) {
+            int64_t p = o->gparent[i];
+            double u = -o->axial[i];
+            double f = u / o->D[i];
+            o->D[p] -= f * u;
+            o->b[p] -= f * o->b[i];
+        }
+        o->V[b0] = o->b[b0] / o->D[b0];
+        for (int64_t i = b0 + 1; i < b1; i++) {
+            double u = -o->axial[i];
+            o->V[i] = (o->b[i] - u * o->V[o->gparent[i]]) / o->D[i];
+        }
+    }
+
+    /* 5. gates at V^{n+1}; synaptic conductance decay */
+    for (int64_t i = 0; i < ncv; i++) {
+        if (o->hh_of[i] < 0) continue;
+        int64_t k = o->hh_of[i];
+        double r[6];
+        orc_hh_rates(o->V[i], r);
+        double *x[3] = {&o->gm[k], &o->gh[k], &o->gn[k]};
+        for (int j = 0; j < 3; j++) {
+            double a = r[2 * j], bb = r[2 * j + 1];
+            double xinf = a / (a + bb);
+            *x[j] = xinf + (*x[j] - xinf) * exp(-dt * (a + bb));
+        }
+    }
+    for (int64_t s = 0; s < N->n_syn; s++) o->g[s] *= o->decay[s];
+
+    /* 6. plasticity: S from step-start h; h, z from step-start h, z, p, c */
+    for (int64_t cell = 0; cell < nc; cell++) {
+        double S = 0.0;
+        for (int64_t i = N->cv_off[cell]; i < N->cv_off[cell + 1]; i++)
+            for (int64_t q = o->cv_syn_off[i]; q < o->cv_syn_off[i + 1]; q++) {
+                int64_t s = o->syn_order[q];
+                if (N->syn_kind[s] == 1) S += fabs(o->h[s] - h0);
+            }
+        o->S[cell] = S;
+    }
+    const double ah = dt / N->tau_h, az = dt / N->tau_z;
+    for (int64_t s = 0; s < N->n_syn; s++) {
+        if (N->syn_kind[s] != 1) continue;
+        double c = o->c[s], h = o->h[s], z = o->z[s], p = o->p[N->syn_cell[s]];
+        double thp = (c - N->theta_p > 0.0) ? 1.0 : 0.0;
+        double thd = (c - N->theta_d > 0.0) ? 1.0 : 0.0;
+        double drift = 0.1 * (h0 - h) + N->gamma_p * (10.0 - h) * thp - N->gamma_d * h * thd;
+        double hn = h + ah * drift;
+        if (thp + thd > 0.0)
+            hn += N->sigma_pl * sqrt((thp + thd) * ah) * orc_normal(N->seed, (uint64_t)s, (uint64_t)n);
+        double tagp = ((h - h0) - N->theta_tag > 0.0) ? 1.0 : 0.0;
+        double tagd = ((h0 - h) - N->theta_tag > 0.0) ? 1.0 : 0.0;
+        double zn = z + az * p * N->f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
+        o->h[s] = hn;
+        o->z[s] = zn;
+        o->c[s] = c * o->r_c;
+    }
+    const double ap = dt / N->tau_p;
+    for (int64_t cell = 0; cell < nc; cell++) {
+        double trig = (o->S[cell] - N->theta_pro > 0.0) ? 1.0 : 0.0;
+        o->p[cell] = o->p[cell] + ap * (-o->p[cell] + N->p_max * trig);
+    }
+
+    /* 7. threshold detection and event generation */
+    for (int64_t cell = 0; cell < nc; cell++) {
+        int64_t d = N->cv_off[cell] + N->detector[cell];
+        double v0 = o->Vold[d], v1 = o->V[d];
+        if (!(v0 < N->theta && v1 >= N->theta)) continue;
+        double ts = tn + dt * ((N->theta - v0) / (v1 - v0));
+        if (record_spike(o, cell, n, ts)) { snprintf(o->err, sizeof o->err, "out of memory"); return -1; }
+        o->post[cell] = 1;
+        for (int64_t q = o->out_off[cell]; q < o->out_off[cell + 1]; q++) {
+            int64_t k = o->out_conn[q];
+            orc_event e = {0};
+            e.src = cell; e.conn = k; e.syn = N->conn_dst[k]; e.w = N->conn_w[k];
+            double te = ts + N->conn_d[k];
+            if (N->conn_ports[k] & 1) {
+                e.t = te; e.step = (int64_t)floor(te / dt); e.port = 1;
+                if (e.step <= n) { snprintf(o->err, sizeof o->err, "event scheduled in the past"); return -1; }
+                if (heap_push(&o->q, e)) { snprintf(o->err, sizeof o->err, "out of memory"); return -1; }
+            }
+            if (N->conn_ports[k] & 2) {
+                e.t = te + N->t_cd; e.step = (int64_t)floor(e.t / dt); e.port = 2;
+                if (e.step <= n) { snprintf(o->err, sizeof o->err, "event scheduled in the past"); return -1; }
+                if (heap_push(&o->q, e)) { snprintf(o->err, sizeof o->err, "out of memory"); return -1; }
+            }
+        }
+    }
+    for (int64_t i = 0; i < ncv; i++) {
+        if (!isfinite(o->V[i])) { snprintf(o->err, sizeof o->err, "non-finite voltage at CV %lld, step %lld", (long long)i, (long long)n); return -1; }
+    }
+    o->step = n + 1;
+    return 0;
+}
+
+int orc_run(orc *o, int64_t n_steps) {
+    for (int64_t k = 0; k < n_steps; k++)
+        if (orc_step(o)) return -1;
+    return 0;
+}
+
+const char *orc_error(const orc *o) { return o->err; }
+int64_t orc_step_count(const orc *o) { return o->step; }
+int64_t orc_n_cv(const orc *o) { return o->n_cv; }
+int64_t orc_n_hh(const orc *o) { return o->n_hh; }
+int64_t orc_spike_count(const orc *o) { return o->n_spikes; }
+
+void orc_spikes(const orc *o, int64_t *gid, int64_t *step, double *t) {
+    for (int64_t k = 0; k < o->n_spikes; k++) { gid[k] = o->sp_gid[k]; step[k] = o->sp_step[k]; t[k] = o->sp_t[k]; }
+}
+
+/* what: 0 V, 1 m, 2 h(HH), 3 n, 4 g, 5 c, 6 h(weight), 7 z, 8 p,
+ *       9 delivered-event counts (2 per synapse), 10 step sums (2 per synapse) */
+int orc_read(const orc *o, int what, void *out) {
+    const orc_net *N = &o->net;
+    size_t nh = (size_t)o->n_hh, ns = (size_t)N->n_syn;
+    switch (what) {
+    case 0: memcpy(out, o->V, (size_t)o->n_cv * 8); return 0;
+    case 1: memcpy(out, o->gm, nh * 8); return 0;
+    case 2: memcpy(out, o->gh, nh * 8); return 0;
+    case 3: memcpy(out, o->gn, nh * 8); return 0;
+    case 4: memcpy(out, o->g, ns * 8); return 0;
+    case 5: memcpy(out, o->c, ns * 8); return 0;
+    case 6: memcpy(out, o->h, ns * 8); return 0;
+    case 7: memcpy(out, o->z, ns * 8); return 0;
+    case 8: memcpy(out, o->p, (size_t)N->n_cells * 8); return 0;
+    case 9: memcpy(out, o->ev_count, 2 * ns * 8); return 0;
+    case 10: memcpy(out, o->ev_stepsum, 2 * ns * 8); return 0;
+    default: return -1;
+    }
+}
+
+/* Test hooks: overwrite a state array (same codes as orc_read, 0-8). */
+int orc_write(orc *o, int what, const double *in) {
+    const orc_net *N = &o->net;
+    size_t nh = (size_t)o->n_hh, ns = (size_t)N->n_syn;
+    switch (what) {
+    case 0: memcpy(o->V, in, (size_t)o->n_cv * 8); return 0;
+    case 1: memcpy(o->gm, in, nh * 8); return 0;
+    case 2: memcpy(o->gh, in, nh * 8); return 0;
+    case 3: memcpy(o->gn, in, nh * 8); return 0;
+    case 4: memcpy(o->g, in, ns * 8); return 0;
+    case 5: memcpy(o->c, in, ns * 8); return 0;
+    case 6: memcpy(o->h, in, ns * 8); return 0;
+    case 7: memcpy(o->z, in, ns * 8); return 0;
+    case 8: memcpy(o->p, in, (size_t)N->n_cells * 8); return 0;
+    default: return -1;
+    }
+}
+
+/* The assembled system of the current state, for the dense-solve check:
+ * diagonal, off-diagonal (to parent) and right-hand side after the step's
+ * currents are computed, without advancing time.  Fills D, U, b (n_cv). */
+int orc_assemble(orc *o, double *Dout, double *Uout, double *bout) {
+    currents(o, (double)o->step * o->net.dt);
+    for (int64_t i = 0; i < o->n_cv; i++) {
+        double v = o->V[i];
+        Dout[i] = o->d0[i] + o->G[i];
+        bout[i] = ((o->cdt[i] * v + o->gpas_e[i]) - o->I[i]) + o->G[i] * v;
+        Uout[i] = -o->axial[i];
+    }
+    return 0;
+}
+
+/* Stand-alone Hines solve of a given tree system (parent[i] < i, parent[0]
+ * = -1): the same elimination as the step, exposed for the dense LU check.
+ * D and b are overwritten; the solution goes to x. */
+void orc_hines(int64_t n, const int64_t *parent, const double *U, double *D, double *b, double *x) {
+    for (int64_t i = n - 1; i > 0; i--) {
+        int64_t p = parent[i];
+        double f = U[i] / D[i];
+        D[p] -= f * U[i];
+        b[p] -= f * b[i];
+    }
+    x[0] = b[0] / D[0];
+    for (int64_t i = 1; i < n; i++) x[i] = (b[i] - U[i] * x[parent[i]]) / D[i];
+}
+
+void orc_destroy(orc *o) {
+    if (!o) return;
+    void *ptrs[] = {o->V, o->Vold, o->I, o->G, o->D, o->b, o->cdt, o->gpas, o->gpas_e, o->axial,
+                    o->d0, o->scale, o->gparent, o->hh_of, o->cv_cell, o->gm, o->gh, o->gn, o->g, o->c, o->h,
+                    o->z, o->decay, o->syn_order, o->cv_syn_off, o->ev_count, o->ev_stepsum, o->p,
+                    o->S, o->post, o->out_off, o->out_conn, o->sp_gid, o->sp_step, o->sp_t, o->q.v};
+    for (size_t k = 0; k < sizeof ptrs / sizeof ptrs[0]; k++) free(ptrs[k]);
+    free(o);
+}
