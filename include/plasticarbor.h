@@ -1,0 +1,265 @@
+/*
+ * plasticarbor.h -- C ABI of the MI355X (gfx950) engine that advances
+ * plastic networks of multi-compartment neurons step by step, after
+ * "Plastic Arbor" (Luboeinski et al., arXiv 2411.16445).
+ *
+ * One implicit-Euler step (fixed dt) of the whole network:
+ *   1. deliver queued spike events to synapses (conductance port and the
+ *      delayed calcium port of the calcium-based rule, Eq. 19; two ports
+ *      per connection are what the round_robin_halt selection policy of
+ *      Sec. 2.2 exists for), then the post-synaptic spike hook (Sec. 2.1);
+ *   2. membrane currents at V^n (ohmic current sum, Sec. 2.4: Hodgkin-Huxley
+ *      soma, passive leak, conductance-based exponential synapses, clamps);
+ *   3. assembly of the cable equation (Eq. 4), linearised backward Euler
+ *      (the "implicit solving methods" of the discussion);
+ *   4. Hines solve of every cell's tree system;
+ *   5. HH gate and synaptic conductance updates at V^{n+1};
+ *   6. calcium-based early phase h (Eqs. 17-18, Euler-Maruyama of Sec. 2.3
+ *      with Threefry-4x64-12 + Box-Muller noise), late phase z (Eq. 20),
+ *      per-cell protein p (Eq. 21) with total weight w = h + h0 z (Eq. 16);
+ *   7. threshold detection and delayed event generation.
+ *
+ * Units everywhere: ms, mV, um, nA, uS (conductance), nF, umol/l.
+ *
+ * Conventions
+ *   - Every call returns a pa_status; no C++ exception crosses the ABI.
+ *     On failure pa_last_error(sim) holds a message.
+ *   - Input arrays are read during the call and copied; the caller keeps
+ *     ownership.  Output arrays are caller-owned host buffers.
+ *   - The library owns all device memory; it allocates it at pa_finalize
+ *     through the allocator set with pa_set_allocator (default hipMalloc).
+ *   - State machine: BUILD --pa_finalize--> READY.  Adding cells, synapses,
+ *     connections, trains, clamps or probes after pa_finalize returns
+ *     PA_ESTATE; advancing before it returns PA_ESTATE.
+ *   - One host thread per simulation; different simulations are
+ *     independent.  All device work of a simulation is ordered on its
+ *     stream (pa_set_stream), and every call that returns data has
+ *     synchronised that stream.
+ */
+#ifndef PLASTICARBOR_H
+#define PLASTICARBOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pa_sim pa_sim;
+typedef int32_t pa_status;
+
+#define PA_OK 0
+#define PA_EINVAL (-1)     /* invalid argument or network description */
+#define PA_ESTATE (-2)     /* call not allowed in the current state */
+#define PA_ENOMEM (-3)     /* allocation failed */
+#define PA_EDEVICE (-4)    /* HIP runtime error */
+#define PA_ERANGE (-5)     /* time off the dt grid, backwards, or an event in the past */
+#define PA_EOVERFLOW (-6)  /* an event slot overflowed: raise slot_capacity */
+#define PA_ENUMERIC (-7)   /* a membrane voltage became non-finite */
+
+/* precision of the run */
+#define PA_FP64 0   /* every state and arithmetic in FP64 */
+#define PA_MIXED 1  /* HH gates, synaptic conductance and calcium in FP32;
+                       cable solve, h, z, p in FP64 */
+/* execution form */
+#define PA_PLAIN 0    /* one kernel per stage per step */
+#define PA_BATCHED 1  /* one fused kernel per epoch of steps */
+
+#define PA_PORT_G 1   /* conductance port: g += w (h + h0 z)/h0, or w */
+#define PA_PORT_CA 2  /* calcium port: c += c_pre after t_c,delay */
+
+#define PA_MECH_PAS 0 /* passive leak (g_pas, e_pas) */
+#define PA_MECH_HH 1  /* Hodgkin-Huxley Na, K, leak */
+
+#define PA_SYN_EXP 0  /* conductance-based exponential synapse */
+#define PA_SYN_STC 1  /* exponential synapse with calcium-based early phase and
+                         tagging-and-capture late phase (Sec. 3.5) */
+
+typedef struct {
+    double dt_ms;            /* time step, > 0 */
+    double threshold_mV;     /* spike detector threshold */
+    uint64_t seed;           /* key of the early-phase noise */
+    int32_t precision;       /* PA_FP64 or PA_MIXED */
+    int32_t mode;            /* PA_PLAIN or PA_BATCHED */
+    uint32_t probe_stride;   /* steps between probe samples, >= 1 */
+    uint32_t slot_capacity;  /* events per (cell, step) slot; 0 = automatic */
+    uint32_t cells_per_block;/* batched form: cells per workgroup; 0 = autotune */
+    uint32_t reserved;
+} pa_config;
+
+/* Table 5 of the paper (h0 = 10 mV * 0.5 gamma_p/(gamma_p + gamma_d),
+ * theta_pro = 0.5 h0, theta_tag = 0.2 h0 are given explicitly). */
+typedef struct {
+    double tau_c, tau_h, tau_p, tau_z;   /* ms */
+    double gamma_p, gamma_d;             /* potentiation / depression rates */
+    double theta_p, theta_d;             /* calcium thresholds */
+    double sigma_pl;                     /* mV */
+    double p_max, f_int;                 /* umol/l, l/umol */
+    double t_cd;                         /* calcium delay t_c,delay, ms */
+    double h0, theta_pro, theta_tag;     /* mV */
+    double c_pre, c_post;                /* calcium jumps */
+} pa_stc_params;
+
+/* Membrane and channel constants of one cell. */
+typedef struct {
+    double cm;        /* uF/cm^2 */
+    double ra;        /* axial resistivity, ohm cm */
+    double v_init;    /* mV */
+    double g_pas;     /* S/cm^2, passive CVs */
+    double e_pas;     /* mV */
+    double gna, gk, gl;  /* S/cm^2, HH CVs */
+    double ena, ek, el;  /* mV */
+} pa_cell_params;
+
+typedef struct {
+    uint64_t n_cells, n_cv, n_syn, n_stc, n_conn, n_trains, n_probes;
+    uint64_t steps, spikes, events;
+    uint32_t epoch_steps;    /* K: steps between spike exchanges */
+    uint32_t ring_slots;     /* R: per-cell event slots */
+    uint32_t slot_capacity;  /* Q */
+    uint32_t cells_per_block;
+    double advance_ms;       /* wall time inside pa_advance* so far */
+    uint64_t device_bytes;   /* device memory held */
+} pa_stats;
+
+/* Creates a simulation in the BUILD state.  cfg and stc are copied.
+ * Errors: PA_EINVAL (NULL pointer, dt <= 0, unknown precision/mode,
+ * probe_stride 0, non-finite or non-positive time constants). */
+pa_status pa_sim_create(const pa_config *cfg, const pa_stc_params *stc, pa_sim **out);
+
+/* Releases everything; NULL-safe. */
+void pa_sim_destroy(pa_sim *sim);
+
+/* Orders all device work of the simulation on `hip_stream` (a hipStream_t,
+ * e.g. a torch stream's handle).  NULL selects a stream the library
+ * creates.  Allowed before pa_finalize only. */
+pa_status pa_set_stream(pa_sim *sim, void *hip_stream);
+
+/* Device memory hooks (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` bytes aligned to 256 bytes, or
+ * NULL; release frees it.  Allowed before pa_finalize only. */
+pa_status pa_set_allocator(pa_sim *sim, void *(*alloc)(size_t bytes, void *ctx),
+                           void (*release)(void *ptr, void *ctx), void *ctx);
+
+/* Adds n cells; cell k owns CVs cv_off[k] .. cv_off[k+1]-1 of the arrays
+ * (cv_off[0] = 0).  parent holds local CV indices: parent[first] = -1 and
+ * 0 <= parent[i] < i (the ordering the Hines elimination relies on).
+ * Each CV is a cylinder of the given length and diameter (um) carrying
+ * PA_MECH_PAS or PA_MECH_HH.  detector_cv is the local CV of the cell's
+ * threshold detector.  params has n entries.  Cell ids (gids) are dense,
+ * in call order; the first is written to *first_gid.  Errors: PA_EINVAL. */
+pa_status pa_cells_add(pa_sim *sim, uint32_t n, const int64_t *cv_off, const int32_t *parent,
+                       const double *length_um, const double *diam_um, const uint8_t *mech,
+                       const int32_t *detector_cv, const pa_cell_params *params,
+                       uint32_t *first_gid);
+
+/* Adds n synapses: synapse k sits on local CV cv[k] of cell gid[k], kind
+ * PA_SYN_EXP or PA_SYN_STC, decay time constant tau_ms[k] > 0, reversal
+ * erev_mV[k].  Synapse ids are dense in call order.  Errors: PA_EINVAL. */
+pa_status pa_synapses_add(pa_sim *sim, uint32_t n, const uint32_t *gid, const uint32_t *cv,
+                          const uint8_t *kind, const double *tau_ms, const double *erev_mV,
+                          uint32_t *first_sid);
+
+/* Adds n connections: a spike of cell src_gid[k] at t* reaches synapse
+ * dst_sid[k] through the ports in ports[k] (PA_PORT_G and/or PA_PORT_CA;
+ * the calcium port needs a PA_SYN_STC target) at t* + delay_ms[k] (plus
+ * t_cd for the calcium port), with weight weight_uS[k] on the conductance
+ * port.  delay_ms >= dt.  Connection ids are dense in call order and break
+ * ties between simultaneous events.  Errors: PA_EINVAL. */
+pa_status pa_connect(pa_sim *sim, uint64_t n, const uint32_t *src_gid, const uint32_t *dst_sid,
+                     const uint8_t *ports, const double *weight_uS, const double *delay_ms);
+
+/* Adds n explicit presynaptic spike trains: train k delivers arrivals at
+ * times_ms[time_off[k] .. time_off[k+1]-1] (non-decreasing, >= 0) to
+ * synapse dst_sid[k] through ports[k] with weight weight_uS[k]; the
+ * calcium port adds t_cd.  Trains act as sources with ids n_cells + k.
+ * Errors: PA_EINVAL. */
+pa_status pa_trains_add(pa_sim *sim, uint32_t n, const uint32_t *dst_sid, const uint8_t *ports,
+                        const double *weight_uS, const int64_t *time_off, const double *times_ms);
+
+/* Adds n current clamps injecting amp_nA[k] into local CV cv[k] of cell
+ * gid[k] during t0 <= t_n < t0 + dur.  Errors: PA_EINVAL. */
+pa_status pa_clamps_add(pa_sim *sim, uint32_t n, const uint32_t *gid, const uint32_t *cv,
+                        const double *t0_ms, const double *dur_ms, const double *amp_nA);
+
+#define PA_PROBE_V 0   /* index: global CV (cv_off of the cell + local CV) */
+#define PA_PROBE_G 1   /* index: synapse id */
+#define PA_PROBE_CA 2  /* index: synapse id (PA_SYN_STC) */
+#define PA_PROBE_H 3   /* index: synapse id (PA_SYN_STC) */
+#define PA_PROBE_Z 4   /* index: synapse id (PA_SYN_STC) */
+#define PA_PROBE_P 5   /* index: cell id */
+
+/* Adds n probes, sampled after every probe_stride-th completed step.
+ * Errors: PA_EINVAL. */
+pa_status pa_probes_add(pa_sim *sim, uint32_t n, const int32_t *what, const uint64_t *index,
+                        uint32_t *first_probe);
+
+/* Validates, orders synapses by (cell, CV, id), builds the cable
+ * invariants, the connection table by source and the event rings,
+ * allocates and uploads device memory, and initialises the state
+ * (V = v_init, gates at steady state, g = c = z = p = 0, h = h0).
+ * Errors: PA_EINVAL, PA_ESTATE, PA_ENOMEM, PA_EDEVICE. */
+pa_status pa_finalize(pa_sim *sim);
+
+/* Advances to t_until_ms, which must lie on the dt grid (within 1e-9
+ * relative) and not before the present time.  Errors: PA_ESTATE,
+ * PA_ERANGE, PA_EOVERFLOW, PA_ENUMERIC, PA_EDEVICE; after any of the last
+ * three the simulation refuses further advances. */
+pa_status pa_advance(pa_sim *sim, double t_until_ms);
+
+/* Advances by n_steps steps.  Errors as pa_advance. */
+pa_status pa_advance_steps(pa_sim *sim, uint64_t n_steps);
+
+/* Number of spikes recorded so far. */
+pa_status pa_spikes_count(const pa_sim *sim, uint64_t *n);
+
+/* Copies up to cap spikes (gid, step of the crossing, interpolated time)
+ * in (step, gid) order; *n receives the number copied. */
+pa_status pa_spikes_read(const pa_sim *sim, uint32_t *gid, uint64_t *step, double *t_ms,
+                         uint64_t cap, uint64_t *n);
+
+/* Number of probe samples (rows) recorded so far. */
+pa_status pa_probe_count(const pa_sim *sim, uint64_t *n_samples);
+
+/* Copies up to cap doubles of the samples, row-major (sample, probe). */
+pa_status pa_probe_read(const pa_sim *sim, double *out, uint64_t cap, uint64_t *n);
+
+#define PA_STATE_V 0        /* n_cv doubles, CV order of pa_cells_add */
+#define PA_STATE_M 1        /* one double per HH CV, in CV order */
+#define PA_STATE_HHH 2
+#define PA_STATE_N 3
+#define PA_STATE_G 4        /* n_syn doubles, synapse id order */
+#define PA_STATE_CA 5
+#define PA_STATE_H 6
+#define PA_STATE_Z 7
+#define PA_STATE_P 8        /* n_cells doubles */
+#define PA_STATE_EVCOUNT 9  /* 2 uint64 per synapse: delivered events per port */
+#define PA_STATE_EVSTEPSUM 10 /* 2 uint64 per synapse: sum of delivery steps */
+
+/* Copies a state array to a host buffer of n elements (count must match).
+ * FP32 state of the mixed form is widened.  READY state only. */
+pa_status pa_state_read(pa_sim *sim, int32_t what, void *out, uint64_t n);
+
+/* Overwrites a state array (codes 0-8) from a host buffer; for setting up
+ * test states.  READY state only. */
+pa_status pa_state_write(pa_sim *sim, int32_t what, const void *in, uint64_t n);
+
+/* Sizes and counters. */
+pa_status pa_stats_get(const pa_sim *sim, pa_stats *out);
+
+/* Per-launch timing of the dominant kernel (the per-step synapse and
+ * plasticity kernel in the plain form, the fused epoch kernel in the
+ * batched form) with HIP events on the simulation's stream.  When enabled,
+ * pa_kernel_time reports the summed duration and the launch count since
+ * the last enable. */
+pa_status pa_kernel_timing(pa_sim *sim, int32_t enable);
+pa_status pa_kernel_time(pa_sim *sim, double *total_ms, uint64_t *launches, const char **name);
+
+const char *pa_last_error(const pa_sim *sim);
+const char *pa_status_str(pa_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLASTICARBOR_H */

@@ -1,0 +1,304 @@
+// HIP kernels (gfx950) of one implicit-Euler step of a plastic network of
+// multi-compartment neurons, and of the spike exchange between epochs.
+//
+// Plain form: one kernel per stage per step (deliver, currents, solve,
+// gates+sum, synapses, cells), each one lane per cell / CV / synapse.
+// Batched form (kernels_fused.hip): one kernel per epoch.
+//
+// Arithmetic follows the definitions of the model term by term, in a fixed
+// order and without contraction into FMA (the library is built with
+// -ffp-contract=off), so that every FP64 result that does not go through a
+// transcendental function is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "sim.hpp"
+#include "device_common.hpp"
+
+namespace pa {
+
+// ----------------------------------------------------------------- init
+template <class T>
+__global__ void k_init(DevNet d) {
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n_hh) return;
+    T v = (T)d.V[d.hh_cv[k]];
+    T r[6];
+    hh_rates<T>(v, r);
+    ((T *)d.gm)[k] = r[0] / (r[0] + r[1]);
+    ((T *)d.gh)[k] = r[2] / (r[2] + r[3]);
+    ((T *)d.gn)[k] = r[4] / (r[4] + r[5]);
+}
+
+// ----------------------------------------------------------------- trains
+// At the start of an epoch ending at `epoch_end`, move every train arrival
+// whose delivery step falls before epoch_end into the target cell's ring.
+__global__ void k_inject(DevNet d, uint32_t nsteps) {
+    uint32_t tr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tr >= d.n_trains) return;
+    const uint32_t cell = d.tr_cell[tr];
+    const uint64_t end = d.tr_off[tr + 1];
+    const uint64_t epoch_start = d.ctr->step;
+    const uint64_t epoch_end = epoch_start + nsteps;
+    Event e;
+    e.w = d.tr_w[tr];
+    e.syn = d.tr_syn[tr];
+    e.src = d.n_cells + tr;
+    e.conn = 0;
+    if (d.tr_ports[tr] & 1) {
+        uint64_t j = d.tr_cur[2 * tr];
+        for (; j < end; ++j) {
+            double t = d.tr_t[j];
+            uint64_t s = (uint64_t)floor(t / d.dt);
+            if (s >= epoch_end) break;
+            e.t = t;
+            e.port = 1;
+            push_event(d, cell, s, e, epoch_start);
+        }
+        d.tr_cur[2 * tr] = j;
+    }
+    if (d.tr_ports[tr] & 2) {
+        uint64_t j = d.tr_cur[2 * tr + 1];
+        for (; j < end; ++j) {
+            double t = d.tr_t[j] + d.stc.t_cd;
+            uint64_t s = (uint64_t)floor(t / d.dt);
+            if (s >= epoch_end) break;
+            e.t = t;
+            e.port = 2;
+            push_event(d, cell, s, e, epoch_start);
+        }
+        d.tr_cur[2 * tr + 1] = j;
+    }
+}
+
+// ----------------------------------------------------------------- deliver
+template <class T>
+__global__ void k_deliver(DevNet d, uint64_t n) {
+    uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= d.n_cells) return;
+    deliver_cell<T>(d, cell, n);
+}
+
+// ----------------------------------------------------------------- currents
+template <class T>
+__global__ void k_current(DevNet d, double tn) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.n_cv) return;
+    double I, G;
+    cv_current<T>(d, i, d.V[i], tn, I, G);
+    d.I[i] = I;
+    d.G[i] = G;
+}
+
+// ----------------------------------------------------------------- solve
+// Assembly of the backward-Euler cable system and Hines elimination in
+// descending CV order, one lane per cell.
+__global__ void k_solve(DevNet d) {
+    uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= d.n_cells) return;
+    const uint32_t b0 = d.cv_off[cell], b1 = d.cv_off[cell + 1];
+    d.vdet_old[cell] = d.V[d.det_cv[cell]];
+    for (uint32_t i = b0; i < b1; ++i) {
+        double v = d.V[i];
+        double G = d.G[i];
+        d.D[i] = d.d0[i] + G;
+        d.b[i] = ((d.cdt[i] * v + d.gpas_e[i]) - d.I[i]) + G * v;
+    }
+    for (uint32_t i = b1 - 1; i > b0; --i) {
+        int32_t p = d.parent[i];
+        double u = -d.axial[i];
+        double f = u / d.D[i];
+        d.D[p] -= f * u;
+        d.b[p] -= f * d.b[i];
+    }
+    bool ok = true;
+    double v0 = d.b[b0] / d.D[b0];
+    d.V[b0] = v0;
+    ok = ok && isfinite(v0);
+    for (uint32_t i = b0 + 1; i < b1; ++i) {
+        double u = -d.axial[i];
+        double v = (d.b[i] - u * d.V[d.parent[i]]) / d.D[i];
+        d.V[i] = v;
+        ok = ok && isfinite(v);
+    }
+    if (!ok) raise_flag(d, FLAG_NONFINITE, cell);
+}
+
+// ----------------------------------------------------------------- gates, S
+template <class T>
+__global__ void k_cellpre(DevNet d) {
+    uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= d.n_cells) return;
+    for (uint32_t k = d.hh_off[cell]; k < d.hh_off[cell + 1]; ++k) gate_update<T>(d, k, d.V[d.hh_cv[k]]);
+    const double h0 = d.stc.h0;
+    double S = 0.0;
+    for (uint32_t s = d.syn_off[cell]; s < d.syn_off[cell + 1]; ++s)
+        if (d.syn_kind[s] == 1) S += fabs(d.h[s] - h0);
+    d.S[cell] = S;
+}
+
+// ----------------------------------------------------------------- synapses
+template <class T>
+__global__ void k_syn(DevNet d, uint64_t n) {
+    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.n_syn) return;
+    syn_update<T>(d, s, n, d.p[d.syn_cell[s]]);
+}
+
+// ----------------------------------------------------------------- cells
+__global__ void k_cellpost(DevNet d, uint64_t n) {
+    uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= d.n_cells) return;
+    prp_update(d, cell);
+    detect(d, cell, n, d.vdet_old[cell], d.V[d.det_cv[cell]]);
+}
+
+// ----------------------------------------------------------------- exchange
+// One wavefront per spike of the epoch (grid-stride), lanes over the
+// source's outgoing connections; each connection port becomes one event in
+// the target cell's ring.  Also appends the epoch's spikes to the history.
+__global__ void k_expand(DevNet d, uint32_t nsteps) {
+    const uint64_t epoch_end = d.ctr->step + nsteps;
+    const uint32_t n_sp = d.ctr->ep_n;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    const uint64_t hist0 = d.ctr->hist_n;
+    for (uint32_t k = wave; k < n_sp; k += n_waves) {
+        const uint32_t gid = d.ep_gid[k];
+        const double ts = d.ep_t[k];
+        if (lane == 0) {
+            uint64_t hpos = hist0 + k;
+            if (hpos < d.hist_cap) {
+                d.hist_gid[hpos] = gid;
+                d.hist_step[hpos] = d.ep_step[k];
+                d.hist_t[hpos] = ts;
+            } else {
+                raise_flag(d, FLAG_OVERFLOW, gid);
+            }
+        }
+        for (uint64_t q = d.out_off[gid] + lane; q < d.out_off[gid + 1]; q += 64) {
+            Event e;
+            e.w = d.out_w[q];
+            e.syn = d.out_syn[q];
+            e.src = gid;
+            e.conn = d.out_cid[q];
+            const uint32_t cell = d.out_cell[q];
+            const uint8_t ports = d.out_ports[q];
+            const double te = ts + d.out_d[q];
+            if (ports & 1) {
+                e.t = te;
+                e.port = 1;
+                push_event(d, cell, (uint64_t)floor(te / d.dt), e, epoch_end);
+            }
+            if (ports & 2) {
+                e.t = te + d.stc.t_cd;
+                e.port = 2;
+                push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, epoch_end);
+            }
+        }
+    }
+}
+
+__global__ void k_epoch_close(DevNet d, uint32_t nsteps) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.ctr->hist_n += d.ctr->ep_n;
+        d.ctr->ep_n = 0;
+        d.ctr->step += nsteps;
+    }
+}
+
+// ----------------------------------------------------------------- probes
+template <class T>
+__global__ void k_probe(DevNet d, uint64_t row) {
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n_probes) return;
+    const uint64_t i = d.pr_idx[k];
+    double v = 0.0;
+    switch (d.pr_what[k]) {
+    case 0: v = d.V[i]; break;
+    case 1: v = (double)((const T *)d.g)[i]; break;
+    case 2: v = (double)((const T *)d.c)[i]; break;
+    case 3: v = d.h[i]; break;
+    case 4: v = d.z[i]; break;
+    default: v = d.p[i]; break;
+    }
+    d.pr_buf[row * d.n_probes + k] = v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ================================================================= launchers
+static inline dim3 grid_for(uint64_t n, uint32_t block) {
+    uint64_t g = (n + block - 1) / block;
+    return dim3((uint32_t)(g ? g : 1));
+}
+
+int launch_init(const DevNet &d, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (d.n_hh == 0) return 0;
+    if (d.mixed) hipLaunchKernelGGL(k_init<float>, grid_for(d.n_hh, 256), dim3(256), 0, s, d);
+    else hipLaunchKernelGGL(k_init<double>, grid_for(d.n_hh, 256), dim3(256), 0, s, d);
+    return (int)hipGetLastError();
+}
+
+int launch_inject(const DevNet &d, uint32_t nsteps, void *stream) {
+    if (d.n_trains == 0) return 0;
+    hipLaunchKernelGGL(k_inject, grid_for(d.n_trains, 256), dim3(256), 0, (hipStream_t)stream, d,
+                       nsteps);
+    return (int)hipGetLastError();
+}
+
+template <class T>
+static int step_plain(const DevNet &d, uint64_t n, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 b(256);
+    const double tn = (double)n * d.dt;
+    hipLaunchKernelGGL(k_deliver<T>, grid_for(d.n_cells, 256), b, 0, s, d, n);
+    hipLaunchKernelGGL(k_current<T>, grid_for(d.n_cv, 256), b, 0, s, d, tn);
+    hipLaunchKernelGGL(k_solve, grid_for(d.n_cells, 64), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_cellpre<T>, grid_for(d.n_cells, 64), dim3(64), 0, s, d);
+    if (e0) (void)hipEventRecord(e0, s);
+    if (d.n_syn) hipLaunchKernelGGL(k_syn<T>, grid_for(d.n_syn, 256), b, 0, s, d, n);
+    if (e1) (void)hipEventRecord(e1, s);
+    hipLaunchKernelGGL(k_cellpost, grid_for(d.n_cells, 256), b, 0, s, d, n);
+    return (int)hipGetLastError();
+}
+
+int launch_step_plain(const DevNet &d, uint64_t n, void *stream, void *ev_begin, void *ev_end) {
+    if (d.mixed)
+        return step_plain<float>(d, n, (hipStream_t)stream, (hipEvent_t)ev_begin, (hipEvent_t)ev_end);
+    return step_plain<double>(d, n, (hipStream_t)stream, (hipEvent_t)ev_begin, (hipEvent_t)ev_end);
+}
+
+int launch_expand(const DevNet &d, uint32_t nsteps, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    // enough wavefronts for a busy epoch, bounded so an idle epoch is cheap
+    uint64_t waves = (uint64_t)d.n_cells * d.K;
+    if (waves > 4096) waves = 4096;
+    if (waves < 4) waves = 4;
+    hipLaunchKernelGGL(k_expand, grid_for(waves * 64, 256), dim3(256), 0, s, d, nsteps);
+    hipLaunchKernelGGL(k_epoch_close, dim3(1), dim3(64), 0, s, d, nsteps);
+    return (int)hipGetLastError();
+}
+
+int launch_probe(const DevNet &d, uint64_t row, void *stream) {
+    if (d.n_probes == 0) return 0;
+    if (d.mixed)
+        hipLaunchKernelGGL(k_probe<float>, grid_for(d.n_probes, 256), dim3(256), 0, (hipStream_t)stream, d, row);
+    else
+        hipLaunchKernelGGL(k_probe<double>, grid_for(d.n_probes, 256), dim3(256), 0, (hipStream_t)stream, d, row);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream) {
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_fill_u32, grid_for(n, 256), dim3(256), 0, (hipStream_t)stream, p, v, n);
+    return (int)hipGetLastError();
+}
+
+}  // namespace pa

@@ -1,0 +1,137 @@
+// Internal layout of a finalized simulation on the device.
+//
+// Structure-of-arrays, indices in uint32 (a single MI355X holds < 2^32 CVs,
+// synapses and connections of any network that fits its 288 GB).  Synapses
+// are stored sorted by (cell, CV, id) so that each CV's synapses and each
+// cell's synapses are contiguous; connections are stored as a table by
+// source cell.  Per cell, events wait in a ring of R slots indexed by
+// delivery step modulo R, each slot holding up to Q events.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pa {
+
+struct Event {
+    double t;       // delivery time t_e (ms): sort key 1
+    double w;       // weight of the conductance port (uS)
+    uint32_t syn;   // sorted synapse index
+    uint32_t src;   // source id: cell gid, or n_cells + train index: sort key 2
+    uint32_t conn;  // connection id (0 for trains): sort key 3
+    uint32_t port;  // 1 conductance, 2 calcium: sort key 4
+};
+static_assert(sizeof(Event) == 32, "event record is 32 bytes");
+
+// Error flags raised on the device, read back after every chunk of steps.
+enum : uint32_t { FLAG_OVERFLOW = 1u, FLAG_LATE = 2u, FLAG_NONFINITE = 4u };
+
+struct Counters {
+    uint64_t step;      // first step of the current epoch (advanced by the epoch close)
+    uint32_t ep_n;      // spikes of the current epoch
+    uint32_t flags;     // FLAG_*
+    uint64_t hist_n;    // spikes in the history buffer of the current chunk
+    uint64_t events;    // events delivered
+    uint32_t bad_cell;  // first cell that raised a flag
+    uint32_t pad;
+};
+
+struct Stc {
+    double tau_c, tau_h, tau_p, tau_z, gamma_p, gamma_d, theta_p, theta_d;
+    double sigma_pl, p_max, f_int, t_cd, h0, theta_pro, theta_tag, c_pre, c_post;
+};
+
+// Everything a kernel needs, passed by value.
+struct DevNet {
+    uint32_t n_cells, n_cv, n_syn, n_hh, n_trains, n_probes;
+    uint32_t R, Q, K;
+    uint32_t mixed;      // gates, g and c stored in FP32
+    double dt, theta;
+    uint64_t seed;
+    Stc stc;
+    double r_c;          // exp(-dt / tau_c)
+    float r_c_f;
+
+    // cells
+    const uint32_t *cv_off;      // n_cells + 1
+    const uint32_t *det_cv;      // global detector CV
+    const uint32_t *syn_off;     // n_cells + 1, into sorted synapses
+    const uint32_t *hh_off;      // n_cells + 1, into the HH list
+    double *p, *S, *vdet_old;
+    uint8_t *post;
+
+    // CVs
+    const int32_t *parent;       // global parent, -1 at roots
+    const double *cdt, *d0, *gpas_e, *axial;
+    const int32_t *hh_of;        // HH slot or -1
+    const uint32_t *cv_syn_off;  // n_cv + 1
+    const uint32_t *cv_cl_off;   // n_cv + 1, into clamps sorted by (CV, id)
+    double *V, *I, *G, *D, *b;
+
+    // HH
+    const uint32_t *hh_cv;
+    const double *hh_scale;      // 1e-2 * area
+    const double *hh_par;        // 6 per HH CV: gna gk gl ena ek el
+    void *gm, *gh, *gn;          // double or float
+
+    // synapses, sorted
+    const uint32_t *syn_cell, *syn_cv;
+    const uint8_t *syn_kind;
+    const double *syn_erev, *syn_decay;
+    const float *syn_decay_f;
+    const uint32_t *syn_sid;
+    void *g, *c;                 // double or float
+    double *h, *z;
+    unsigned long long *ev_cnt, *ev_sum;  // 2 per synapse
+
+    // connections by source
+    const uint64_t *out_off;     // n_cells + 1
+    const uint32_t *out_syn, *out_cell, *out_cid;
+    const uint8_t *out_ports;
+    const double *out_w, *out_d;
+
+    // trains
+    const uint32_t *tr_syn, *tr_cell;
+    const uint8_t *tr_ports;
+    const double *tr_w, *tr_t;
+    const uint64_t *tr_off;
+    uint64_t *tr_cur;            // 2 per train: conductance and calcium cursors
+
+    // clamps, sorted by (CV, id)
+    const double *cl_t0, *cl_dur, *cl_amp;
+
+    // event rings
+    uint32_t *ev_n;              // n_cells * R
+    Event *ev;                   // n_cells * R * Q
+
+    // spikes
+    uint32_t *ep_gid, *ep_step;  // capacity K * n_cells
+    double *ep_t;
+    uint32_t *hist_gid;          // capacity hist_cap
+    uint64_t *hist_step;
+    double *hist_t;
+    uint64_t hist_cap;
+    Counters *ctr;
+
+    // probes
+    const int32_t *pr_what;
+    const uint64_t *pr_idx;      // internal index (sorted synapse, CV, cell)
+    double *pr_buf;              // samples x n_probes
+};
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return a HIP error
+// code (0 on success).
+int launch_init(const DevNet &d, void *stream);
+// The epoch kernels (inject, fused epoch, expand, close) take the epoch's
+// first step from Counters::step on the device, so that a captured graph
+// of epochs can be replayed; the close kernel advances it.
+int launch_inject(const DevNet &d, uint32_t nsteps, void *stream);
+int launch_step_plain(const DevNet &d, uint64_t n, void *stream, void *ev_begin, void *ev_end);
+int launch_expand(const DevNet &d, uint32_t nsteps, void *stream);
+int launch_probe(const DevNet &d, uint64_t row, void *stream);
+// Fused epoch: block b owns cells blk[4b] .. blk[4b+1]-1 (see BlockPlan).
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, uint32_t n_blocks,
+                       size_t lds_bytes, void *stream);
+int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream);
+
+}  // namespace pa

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded
+networks, through the C ABI.
+
+Bar (FP64 forms): spike rasters identical in count, order (step, gid) and
+crossing step; crossing times within 1e-9 relative; delivered-event
+multiset per (synapse, port) identical (count and sum of delivery steps);
+voltages |dV| <= 1e-9 max(|V|, 1 mV); other state within 1e-9 relative.
+Transcendentals (exp, log, sin, cos) differ in the last ulp between the
+host C library and the device math library, which is all that separates
+the two sides' FP64 arithmetic; the event-driven coupling between cells is
+quantised to steps, so these ulps do not reach the rasters.
+"""
+import numpy as np
+import pytest
+
+import netgen
+import oracle
+from _parity import (assert_raster_equal, assert_routing_equal, assert_state_close,
+                     assert_v_close, run_pair)
+from paper_2411_16445_amd import PAError, Simulation
+from paper_2411_16445_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+@pytest.mark.parametrize("seed", [3, 7, 11])
+def test_tiny_networks_match_oracle(seed, mode):
+    net = netgen.tiny(seed=seed, n_cells=13, t_end=200.0)
+    _say(f"tiny seed={seed} mode={mode}")
+    o, s = run_pair(net, 1000, chunks=3, mode=mode)
+    n = assert_raster_equal(o, s)
+    assert n > 10
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_single_synapse_config_full_horizon(mode):
+    """1 cell, 9 CVs, one plastic synapse at 20 Hz, 10 s (50,000 steps)."""
+    net = netgen.config1()
+    _say(f"config1 10s mode={mode}")
+    o, s = run_pair(net, 50000, chunks=2, mode=mode)
+    assert assert_raster_equal(o, s) > 50
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_ei_network_full_size_short_horizon(mode):
+    """2000 ball-and-stick cells, ~400k synapses (~255k plastic), 60 ms."""
+    net = netgen.config2(t_end=200.0)
+    _say(f"config2 full size 300 steps mode={mode}")
+    o, s = run_pair(net, 300, chunks=2, mode=mode)
+    assert assert_raster_equal(o, s) > 100
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_uneven_trees_full_size_short_horizon(mode):
+    """4096 random trees of 10-300 CVs, 100 plastic sites each, 30 ms."""
+    net = netgen.config3(t_end=60.0)
+    _say(f"config3 full size 150 steps mode={mode}")
+    o, s = run_pair(net, 150, mode=mode)
+    assert_raster_equal(o, s)
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
+def test_probes_sample_the_oracle_trajectory():
+    net = netgen.tiny(seed=5, n_cells=7, t_end=100.0)
+    probes = [("V", 0), ("V", int(net["cv_off"][3]) + 1), ("p", 2)]
+    stc_syn = int(np.nonzero(net["syn_kind"] == 1)[0][0])
+    probes += [("g", stc_syn), ("c", stc_syn), ("h", stc_syn), ("z", stc_syn)]
+    _say("probes tiny seed=5")
+    s = Simulation(net, probes=probes, probe_stride=3)
+    o = oracle.Oracle(net)
+    rows = []
+    for _ in range(100):
+        o.run(3)
+        v = o.read("V")
+        rows.append([v[0], v[probes[1][1]], o.read("p")[2], o.read("g")[stc_syn],
+                     o.read("c")[stc_syn], o.read("h")[stc_syn], o.read("z")[stc_syn]])
+    s.advance_steps(150)
+    s.advance_steps(150)
+    got = s.probes()
+    assert got.shape == (100, 7)
+    np.testing.assert_allclose(got, np.array(rows), rtol=1e-9, atol=1e-12)
+
+
+def test_noise_path_matches_bitwise_generator():
+    """Both thresholds crossed on many synapses: one step of h carries the
+    Threefry + Box-Muller normal; agreement to 1e-12 means the device
+    generator produced the same 64-bit words as the oracle's."""
+    b = netgen._Builder()
+    b.add_cell([-1], [20.0], [20.0], [netgen.MECH_PAS])
+    for _ in range(3000):
+        b.add_syn(0, 0, netgen.KIND_STC, 5.0, 0.0)
+    net = b.finish("noise", 0.2, 10.0, 123456789, netgen.STC_TABLE5)
+    o = oracle.Oracle(net)
+    s = Simulation(net)
+    rng = np.random.default_rng(0)
+    for k in range(6):
+        h = rng.uniform(3.0, 5.0, 3000)
+        for x in (o, s):
+            x.write("h", h)
+            x.write("c", np.full(3000, 50.0))
+        o.run(1)
+        s.advance_steps(1)
+        ho, hs = o.read("h"), s.read("h")
+        assert np.abs(hs - ho).max() <= 1e-12 * np.abs(ho).max()
+        assert np.abs(ho - h).max() > 1e-6  # the noise is there
+
+
+def test_gpu_runs_are_deterministic():
+    net = netgen.tiny(seed=21, n_cells=17, t_end=150.0)
+    _say("determinism tiny seed=21")
+    r = []
+    for _ in range(2):
+        s = Simulation(net)
+        s.advance_steps(750)
+        r.append((s.spikes(), s.read("V"), s.read("h"), s.read("g")))
+    for a, b in zip(r[0][0], r[1][0]):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(r[0][1:], r[1][1:]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_plain_and_batched_forms_are_bitwise_identical():
+    net = netgen.tiny(seed=8, n_cells=23, t_end=150.0)
+    _say("plain vs batched tiny seed=8")
+    out = []
+    for mode in ("plain", "batched"):
+        s = Simulation(net, mode=mode)
+        s.advance_steps(700)
+        out.append((s.spikes(), s.read("V"), s.read("h"), s.read("z"), s.read("g"), s.read("c")))
+    for a, b in zip(out[0][0], out[1][0]):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(out[0][1:], out[1][1:]):
+        np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------------------------------------------ edges
+def test_edge_cases_empty_and_degenerate():
+    """Cells without synapses, a network without connections or trains, a
+    single one-CV cell, zero-step advances."""
+    b = netgen._Builder()
+    b.add_cell([-1], [20.0], [20.0], [netgen.MECH_HH])
+    b.add_cell([-1, 0, 1, 1], [20.0, 10.0, 10.0, 10.0], [20.0, 1.0, 1.0, 2.0], [1, 0, 0, 0])
+    b.add_clamp(1, 0, 2.0, 5.0, 0.3)
+    net = b.finish("edges", 0.1, 50.0, 1, netgen.STC_TABLE5)
+    _say("edges")
+    for mode in ("plain", "batched"):
+        o, s = run_pair(net, 400, chunks=4, mode=mode)
+        s.advance_steps(0)
+        assert_raster_equal(o, s)
+        assert_v_close(o.read("V"), s.read("V"))
+
+
+def test_advance_time_grid_and_errors():
+    net = netgen.tiny(seed=2, n_cells=5, t_end=20.0)
+    s = Simulation(net)
+    s.advance(10.0)
+    assert s.stats()["steps"] == 50
+    with pytest.raises(PAError) as e:
+        s.advance(10.05)        # off the 0.2 ms grid
+    assert e.value.status == B.PA_ERANGE
+    with pytest.raises(PAError) as e:
+        s.advance(4.0)          # backwards
+    assert e.value.status == B.PA_ERANGE
+    s.advance(10.0)             # same time: no-op
+    s.advance(20.0)
+    assert s.stats()["steps"] == 100
+
+
+def test_slot_overflow_is_reported():
+    net = netgen.tiny(seed=4, n_cells=9, t_end=100.0, ext_rate=2000.0)
+    _say("overflow tiny seed=4 slot_capacity=1")
+    s = Simulation(net, slot_capacity=1)
+    with pytest.raises(PAError) as e:
+        s.advance_steps(500)
+    assert e.value.status == B.PA_EOVERFLOW
+    with pytest.raises(PAError) as e:
+        s.advance_steps(1)      # refuses after a failure
+    assert e.value.status == B.PA_ESTATE
+
+
+def test_non_finite_voltage_is_reported():
+    net = netgen.tiny(seed=6, n_cells=4, t_end=10.0)
+    s = Simulation(net)
+    v = s.read("V")
+    v[3] = np.nan
+    s.write("V", v)
+    _say("nonfinite")
+    with pytest.raises(PAError) as e:
+        s.advance_steps(5)
+    assert e.value.status == B.PA_ENUMERIC
+
+
+def test_mixed_precision_stays_close_over_short_horizon():
+    """Mixed form (FP32 gates, conductances, calcium): a report, not parity.
+    Until the first spike the voltage error is FP32 rounding (< 0.01 mV);
+    over 40 ms the spike count stays within 25 % of the FP64 oracle's."""
+    net = netgen.tiny(seed=3, n_cells=13, t_end=60.0)
+    _say("mixed tiny seed=3")
+    for mode in ("plain", "batched"):
+        o = oracle.Oracle(net)
+        s = Simulation(net, precision="mixed", mode=mode)
+        checked = 0
+        while o.step < 200:
+            o.run(1)
+            s.advance_steps(1)
+            if o.spikes()[0].size:
+                break
+            assert np.abs(s.read("V") - o.read("V")).max() < 1e-2
+            checked += 1
+        assert checked >= 5
+        o.run(200 - o.step)
+        s.advance_steps(200 - s.stats()["steps"])
+        no, ns = o.spikes()[0].size, s.spikes()[0].size
+        assert abs(ns - no) <= 0.25 * no + 2, (no, ns)
+        assert np.all(np.isfinite(s.read("V")))
