@@ -149,7 +149,8 @@ def main():
         "config": {"workload": "ei-ball-and-stick-2000x21cv", "cells": head["stats"]["n_cells"],
                    "cvs": head["stats"]["n_cv"], "synapses": head["stats"]["n_syn"],
                    "stc_synapses": head["stats"]["n_stc"], "dt_ms": 0.2, "form": args.form,
-                   "epoch_steps": head["epoch_steps"], "parallelism": "single-gpu"},
+                   "epoch_steps": head["epoch_steps"], "cells_per_block": head["cells_per_block"],
+                   "parallelism": "single-gpu"},
         "synapse_updates_per_s": head["synapse_updates_per_s"],
         "stc_synapse_updates_per_s": head["stc_synapse_updates_per_s"],
         "spikes": head["spikes"],

@@ -113,7 +113,7 @@ typedef struct {
 } pa_cell_params;
 
 typedef struct {
-    uint64_t n_cells, n_cv, n_syn, n_stc, n_conn, n_trains, n_probes;
+    uint64_t n_cells, n_cv, n_syn, n_stc, n_conn, n_trains, n_probes, n_poisson;
     uint64_t steps, spikes, events;
     uint32_t epoch_steps;    /* K: steps between spike exchanges */
     uint32_t ring_slots;     /* R: per-cell event slots */
@@ -177,6 +177,17 @@ pa_status pa_connect(pa_sim *sim, uint64_t n, const uint32_t *src_gid, const uin
  * Errors: PA_EINVAL. */
 pa_status pa_trains_add(pa_sim *sim, uint32_t n, const uint32_t *dst_sid, const uint8_t *ports,
                         const double *weight_uS, const int64_t *time_off, const double *times_ms);
+
+/* Adds n Poisson sources: source k delivers arrivals of a homogeneous
+ * Poisson process of rate_hz[k] to synapse dst_sid[k] through ports[k] with
+ * weight weight_uS[k] (the calcium port adds t_cd).  Arrival j of source k
+ * follows the previous one (or t = 0) after -ln(u) / rate, u the first
+ * output word of Threefry-4x64-12 with counter (j, 0, 0, 0) and key (seed,
+ * k, tag, 0) mapped to (0, 1); k counts Poisson sources in call order.
+ * Sources act as event sources with ids n_cells + n_trains + k.  rate 0
+ * gives no arrivals.  Errors: PA_EINVAL. */
+pa_status pa_poisson_add(pa_sim *sim, uint32_t n, const uint32_t *dst_sid, const uint8_t *ports,
+                         const double *weight_uS, const double *rate_hz);
 
 /* Adds n current clamps injecting amp_nA[k] into local CV cv[k] of cell
  * gid[k] during t0 <= t_n < t0 + dur.  Errors: PA_EINVAL. */

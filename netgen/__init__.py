@@ -21,6 +21,8 @@ Network dictionary (all arrays are numpy, C-contiguous):
   trains     train_dst, train_ports, train_w, train_off[int64 n+1],
              train_times[f64 ms, sorted within each train]
   clamps     clamp_cell, clamp_cv, clamp_t0, clamp_dur, clamp_amp[nA]
+  poisson    pois_dst, pois_ports, pois_w, pois_rate[Hz]: sources whose
+             arrivals are drawn by the simulator from the network's seed
   scalars    dt, theta (detector threshold mV), seed, t_end, name, stc{...}
 
 Units: ms, mV, um, nA, uS, nF.  The seed recipe (one master seed, split into
@@ -68,10 +70,15 @@ class _Builder:
         self.cv_off = [0]
         self.parent, self.length, self.diam, self.mech = [], [], [], []
         self.detector, self.cell_params = [], []
-        self.syn = []      # (cell, cv, kind, tau, erev)
+        self.syn = []      # (cell, cv, kind, tau, erev) added one by one
+        self._bulk = []    # bulk synapse arrays
+        self._nbulk = 0
+        self._chunks = []  # flushed synapse arrays, in id order
+        self._nsyn_flushed = 0
         self.conn = []     # arrays appended in chunks
         self.trains = []   # (dst, ports, w, times)
         self.clamps = []
+        self.pois = []     # (dst, ports, w, rate)
 
     @property
     def n_cells(self):
@@ -89,8 +96,43 @@ class _Builder:
         return self.n_cells - 1
 
     def add_syn(self, cell, cv, kind, tau=5.0, erev=0.0):
+        if self._bulk:
+            self._flush_bulk()
         self.syn.append((cell, cv, kind, tau, erev))
-        return len(self.syn) - 1
+        return self.n_syn - 1
+
+    def add_syns(self, cells, cvs, kind, tau=5.0, erev=0.0):
+        """Bulk form of add_syn; returns the new synapse ids."""
+        if self.syn:
+            self._flush_bulk()
+        cells = np.asarray(cells, np.int32)
+        n = len(cells)
+        first = self.n_syn
+        self._bulk.append((cells, np.asarray(cvs, np.int32),
+                           np.broadcast_to(np.asarray(kind, np.uint8), (n,)).copy(),
+                           np.broadcast_to(np.asarray(tau, np.float64), (n,)).copy(),
+                           np.broadcast_to(np.asarray(erev, np.float64), (n,)).copy()))
+        self._nbulk += n
+        return np.arange(first, first + n, dtype=np.int64)
+
+    @property
+    def n_syn(self):
+        return self._nsyn_flushed + len(self.syn) + self._nbulk
+
+    def _flush_bulk(self):
+        # keep synapse ids in call order: tuples added so far become a chunk
+        if self.syn:
+            s = self.syn
+            self._chunks.append((np.array([x[0] for x in s], np.int32), np.array([x[1] for x in s], np.int32),
+                                 np.array([x[2] for x in s], np.uint8), np.array([x[3] for x in s], np.float64),
+                                 np.array([x[4] for x in s], np.float64)))
+            self._nsyn_flushed += len(s)
+            self.syn = []
+        if self._bulk:
+            self._chunks.extend(self._bulk)
+            self._nsyn_flushed += self._nbulk
+            self._bulk = []
+            self._nbulk = 0
 
     def add_conns(self, src, dst, ports, w, d):
         src = np.asarray(src, np.int32)
@@ -106,6 +148,11 @@ class _Builder:
     def add_clamp(self, cell, cv, t0, dur, amp):
         self.clamps.append((cell, cv, t0, dur, amp))
 
+    def add_poisson(self, dst, ports, w, rate_hz):
+        dst = np.atleast_1d(np.asarray(dst, np.int64))
+        for x in dst:
+            self.pois.append((int(x), ports, w, rate_hz))
+
     def finish(self, name, dt, t_end, seed, stc, theta=-10.0):
         net = dict(name=name, dt=float(dt), t_end=float(t_end), seed=int(seed),
                    theta=float(theta), stc=dict(stc))
@@ -119,12 +166,11 @@ class _Builder:
         net["detector"] = np.asarray(self.detector, np.int32)
         net["cell_params"] = np.ascontiguousarray(np.stack(self.cell_params).astype(np.float64)) \
             if self.cell_params else np.zeros((0, N_CELL_PARAMS))
-        s = self.syn
-        net["syn_cell"] = np.array([x[0] for x in s], np.int32)
-        net["syn_cv"] = np.array([x[1] for x in s], np.int32)
-        net["syn_kind"] = np.array([x[2] for x in s], np.uint8)
-        net["syn_tau"] = np.array([x[3] for x in s], np.float64)
-        net["syn_erev"] = np.array([x[4] for x in s], np.float64)
+        self._flush_bulk()
+        ch = self._chunks
+        for k, (name, t) in enumerate((("syn_cell", np.int32), ("syn_cv", np.int32), ("syn_kind", np.uint8),
+                                        ("syn_tau", np.float64), ("syn_erev", np.float64))):
+            net[name] = np.concatenate([c[k] for c in ch]).astype(t) if ch else np.zeros(0, t)
         if self.conn:
             c = list(zip(*self.conn))
             net["conn_src"] = np.concatenate(c[0]).astype(np.int32)
@@ -148,6 +194,11 @@ class _Builder:
         net["clamp_t0"] = np.array([x[2] for x in cl], np.float64)
         net["clamp_dur"] = np.array([x[3] for x in cl], np.float64)
         net["clamp_amp"] = np.array([x[4] for x in cl], np.float64)
+        po = self.pois
+        net["pois_dst"] = np.array([x[0] for x in po], np.int32)
+        net["pois_ports"] = np.array([x[1] for x in po], np.uint8)
+        net["pois_w"] = np.array([x[2] for x in po], np.float64)
+        net["pois_rate"] = np.array([x[3] for x in po], np.float64)
         return net
 
 
@@ -236,8 +287,9 @@ def poisson_times(rng, rate_hz, t_end_ms):
 
 
 def _merge_trains(rng, n_sources, rate_hz, t_end_ms):
-    """One sorted train holding the union of n independent Poisson sources."""
-    return np.sort(np.concatenate([poisson_times(rng, rate_hz, t_end_ms) for _ in range(n_sources)]))
+    """Arrivals of n independent Poisson sources onto one synapse: their
+    union is a Poisson process of the summed rate, drawn as such."""
+    return poisson_times(rng, n_sources * rate_hz, t_end_ms)
 
 
 # ---------------------------------------------------------------- workloads
@@ -317,17 +369,14 @@ def _tree_network(name, seed, t_end, n_cells, n_min, n_max, sites=100, p=None,
                   n_ext=25, ext_rate=5.0, explicit_trains=True, max_train_t=None):
     rng_m, rng_s, rng_c, rng_d, rng_t = _streams(seed, 5)
     b = _Builder()
-    site_ids = []
     for c in range(n_cells):
         parent, length, diam, mech = random_tree(rng_m, n_min, n_max)
         b.add_cell(parent, length, diam, mech)
-        ncv = len(parent)
-        cvs = rng_s.integers(1, ncv, sites)
-        site_ids.append([b.add_syn(c, int(cv), KIND_STC, 5.0, 0.0) for cv in cvs])
-    ext_syn = []
-    for c in range(n_cells):
-        ncv = b.cv_off[c + 1] - b.cv_off[c]
-        ext_syn.append(b.add_syn(c, ncv - 1, KIND_EXPSYN, 5.0, 0.0))
+    ncv = np.diff(np.asarray(b.cv_off))
+    # sites of cell c are synapses c*sites .. c*sites+sites-1
+    site_cv = (1 + np.floor(rng_s.random((n_cells, sites)) * (ncv[:, None] - 1))).astype(np.int32)
+    b.add_syns(np.repeat(np.arange(n_cells), sites), site_cv.ravel(), KIND_STC, 5.0, 0.0)
+    ext_syn = b.add_syns(np.arange(n_cells), ncv - 1, KIND_EXPSYN, 5.0, 0.0)
     src_all, dst_all = [], []
     for tgt in range(n_cells):
         if indegree is not None:
@@ -337,9 +386,10 @@ def _tree_network(name, seed, t_end, n_cells, n_min, n_max, sites=100, p=None,
             src = np.nonzero(rng_c.random(n_cells) < p)[0]
             src = src[src != tgt]
         # incoming connection j goes to site j mod sites (round-robin)
-        for j, s_ in enumerate(src):
-            src_all.append(int(s_))
-            dst_all.append(site_ids[tgt][j % sites])
+        src_all.append(src.astype(np.int32))
+        dst_all.append((tgt * sites + np.arange(len(src)) % sites).astype(np.int32))
+    src_all = np.concatenate(src_all)
+    dst_all = np.concatenate(dst_all)
     nc = len(src_all)
     if delay_exp:
         d = 1.0 + rng_d.exponential(1.0, nc)
@@ -353,7 +403,10 @@ def _tree_network(name, seed, t_end, n_cells, n_min, n_max, sites=100, p=None,
     if explicit_trains:
         t_tr = t_end if max_train_t is None else min(t_end, max_train_t)
         for c in range(n_cells):
-            b.add_train(ext_syn[c], PORT_G, w_ext, _merge_trains(rng_t, n_ext, ext_rate, t_tr))
+            b.add_train(int(ext_syn[c]), PORT_G, w_ext, _merge_trains(rng_t, n_ext, ext_rate, t_tr))
+    else:
+        # simulator-drawn Poisson input, one source of the summed rate per cell
+        b.add_poisson(ext_syn, PORT_G, w_ext, n_ext * ext_rate)
     stc = dict(STC_TABLE5)
     stc.update(CA_INVIVO)
     net = b.finish(name, 0.2, t_end, seed, stc)
@@ -367,15 +420,16 @@ def config3(seed=3, t_end=10000.0, **kw):
     return _tree_network("uneven-trees-4096", seed, t_end, 4096, 10, 300, p=0.02, **kw)
 
 
-def config5(seed=5, t_end=10000.0, n_cells=100_000, **kw):
+def config5(seed=5, t_end=10000.0, n_cells=100_000, explicit_trains=False, **kw):
     """1e5 cells with random trees of 10-60 dendritic CVs, in-degree exactly
-    100 (one source per STC site), delays 1 ms + Exp(1 ms) redrawn above 5 ms."""
+    100 (one source per STC site), delays 1 ms + Exp(1 ms) redrawn above 5 ms;
+    external drive drawn by the simulator (one 125 Hz Poisson source per cell)."""
     return _tree_network("large-1e5", seed, t_end, n_cells, 10, 60, indegree=100,
-                         delay_exp=True, **kw)
+                         delay_exp=True, explicit_trains=explicit_trains, **kw)
 
 
 def tiny(seed=7, n_cells=13, t_end=200.0, n_min=2, n_max=24, p=0.35, n_static=3,
-         clamp=True, dt=0.2, delay_range=(0.6, 4.0), w_ext=0.02, ext_rate=150.0):
+         clamp=True, dt=0.2, delay_range=(0.6, 4.0), w_ext=0.02, ext_rate=150.0, poisson=False):
     """Small random network exercising every feature: random trees (1-CV
     cells included), mixed synapse kinds, several synapses per CV, random
     delays, two-port connections, explicit trains and current clamps."""
@@ -418,6 +472,12 @@ def tiny(seed=7, n_cells=13, t_end=200.0, n_min=2, n_max=24, p=0.35, n_static=3,
         sid = int(rng_t.choice(cell_syns))
         pr = PORT_G | PORT_CA if kinds[sid] == KIND_STC else PORT_G
         b.add_train(sid, pr, w_ext, poisson_times(rng_t, ext_rate, t_end))
+    if poisson:
+        for c in range(n_cells):
+            cell_syns = [i for i in range(n_syn) if b.syn[i][0] == c]
+            sid = int(rng_t.choice(cell_syns))
+            pr = PORT_G | PORT_CA if kinds[sid] == KIND_STC else PORT_G
+            b.add_poisson(sid, pr, w_ext, ext_rate)
     if clamp:
         b.add_clamp(0, 0, 5.0, 40.0, 0.3)
         b.add_clamp(min(2, n_cells - 1), 0, 60.0, 30.0, 0.25)
@@ -435,4 +495,4 @@ def summary(net):
     return dict(name=net["name"], cells=int(net["n_cells"]), cvs=int(net["cv_off"][-1]),
                 syn=int(len(kinds)), stc=int((kinds == KIND_STC).sum()),
                 conns=int(len(net["conn_src"])), trains=int(len(net["train_dst"])),
-                train_events=int(len(net["train_times"])))
+                train_events=int(len(net["train_times"])), poisson=int(len(net.get("pois_dst", []))))

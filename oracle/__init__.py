@@ -56,7 +56,8 @@ class _Net(C.Structure):
          ("n_trains", _I64), ("train_dst", _P), ("train_ports", _P), ("train_w", _P),
          ("train_off", _P), ("train_times", _P),
          ("n_clamps", _I64), ("clamp_cell", _P), ("clamp_cv", _P), ("clamp_t0", _P),
-         ("clamp_dur", _P), ("clamp_amp", _P)]
+         ("clamp_dur", _P), ("clamp_amp", _P),
+         ("n_pois", _I64), ("pois_dst", _P), ("pois_ports", _P), ("pois_w", _P), ("pois_rate", _P)]
 
 
 _lib = None
@@ -89,6 +90,8 @@ def _load():
         lib.orc_normal.restype = _D
         lib.orc_normal.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
         lib.orc_hh_rates.argtypes = [_D, _P]
+        lib.orc_poisson_isi.restype = _D
+        lib.orc_poisson_isi.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, _D]
         _lib = lib
     return _lib
 
@@ -104,6 +107,7 @@ _ARRAYS = {
     "train_w": np.float64, "train_off": np.int64, "train_times": np.float64,
     "clamp_cell": np.int32, "clamp_cv": np.int32, "clamp_t0": np.float64,
     "clamp_dur": np.float64, "clamp_amp": np.float64,
+    "pois_dst": np.int32, "pois_ports": np.uint8, "pois_w": np.float64, "pois_rate": np.float64,
 }
 
 
@@ -116,7 +120,7 @@ class Oracle:
 
     def __init__(self, net: dict):
         lib = _load()
-        self._keep = {k: np.ascontiguousarray(net[k], dtype=t) for k, t in _ARRAYS.items()}
+        self._keep = {k: np.ascontiguousarray(net.get(k, np.zeros(0, t)), dtype=t) for k, t in _ARRAYS.items()}
         st = net["stc"]
         s = _Net()
         s.dt, s.theta, s.seed = net["dt"], net["theta"], int(net["seed"]) & (2**64 - 1)
@@ -131,6 +135,7 @@ class Oracle:
         s.n_conn = len(self._keep["conn_src"])
         s.n_trains = len(self._keep["train_dst"])
         s.n_clamps = len(self._keep["clamp_cell"])
+        s.n_pois = len(self._keep["pois_dst"])
         self._s = s
         err = C.create_string_buffer(256)
         h = lib.orc_create(C.byref(s), err, 256)
@@ -225,6 +230,10 @@ def threefry(ctr, key):
 
 def normal(seed, sid, n):
     return _load().orc_normal(int(seed), int(sid), int(n))
+
+
+def poisson_isi(seed, k, j, rate_hz):
+    return _load().orc_poisson_isi(int(seed), int(k), int(j), float(rate_hz))
 
 
 def hh_rates(v):

@@ -31,6 +31,8 @@
  *     the crossing time, and one queued event per outgoing connection and
  *     port (delay d, calcium port a further t_c,delay later), delivered at
  *     step floor(t_e / dt).
+ *  External drive: explicit arrival trains, and Poisson sources whose
+ *  inter-arrival times come from a counter-based generator.
  *
  * The event queue is a single binary min-heap; there are no epochs.
  * Functions whose result no test pins against an independent fact are
@@ -78,6 +80,11 @@ typedef struct {
     int64_t n_clamps;
     const int32_t *clamp_cell, *clamp_cv;
     const double *clamp_t0, *clamp_dur, *clamp_amp;
+
+    int64_t n_pois;               /* Poisson sources drawn from the noise key */
+    const int32_t *pois_dst;
+    const uint8_t *pois_ports;
+    const double *pois_w, *pois_rate;
 } orc_net;
 
 /* ------------------------------------------------------------ event heap */
@@ -166,6 +173,7 @@ void orc_threefry4x64_12(const uint64_t ctr[4], const uint64_t key[4], uint64_t 
 }
 
 #define ORC_NOISE_TAG 0x5354432d6e6f6973ULL /* domain tag of the early-phase noise */
+#define ORC_POIS_TAG 0x706f6973736f6e21ULL  /* domain tag of the Poisson sources */
 
 /* uniform in (0,1): top 53 bits, offset by half an ulp so 0 never occurs */
 static double to_unit(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
@@ -184,6 +192,17 @@ double orc_normal(uint64_t seed, uint64_t sid, uint64_t n) {
     double r = sqrt(-2.0 * log(ua));
     double ang = 6.283185307179586 * ub;
     return (lane & 1) ? r * sin(ang) : r * cos(ang);
+}
+
+/* Inter-arrival time (ms) number j of Poisson source k at rate (Hz):
+ * -ln(u) / rate with u the first word of Threefry(counter j, key (seed, k,
+ * tag, 0)) mapped to (0,1).  Arrival j is the sum of intervals 0..j. */
+double orc_poisson_isi(uint64_t seed, uint64_t k, uint64_t j, double rate_hz) {
+    uint64_t key[4] = {seed, k, ORC_POIS_TAG, 0};
+    uint64_t ctr[4] = {j, 0, 0, 0};
+    uint64_t x[4];
+    orc_threefry4x64_12(ctr, key, x);
+    return -log(to_unit(x[0])) * (1000.0 / rate_hz);
 }
 
 /* ------------------------------------------------------------ HH rates */
@@ -223,6 +242,9 @@ typedef struct {
     double *p, *S;
     uint8_t *post;
     int64_t *out_off, *out_conn; /* outgoing connections per cell */
+    /* Poisson sources: next arrival time and its index */
+    double *pois_t;
+    int64_t *pois_j;
     /* spikes */
     int64_t n_spikes, cap_spikes;
     int64_t *sp_gid, *sp_step;
@@ -379,6 +401,15 @@ orc *orc_create(const orc_net *net, char *err, int errlen) {
         int32_t cell = N->clamp_cell[k];
         if (cell < 0 || cell >= nc || N->clamp_cv[k] < 0 || N->clamp_cv[k] >= N->cv_off[cell + 1] - N->cv_off[cell]) FAIL("bad clamp");
     }
+    o->pois_t = xcalloc(N->n_pois, 8);
+    o->pois_j = xcalloc(N->n_pois, 8);
+    for (int64_t k = 0; k < N->n_pois; k++) {
+        int32_t s = N->pois_dst[k];
+        if (s < 0 || s >= ns) FAIL("Poisson source %lld: bad target", (long long)k);
+        if ((N->pois_ports[k] & 2) && N->syn_kind[s] != 1) FAIL("calcium port needs a plasticity synapse");
+        if (!(N->pois_rate[k] >= 0)) FAIL("negative rate");
+        o->pois_t[k] = N->pois_rate[k] > 0 ? orc_poisson_isi(N->seed, (uint64_t)k, 0, N->pois_rate[k]) : INFINITY;
+    }
 #undef FAIL
     return o;
 }
@@ -437,6 +468,26 @@ static int orc_step(orc *o) {
     const orc_net *N = &o->net;
     const int64_t n = o->step, nc = N->n_cells, ncv = o->n_cv;
     const double dt = N->dt, tn = (double)n * dt, h0 = N->h0;
+
+    /* Poisson arrivals due in this step enter the queue (their calcium
+       events later) */
+    for (int64_t k = 0; k < N->n_pois; k++) {
+        while (floor(o->pois_t[k] / dt) <= (double)n) {
+            double t = o->pois_t[k];
+            orc_event e = {0};
+            e.src = nc + N->n_trains + k; e.conn = 0; e.syn = N->pois_dst[k]; e.w = N->pois_w[k];
+            if (N->pois_ports[k] & 1) {
+                e.t = t; e.step = (int64_t)floor(t / dt); e.port = 1;
+                if (heap_push(&o->q, e)) { snprintf(o->err, sizeof o->err, "out of memory"); return -1; }
+            }
+            if (N->pois_ports[k] & 2) {
+                e.t = t + N->t_cd; e.step = (int64_t)floor(e.t / dt); e.port = 2;
+                if (heap_push(&o->q, e)) { snprintf(o->err, sizeof o->err, "out of memory"); return -1; }
+            }
+            o->pois_j[k] += 1;
+            o->pois_t[k] = t + orc_poisson_isi(N->seed, (uint64_t)k, (uint64_t)o->pois_j[k], N->pois_rate[k]);
+        }
+    }
 
     /* 1. event delivery, then the post-synaptic hook */
     while (o->q.n > 0 && o->q.v[0].step <= n) {
@@ -650,7 +701,8 @@ void orc_destroy(orc *o) {
     void *ptrs[] = {o->V, o->Vold, o->I, o->G, o->D, o->b, o->cdt, o->gpas, o->gpas_e, o->axial,
                     o->d0, o->scale, o->gparent, o->hh_of, o->cv_cell, o->gm, o->gh, o->gn, o->g, o->c, o->h,
                     o->z, o->decay, o->syn_order, o->cv_syn_off, o->ev_count, o->ev_stepsum, o->p,
-                    o->S, o->post, o->out_off, o->out_conn, o->sp_gid, o->sp_step, o->sp_t, o->q.v};
+                    o->S, o->post, o->out_off, o->out_conn, o->sp_gid, o->sp_step, o->sp_t, o->q.v,
+                    o->pois_t, o->pois_j};
     for (size_t k = 0; k < sizeof ptrs / sizeof ptrs[0]; k++) free(ptrs[k]);
     free(o);
 }

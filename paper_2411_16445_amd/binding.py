@@ -30,7 +30,7 @@ PA_STATE = {"V": 0, "m": 1, "hh": 2, "n": 3, "g": 4, "c": 5, "h": 6, "z": 7, "p"
 
 EXPORTS = [
     "pa_sim_create", "pa_sim_destroy", "pa_set_stream", "pa_set_allocator", "pa_cells_add",
-    "pa_synapses_add", "pa_connect", "pa_trains_add", "pa_clamps_add", "pa_probes_add",
+    "pa_synapses_add", "pa_connect", "pa_trains_add", "pa_poisson_add", "pa_clamps_add", "pa_probes_add",
     "pa_finalize", "pa_advance", "pa_advance_steps", "pa_spikes_count", "pa_spikes_read",
     "pa_probe_count", "pa_probe_read", "pa_state_read", "pa_state_write", "pa_stats_get",
     "pa_kernel_timing", "pa_kernel_time", "pa_last_error", "pa_status_str",
@@ -60,7 +60,8 @@ class pa_cell_params(C.Structure):
 
 class pa_stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("n_cells", "n_cv", "n_syn", "n_stc", "n_conn",
-                                          "n_trains", "n_probes", "steps", "spikes", "events")] + \
+                                          "n_trains", "n_probes", "n_poisson", "steps", "spikes",
+                                          "events")] + \
         [("epoch_steps", C.c_uint32), ("ring_slots", C.c_uint32), ("slot_capacity", C.c_uint32),
          ("cells_per_block", C.c_uint32), ("advance_ms", C.c_double), ("device_bytes", C.c_uint64)]
 
@@ -97,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "pa_synapses_add": (st, [_P, C.c_uint32, _P, _P, _P, _P, _P, C.POINTER(C.c_uint32)]),
         "pa_connect": (st, [_P, C.c_uint64, _P, _P, _P, _P, _P]),
         "pa_trains_add": (st, [_P, C.c_uint32, _P, _P, _P, _P, _P]),
+        "pa_poisson_add": (st, [_P, C.c_uint32, _P, _P, _P, _P]),
         "pa_clamps_add": (st, [_P, C.c_uint32, _P, _P, _P, _P, _P]),
         "pa_probes_add": (st, [_P, C.c_uint32, _P, _P, C.POINTER(C.c_uint32)]),
         "pa_finalize": (st, [_P]),
@@ -247,6 +249,12 @@ class Simulation:
         tt = np.ascontiguousarray(net["train_times"], np.float64)
         if len(td):
             self._check(lib.pa_trains_add(h, len(td), _ptr(td), _ptr(tp), _ptr(tw), _ptr(to), _ptr(tt)))
+        pd = np.ascontiguousarray(net.get("pois_dst", np.zeros(0)), np.uint32)
+        if len(pd):
+            self._check(lib.pa_poisson_add(
+                h, len(pd), _ptr(pd), _ptr(np.ascontiguousarray(net["pois_ports"], np.uint8)),
+                _ptr(np.ascontiguousarray(net["pois_w"], np.float64)),
+                _ptr(np.ascontiguousarray(net["pois_rate"], np.float64))))
         kc = np.ascontiguousarray(net["clamp_cell"], np.uint32)
         if len(kc):
             self._check(lib.pa_clamps_add(

@@ -67,6 +67,9 @@ struct pa_sim {
     std::vector<double> tr_w;
     std::vector<uint64_t> tr_off{0};
     std::vector<double> tr_t;
+    std::vector<uint32_t> po_dst;
+    std::vector<uint8_t> po_ports;
+    std::vector<double> po_w, po_rate;
     std::vector<uint32_t> cl_cell, cl_cv;
     std::vector<double> cl_t0, cl_dur, cl_amp;
     std::vector<int32_t> pr_what;
@@ -364,6 +367,27 @@ pa_status pa_trains_add(pa_sim *s, uint32_t n, const uint32_t *dst, const uint8_
     return PA_OK;
 }
 
+pa_status pa_poisson_add(pa_sim *s, uint32_t n, const uint32_t *dst, const uint8_t *ports, const double *w,
+                         const double *rate) {
+    if (!s) return PA_EINVAL;
+    if (s->state != 0) return fail(s, PA_ESTATE, "Poisson sources cannot be added after pa_finalize");
+    if (n && (!dst || !ports || !w || !rate)) return fail(s, PA_EINVAL, "null array");
+    const uint64_t nsyn = s->syn_cell.size();
+    for (uint32_t k = 0; k < n; ++k) {
+        if (dst[k] >= nsyn) return fail(s, PA_EINVAL, "Poisson source %u: unknown target synapse", k);
+        if (ports[k] == 0 || ports[k] > 3) return fail(s, PA_EINVAL, "Poisson source %u: bad ports", k);
+        if ((ports[k] & PA_PORT_CA) && s->syn_kind[dst[k]] != PA_SYN_STC)
+            return fail(s, PA_EINVAL, "Poisson source %u: calcium port needs a PA_SYN_STC target", k);
+        if (!std::isfinite(w[k]) || !std::isfinite(rate[k]) || rate[k] < 0)
+            return fail(s, PA_EINVAL, "Poisson source %u: weight and rate must be finite, rate >= 0", k);
+    }
+    s->po_dst.insert(s->po_dst.end(), dst, dst + n);
+    s->po_ports.insert(s->po_ports.end(), ports, ports + n);
+    s->po_w.insert(s->po_w.end(), w, w + n);
+    s->po_rate.insert(s->po_rate.end(), rate, rate + n);
+    return PA_OK;
+}
+
 pa_status pa_clamps_add(pa_sim *s, uint32_t n, const uint32_t *gid, const uint32_t *cv, const double *t0,
                         const double *dur, const double *amp) {
     if (!s) return PA_EINVAL;
@@ -594,6 +618,15 @@ pa_status build(pa_sim *s) {
         tr_cell[k] = s->syn_cell[s->tr_dst[k]];
     }
 
+    // ---- Poisson sources
+    const uint32_t npo = (uint32_t)s->po_dst.size();
+    d.n_pois = npo;
+    std::vector<uint32_t> po_syn(npo), po_cell(npo);
+    for (uint32_t k = 0; k < npo; ++k) {
+        po_syn[k] = s->syn_rank[s->po_dst[k]];
+        po_cell[k] = s->syn_cell[s->po_dst[k]];
+    }
+
     // ---- probes: internal indices
     std::vector<uint64_t> pr_idx(d.n_probes);
     for (uint32_t k = 0; k < d.n_probes; ++k) {
@@ -612,6 +645,56 @@ pa_status build(pa_sim *s) {
     d.vdet_old = zeros<double>(s, nc, ok);
     d.post = zeros<uint8_t>(s, nc, ok);
     d.parent = upload(s, gparent, ok);
+    {
+        // run length of parent == predecessor links ending at each CV
+        std::vector<uint16_t> run(ncv, 0);
+        for (uint32_t i = 0; i < ncv; ++i)
+            if (gparent[i] >= 0 && (uint32_t)gparent[i] == i - 1) run[i] = (uint16_t)std::min<uint32_t>(run[i - 1] + 1u, 60000u);
+        d.run = upload(s, run, ok);
+        // branch segments per cell
+        bool too_deep = false;
+        std::vector<uint32_t> nkid(ncv, 0);
+        for (uint32_t i = 0; i < ncv; ++i)
+            if (gparent[i] >= 0) nkid[gparent[i]]++;
+        std::vector<uint32_t> seg_off(nc + 1, 0), seg_a, seg_b, kid_off{0}, kids, seg_of(ncv);
+        std::vector<uint8_t> seg_lvl;
+        for (uint32_t c = 0; c < nc; ++c) {
+            seg_off[c] = (uint32_t)seg_a.size();
+            const uint32_t b0 = cvoff[c], b1 = cvoff[c + 1];
+            for (uint32_t i = b0; i < b1; ++i) {
+                const bool cont = i > b0 && (uint32_t)gparent[i] == i - 1 && nkid[i - 1] == 1;
+                if (!cont) {
+                    seg_a.push_back(i);
+                    seg_b.push_back(i);
+                    const uint32_t lvl = (i == b0) ? 0u : seg_lvl[seg_of[gparent[i]]] + 1u;
+                    seg_lvl.push_back((uint8_t)std::min<uint32_t>(lvl, 255u));
+                    if (lvl > 255) too_deep = true;
+                } else {
+                    seg_b.back() = i;
+                }
+                seg_of[i] = (uint32_t)seg_a.size() - 1;
+            }
+        }
+        seg_off[nc] = (uint32_t)seg_a.size();
+        const uint32_t nseg = (uint32_t)seg_a.size();
+        // children of each segment's bottom node, in descending head index
+        std::vector<std::vector<uint32_t>> ch(nseg);
+        for (uint32_t g = 0; g < nseg; ++g)
+            if (gparent[seg_a[g]] >= 0) ch[seg_of[gparent[seg_a[g]]]].push_back(g);
+        for (uint32_t g = 0; g < nseg; ++g) {
+            std::sort(ch[g].begin(), ch[g].end(), [&](uint32_t x, uint32_t y) { return seg_a[x] > seg_a[y]; });
+            kids.insert(kids.end(), ch[g].begin(), ch[g].end());
+            kid_off.push_back((uint32_t)kids.size());
+        }
+        d.n_seg = nseg;
+        d.seg_off = upload(s, seg_off, ok);
+        d.seg_a = upload(s, seg_a, ok);
+        d.seg_b = upload(s, seg_b, ok);
+        d.seg_lvl = upload(s, seg_lvl, ok);
+        d.kid_off = upload(s, kid_off, ok);
+        d.kids = upload(s, kids, ok);
+        if (too_deep) return fail(s, PA_EINVAL, "a tree is deeper than 255 branch levels");
+    }
     d.cdt = upload(s, cdt, ok);
     d.d0 = upload(s, d0, ok);
     d.gpas_e = upload(s, gpas_e, ok);
@@ -663,6 +746,13 @@ pa_status build(pa_sim *s) {
         for (uint32_t k = 0; k < ntr; ++k) cur[2 * k] = cur[2 * k + 1] = s->tr_off[k];
         d.tr_cur = upload(s, cur, ok);
     }
+    d.pois_syn = upload(s, po_syn, ok);
+    d.pois_cell = upload(s, po_cell, ok);
+    d.pois_ports = upload(s, s->po_ports, ok);
+    d.pois_w = upload(s, s->po_w, ok);
+    d.pois_rate = upload(s, s->po_rate, ok);
+    d.pois_t = zeros<double>(s, npo, ok);
+    d.pois_j = zeros<uint64_t>(s, npo, ok);
     d.cl_t0 = upload(s, clt0, ok);
     d.cl_dur = upload(s, cldur, ok);
     d.cl_amp = upload(s, clamp, ok);
@@ -1020,6 +1110,7 @@ extern "C" pa_status pa_stats_get(const pa_sim *s, pa_stats *o) {
     o->n_conn = s->conn_src.size();
     o->n_trains = s->tr_dst.size();
     o->n_probes = s->pr_what.size();
+    o->n_poisson = s->po_dst.size();
     o->steps = s->step;
     o->spikes = s->sp_gid.size();
     o->epoch_steps = s->d.K;
@@ -1076,6 +1167,7 @@ pa_status pa_snapshot(pa_sim *s, int restore) {
         {d.S, (size_t)d.n_cells * 8}, {d.vdet_old, (size_t)d.n_cells * 8}, {d.post, (size_t)d.n_cells},
         {d.ev_cnt, (size_t)d.n_syn * 16}, {d.ev_sum, (size_t)d.n_syn * 16},
         {d.ev_n, (size_t)d.n_cells * d.R * 4}, {d.tr_cur, (size_t)d.n_trains * 16},
+        {d.pois_t, (size_t)d.n_pois * 8}, {d.pois_j, (size_t)d.n_pois * 8},
         {d.ctr, sizeof(Counters)}};
     size_t total = 0;
     for (const Span &x : spans) total += (x.n + 255) & ~size_t(255);

@@ -74,6 +74,18 @@ __device__ inline double std_normal(uint64_t seed, uint64_t sid, uint64_t n) {
     return (lane & 1) ? r * sin(ang) : r * cos(ang);
 }
 
+constexpr uint64_t POIS_TAG = 0x706f6973736f6e21ull;
+
+// Inter-arrival time (ms) number j of Poisson source k at rate (Hz):
+// -ln(u) / rate, u from the first word of Threefry(counter j, key
+// (seed, k, tag, 0)).
+__device__ inline double poisson_isi(uint64_t seed, uint64_t k, uint64_t j, double rate_hz) {
+    uint64_t x[4];
+    threefry4x64_12(j, 0, 0, 0, seed, k, POIS_TAG, 0, x);
+    const double u = ((double)(x[0] >> 11) + 0.5) * 0x1.0p-53;
+    return -log(u) * (1000.0 / rate_hz);
+}
+
 // --------------------------------------------------------------- HH rates
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
@@ -96,15 +108,41 @@ __device__ __forceinline__ void hh_rates(T v, T r[6]) {
     r[5] = T(0.125) * dexp(-(v + T(65)) / T(80));
 }
 
+// State views: the same device functions update state held in global
+// memory (plain form, base 0) or staged in LDS for an epoch (fused form,
+// base = first index owned by the workgroup).
+template <class T>
+struct GateView {
+    T *m, *h, *n;
+    uint32_t base;
+};
+
+template <class T>
+struct SynView {
+    T *g, *c;
+    double *h, *z;
+    uint32_t base;
+};
+
+// Per-synapse constants (reversal potential, decay factor, kind), global
+// or staged in LDS (base as in SynView).
+template <class T>
+struct SynConst {
+    const double *erev;
+    const T *decay;
+    const uint8_t *kind;
+    uint32_t base;
+};
+
 // Exact exponential integration of the three gates at the new voltage.
 template <class T>
-__device__ inline void gate_update(const DevNet &d, uint32_t k, double vnew) {
-    T *gm = (T *)d.gm, *gh = (T *)d.gh, *gn = (T *)d.gn;
+__device__ inline void gate_update(const DevNet &d, uint32_t k, double vnew, const GateView<T> &gv) {
+    const uint32_t j0 = k - gv.base;
     const T v = (T)vnew;
     const T dt = (T)d.dt;
     T r[6];
     hh_rates<T>(v, r);
-    T *x[3] = {gm + k, gh + k, gn + k};
+    T *x[3] = {gv.m + j0, gv.h + j0, gv.n + j0};
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const T a = r[2 * j], b = r[2 * j + 1];
@@ -146,104 +184,300 @@ __device__ __forceinline__ bool ev_before(const Event &a, const Event &b) {
     return a.port < b.port;
 }
 
-// Applies one event to its synapse.
+// Applies one event (synapse s, port, weight w) to the synapse state.
 template <class T>
-__device__ __forceinline__ void apply_event(const DevNet &d, const Event &e, uint64_t n) {
-    const uint32_t s = e.syn;
-    if (e.port == 1) {
-        T *g = (T *)d.g;
-        if (d.syn_kind[s] == 1) {
+__device__ __forceinline__ void apply_event(const DevNet &d, uint32_t s, uint32_t port, double w,
+                                            const SynView<T> &sv, const SynConst<T> &sc) {
+    const uint32_t j = s - sv.base;
+    if (port == 1) {
+        if (sc.kind[s - sc.base] == 1) {
             const double h0 = d.stc.h0;
-            g[s] = g[s] + (T)(e.w * ((d.h[s] + h0 * d.z[s]) / h0));
+            sv.g[j] = sv.g[j] + (T)(w * ((sv.h[j] + h0 * sv.z[j]) / h0));
         } else {
-            g[s] = g[s] + (T)e.w;
+            sv.g[j] = sv.g[j] + (T)w;
         }
     } else {
-        T *c = (T *)d.c;
-        c[s] = c[s] + (T)d.stc.c_pre;
+        sv.c[j] = sv.c[j] + (T)d.stc.c_pre;
     }
-    d.ev_cnt[2 * s + e.port - 1] += 1ull;
-    d.ev_sum[2 * s + e.port - 1] += (unsigned long long)n;
 }
 
-// Delivers the events of step n of one cell in (t_e, src, conn, port)
-// order, then the post-synaptic hook of a spike in the previous step.
-template <class T>
-__device__ inline void deliver_cell(const DevNet &d, uint32_t cell, uint64_t n) {
-    const uint64_t ring = (uint64_t)cell * d.R + (uint32_t)(n % d.R);
-    uint32_t cnt = d.ev_n[ring];
-    if (cnt) {
-        if (cnt > d.Q) cnt = d.Q;  // overflow was flagged at insertion
-        Event *ev = d.ev + ring * d.Q;
-        // insertion sort in place; slots hold few events
-        for (uint32_t i = 1; i < cnt; ++i) {
-            Event x = ev[i];
-            uint32_t j = i;
-            while (j > 0 && ev_before(x, ev[j - 1])) {
-                ev[j] = ev[j - 1];
-                --j;
-            }
-            ev[j] = x;
+// Sorts the cnt events of a ring slot in place into delivery order.
+__device__ inline void sort_slot(Event *ev, uint32_t cnt) {
+    for (uint32_t i = 1; i < cnt; ++i) {
+        Event x = ev[i];
+        uint32_t j = i;
+        while (j > 0 && ev_before(x, ev[j - 1])) {
+            ev[j] = ev[j - 1];
+            --j;
         }
-        for (uint32_t i = 0; i < cnt; ++i) apply_event<T>(d, ev[i], n);
-        d.ev_n[ring] = 0;
-        atomicAdd((unsigned long long *)&d.ctr->events, (unsigned long long)cnt);
+        ev[j] = x;
     }
-    if (d.post[cell]) {
-        T *c = (T *)d.c;
-        const T cp = (T)d.stc.c_post;
-        for (uint32_t s = d.syn_off[cell]; s < d.syn_off[cell + 1]; ++s)
-            if (d.syn_kind[s] == 1) c[s] = c[s] + cp;
-        d.post[cell] = 0;
+}
+
+// Delivers the cnt events waiting in the ring slot of step n of one cell in
+// (t_e, src, conn, port) order and empties the slot.  The post-synaptic hook
+// is applied with the synapse update (syn_update).
+template <class T>
+__device__ inline void deliver_slot(const DevNet &d, uint32_t cell, uint64_t n, uint32_t cnt,
+                                    const SynView<T> &sv, const SynConst<T> &sc) {
+    const uint64_t ring = (uint64_t)cell * d.R + (uint32_t)(n % d.R);
+    if (cnt > d.Q) cnt = d.Q;  // overflow was flagged at insertion
+    Event *ev = d.ev + ring * d.Q;
+    sort_slot(ev, cnt);
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const Event e = ev[i];
+        apply_event<T>(d, e.syn, e.port, e.w, sv, sc);
+        d.ev_cnt[2 * e.syn + e.port - 1] += 1ull;
+        d.ev_sum[2 * e.syn + e.port - 1] += (unsigned long long)n;
     }
 }
 
 // --------------------------------------------------------------- currents
-// Membrane current (nA, outward positive) and dI/dV (uS) of CV i at V^n:
-// HH, synapses in (CV, id) order, then clamps active at t_n.
+// Membrane current (nA, outward positive) and dI/dV (uS) of one CV at V^n:
+// HH (gate slot k, -1 if none), the CV's synapses q0..q1-1 in (CV, id) order,
+// then its clamps cl0..cl1-1 active at t_n.
+// P: gNa, gK, gL, ENa, EK, EL of the HH slot; sca: 1e-2 x lateral area.
 template <class T>
-__device__ inline void cv_current(const DevNet &d, uint32_t i, double v, double tn, double &Iout,
-                                  double &Gout) {
+__device__ inline void cv_current(const DevNet &d, int32_t k, const double *P, double sca, double v, double tn,
+                                  const GateView<T> &gv, const SynView<T> &sv, const SynConst<T> &sc,
+                                  uint32_t q0, uint32_t q1, uint32_t cl0, uint32_t cl1, double &Iout, double &Gout) {
     double I = 0.0, G = 0.0;
-    const int32_t k = d.hh_of[i];
     if (k >= 0) {
-        const double *P = d.hh_par + 6 * (size_t)k;
-        const double m = (double)((const T *)d.gm)[k];
-        const double hh = (double)((const T *)d.gh)[k];
-        const double nn = (double)((const T *)d.gn)[k];
+        const uint32_t j = (uint32_t)k - gv.base;
+        const double m = (double)gv.m[j];
+        const double hh = (double)gv.h[j];
+        const double nn = (double)gv.n[j];
         const double gna = P[0] * m * m * m * hh;
         const double gk = P[1] * nn * nn * nn * nn;
         const double idens = gna * (v - P[3]) + gk * (v - P[4]) + P[2] * (v - P[5]);
-        const double sc = d.hh_scale[k];
-        I = sc * idens;
-        G = sc * (gna + gk + P[2]);
+        I = sca * idens;
+        G = sca * (gna + gk + P[2]);
     }
-    const T *g = (const T *)d.g;
-    for (uint32_t q = d.cv_syn_off[i]; q < d.cv_syn_off[i + 1]; ++q) {
-        const double gs = (double)g[q];
-        I += gs * (v - d.syn_erev[q]);
+    uint32_t q = q0;
+    for (; q + 4 <= q1; q += 4) {
+        double gs[4], er[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            gs[j] = (double)sv.g[q + j - sv.base];
+            er[j] = sc.erev[q + j - sc.base];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            I += gs[j] * (v - er[j]);
+            G += gs[j];
+        }
+    }
+    for (; q < q1; ++q) {
+        const double gs = (double)sv.g[q - sv.base];
+        I += gs * (v - sc.erev[q - sc.base]);
         G += gs;
     }
-    for (uint32_t q = d.cv_cl_off[i]; q < d.cv_cl_off[i + 1]; ++q) {
+    for (uint32_t q = cl0; q < cl1; ++q) {
         if (d.cl_t0[q] <= tn && tn < d.cl_t0[q] + d.cl_dur[q]) I -= d.cl_amp[q];
     }
     Iout = I;
     Gout = G;
 }
 
+// Orders the LDS accesses of the lanes of one wavefront (a barrier among
+// the wavefront's own lanes).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// --------------------------------------------------------------- cable
+// Quotient x / y.  EXACT: IEEE division (bitwise equal to the sequential
+// CPU elimination).  Otherwise (mixed form) x times a reciprocal refined by
+// two Newton steps from the hardware estimate: FP64 accurate to about one
+// ulp, with a third of the dependent latency.
+template <bool EXACT>
+__device__ __forceinline__ double qdiv(double x, double y) {
+    if constexpr (EXACT) {
+        return x / y;
+    } else {
+        double r = __builtin_amdgcn_rcp(y);
+        double e = fma(-y, r, 1.0);
+        r = fma(e, r, r);
+        e = fma(-y, r, 1.0);
+        r = fma(e, r, r);
+        return x * r;
+    }
+}
+
+// Hines elimination of one cell's tree system in descending index order
+// (parent[i] < i), then substitution in ascending order.  D and B hold the
+// assembled diagonal and right-hand side and are overwritten; V receives the
+// solution.  Indices b0..b1-1 and par[] are in the same index space; run[i]
+// counts the consecutive nodes ending at i whose parent is their
+// predecessor.  Along such runs eight nodes' operands are loaded ahead and
+// the diagonal and right-hand side of the node being eliminated are carried
+// in registers; the floating-point operations and their order are those of
+// the plain elimination.  Returns false if a voltage is not finite.
+template <bool EXACT>
+__device__ inline bool hines_solve(double *D, double *B, double *V, const int32_t *par,
+                                   const double *ax, const uint16_t *run, uint32_t b0, uint32_t b1) {
+    double dc = D[b1 - 1], bc = B[b1 - 1];
+    uint32_t i = b1 - 1;
+    while (i > b0) {
+        if (i >= b0 + 8 && run[i] >= 8) {
+            double U[8], Dp[8], Bp[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                U[j] = -ax[i - j];
+                Dp[j] = D[i - j - 1];
+                Bp[j] = B[i - j - 1];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double f = qdiv<EXACT>(U[j], dc);
+                D[i - j] = dc;
+                B[i - j] = bc;
+                dc = Dp[j] - f * U[j];
+                bc = Bp[j] - f * bc;
+            }
+            i -= 8;
+            continue;
+        }
+        const int32_t p = par[i];
+        const double u = -ax[i];
+        const double f = qdiv<EXACT>(u, dc);
+        D[i] = dc;
+        B[i] = bc;
+        if ((uint32_t)p == i - 1) {
+            dc = D[p] - f * u;
+            bc = B[p] - f * bc;
+        } else {
+            D[p] -= f * u;
+            B[p] -= f * bc;
+            dc = D[i - 1];
+            bc = B[i - 1];
+        }
+        --i;
+    }
+    D[b0] = dc;
+    B[b0] = bc;
+    bool ok = true;
+    double vp = qdiv<EXACT>(bc, dc);
+    V[b0] = vp;
+    ok = ok && isfinite(vp);
+    i = b0 + 1;
+    while (i < b1) {
+        if (i + 8 <= b1 && run[i + 7] >= 8) {
+            double U[8], Dl[8], Bl[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                U[j] = -ax[i + j];
+                Dl[j] = D[i + j];
+                Bl[j] = B[i + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                vp = qdiv<EXACT>(Bl[j] - U[j] * vp, Dl[j]);
+                V[i + j] = vp;
+                ok = ok && isfinite(vp);
+            }
+            i += 8;
+            continue;
+        }
+        const int32_t p = par[i];
+        const double u = -ax[i];
+        const double vpar = ((uint32_t)p == i - 1) ? vp : V[p];
+        vp = qdiv<EXACT>(B[i] - u * vpar, D[i]);
+        V[i] = vp;
+        ok = ok && isfinite(vp);
+        ++i;
+    }
+    return ok;
+}
+
+// Elimination of one unbranched segment [a, b] (every node after a has its
+// predecessor as parent and only child), from the bottom node b, whose
+// diagonal and right-hand side (after its children's contributions) are
+// dc, bc.  Stores every node's final diagonal and right-hand side and
+// returns those of the head a in dc, bc.
+template <bool EXACT>
+__device__ inline void seg_backward(double *D, double *B, const double *ax, uint32_t a, uint32_t b,
+                                    double &dc, double &bc) {
+    uint32_t i = b;
+    while (i >= a + 8) {
+        double U[8], Dp[8], Bp[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            U[j] = -ax[i - j];
+            Dp[j] = D[i - j - 1];
+            Bp[j] = B[i - j - 1];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const double f = qdiv<EXACT>(U[j], dc);
+            D[i - j] = dc;
+            B[i - j] = bc;
+            dc = Dp[j] - f * U[j];
+            bc = Bp[j] - f * bc;
+        }
+        i -= 8;
+    }
+    for (; i > a; --i) {
+        const double u = -ax[i];
+        const double f = qdiv<EXACT>(u, dc);
+        D[i] = dc;
+        B[i] = bc;
+        dc = D[i - 1] - f * u;
+        bc = B[i - 1] - f * bc;
+    }
+    D[a] = dc;
+    B[a] = bc;
+}
+
+// Substitution along an unbranched segment [a, b] given V[a].
+template <bool EXACT>
+__device__ inline bool seg_forward(const double *D, const double *B, double *V, const double *ax,
+                                   uint32_t a, uint32_t b) {
+    double vp = V[a];
+    bool ok = isfinite(vp);
+    uint32_t i = a + 1;
+    while (i + 8 <= b + 1) {
+        double U[8], Dl[8], Bl[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            U[j] = -ax[i + j];
+            Dl[j] = D[i + j];
+            Bl[j] = B[i + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            vp = qdiv<EXACT>(Bl[j] - U[j] * vp, Dl[j]);
+            V[i + j] = vp;
+            ok = ok && isfinite(vp);
+        }
+        i += 8;
+    }
+    for (; i <= b; ++i) {
+        vp = qdiv<EXACT>(B[i] - (-ax[i]) * vp, D[i]);
+        V[i] = vp;
+        ok = ok && isfinite(vp);
+    }
+    return ok;
+}
+
 // --------------------------------------------------------------- synapses
 // Conductance decay, then for tagging-and-capture synapses one step of
-// Eqs. 17-20 from step-start h, z, c and the cell's step-start p.
+// Eqs. 17-20 from step-start h, z, c and the cell's step-start p.  If the
+// cell fired in the previous step, the post-synaptic calcium jump is added
+// first (after this step's events, as in the sequential definition).
+// Returns |h - h0| of step start (0 for plain synapses).
 template <class T>
-__device__ inline void syn_update(const DevNet &d, uint32_t s, uint64_t n, double p) {
-    T *g = (T *)d.g;
-    if constexpr (sizeof(T) == 8) g[s] = g[s] * (T)d.syn_decay[s];
-    else g[s] = g[s] * d.syn_decay_f[s];
-    if (d.syn_kind[s] != 1) return;
-    T *cp = (T *)d.c;
+__device__ inline double syn_update(const DevNet &d, uint32_t s, uint64_t n, double p, bool post,
+                                    const SynView<T> &sv, const SynConst<T> &sc) {
+    const uint32_t j = s - sv.base, jc = s - sc.base;
+    sv.g[j] = sv.g[j] * sc.decay[jc];
+    if (sc.kind[jc] != 1) return 0.0;
     const Stc &P = d.stc;
-    const T c = cp[s];
-    const double h = d.h[s], z = d.z[s], h0 = P.h0;
+    T c = sv.c[j];
+    if (post) c = c + (T)P.c_post;
+    const double h = sv.h[j], z = sv.z[j], h0 = P.h0;
     const double thp = (c - (T)P.theta_p > T(0)) ? 1.0 : 0.0;
     const double thd = (c - (T)P.theta_d > T(0)) ? 1.0 : 0.0;
     const double ah = d.dt / P.tau_h;
@@ -255,31 +489,31 @@ __device__ inline void syn_update(const DevNet &d, uint32_t s, uint64_t n, doubl
     const double tagd = ((h0 - h) - P.theta_tag > 0.0) ? 1.0 : 0.0;
     const double az = d.dt / P.tau_z;
     const double zn = z + az * p * P.f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
-    d.h[s] = hn;
-    d.z[s] = zn;
-    if constexpr (sizeof(T) == 8) cp[s] = c * (T)d.r_c;
-    else cp[s] = c * d.r_c_f;
+    sv.h[j] = hn;
+    sv.z[j] = zn;
+    if constexpr (sizeof(T) == 8) sv.c[j] = c * (T)d.r_c;
+    else sv.c[j] = c * d.r_c_f;
+    return fabs(h - h0);
 }
 
 // --------------------------------------------------------------- cells
-__device__ inline void prp_update(const DevNet &d, uint32_t cell) {
+__device__ inline double prp_next(const DevNet &d, double p, double S) {
     const double ap = d.dt / d.stc.tau_p;
-    const double trig = (d.S[cell] - d.stc.theta_pro > 0.0) ? 1.0 : 0.0;
-    const double p = d.p[cell];
-    d.p[cell] = p + ap * (-p + d.stc.p_max * trig);
+    const double trig = (S - d.stc.theta_pro > 0.0) ? 1.0 : 0.0;
+    return p + ap * (-p + d.stc.p_max * trig);
 }
 
 // Threshold crossing V^n < theta <= V^{n+1}: records the spike with the
-// linearly interpolated time and arms the post-synaptic hook.
-__device__ inline void detect(const DevNet &d, uint32_t cell, uint64_t n, double v0, double v1) {
-    if (!(v0 < d.theta && v1 >= d.theta)) return;
+// linearly interpolated time; returns whether the cell fired.
+__device__ inline bool detect(const DevNet &d, uint32_t cell, uint64_t n, double v0, double v1) {
+    if (!(v0 < d.theta && v1 >= d.theta)) return false;
     const double tn = (double)n * d.dt;
     const double ts = tn + d.dt * ((d.theta - v0) / (v1 - v0));
     const uint32_t pos = atomicAdd(&d.ctr->ep_n, 1u);
     d.ep_gid[pos] = cell;
     d.ep_step[pos] = (uint32_t)n;
     d.ep_t[pos] = ts;
-    d.post[cell] = 1;
+    return true;
 }
 
 }  // namespace pa

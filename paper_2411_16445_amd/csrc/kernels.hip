@@ -32,12 +32,50 @@ __global__ void k_init(DevNet d) {
     ((T *)d.gn)[k] = r[4] / (r[4] + r[5]);
 }
 
+__global__ void k_init_poisson(DevNet d) {
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n_pois) return;
+    d.pois_j[k] = 0;
+    d.pois_t[k] = d.pois_rate[k] > 0.0 ? poisson_isi(d.seed, k, 0, d.pois_rate[k]) : INFINITY;
+}
+
 // ----------------------------------------------------------------- trains
 // At the start of an epoch ending at `epoch_end`, move every train arrival
 // whose delivery step falls before epoch_end into the target cell's ring.
 __global__ void k_inject(DevNet d, uint32_t nsteps) {
     uint32_t tr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tr >= d.n_trains) return;
+    if (tr >= d.n_trains) {
+        // Poisson sources: draw the arrivals due before the epoch's end
+        const uint32_t k = tr - d.n_trains;
+        if (k >= d.n_pois) return;
+        const uint64_t epoch_start = d.ctr->step;
+        const uint64_t epoch_end = epoch_start + nsteps;
+        double t = d.pois_t[k];
+        uint64_t j = d.pois_j[k];
+        const uint32_t cell = d.pois_cell[k];
+        Event e;
+        e.w = d.pois_w[k];
+        e.syn = d.pois_syn[k];
+        e.src = d.n_cells + d.n_trains + k;
+        e.conn = 0;
+        while (floor(t / d.dt) < (double)epoch_end) {
+            if (d.pois_ports[k] & 1) {
+                e.t = t;
+                e.port = 1;
+                push_event(d, cell, (uint64_t)floor(t / d.dt), e, epoch_start);
+            }
+            if (d.pois_ports[k] & 2) {
+                e.t = t + d.stc.t_cd;
+                e.port = 2;
+                push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, epoch_start);
+            }
+            ++j;
+            t = t + poisson_isi(d.seed, k, j, d.pois_rate[k]);
+        }
+        d.pois_t[k] = t;
+        d.pois_j[k] = j;
+        return;
+    }
     const uint32_t cell = d.tr_cell[tr];
     const uint64_t end = d.tr_off[tr + 1];
     const uint64_t epoch_start = d.ctr->step;
@@ -73,12 +111,32 @@ __global__ void k_inject(DevNet d, uint32_t nsteps) {
     }
 }
 
+// ----------------------------------------------------------------- views
+template <class T>
+__device__ __forceinline__ SynView<T> global_syn(const DevNet &d) {
+    return SynView<T>{(T *)d.g, (T *)d.c, d.h, d.z, 0u};
+}
+template <class T>
+__device__ __forceinline__ GateView<T> global_gates(const DevNet &d) {
+    return GateView<T>{(T *)d.gm, (T *)d.gh, (T *)d.gn, 0u};
+}
+template <class T>
+__device__ __forceinline__ SynConst<T> global_const(const DevNet &d) {
+    if constexpr (sizeof(T) == 8) return SynConst<T>{d.syn_erev, (const T *)d.syn_decay, d.syn_kind, 0u};
+    else return SynConst<T>{d.syn_erev, (const T *)d.syn_decay_f, d.syn_kind, 0u};
+}
+
 // ----------------------------------------------------------------- deliver
 template <class T>
 __global__ void k_deliver(DevNet d, uint64_t n) {
     uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= d.n_cells) return;
-    deliver_cell<T>(d, cell, n);
+    const uint64_t ring = (uint64_t)cell * d.R + (uint32_t)(n % d.R);
+    const uint32_t cnt = d.ev_n[ring];
+    if (!cnt) return;
+    deliver_slot<T>(d, cell, n, cnt, global_syn<T>(d), global_const<T>(d));
+    d.ev_n[ring] = 0;
+    atomicAdd((unsigned long long *)&d.ctr->events, (unsigned long long)cnt);
 }
 
 // ----------------------------------------------------------------- currents
@@ -87,14 +145,18 @@ __global__ void k_current(DevNet d, double tn) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.n_cv) return;
     double I, G;
-    cv_current<T>(d, i, d.V[i], tn, I, G);
+    const int32_t hk = d.hh_of[i];
+    const double *P = hk >= 0 ? d.hh_par + 6 * (size_t)hk : nullptr;
+    const double sca = hk >= 0 ? d.hh_scale[hk] : 0.0;
+    cv_current<T>(d, hk, P, sca, d.V[i], tn, global_gates<T>(d), global_syn<T>(d), global_const<T>(d),
+                  d.cv_syn_off[i], d.cv_syn_off[i + 1], d.cv_cl_off[i], d.cv_cl_off[i + 1], I, G);
     d.I[i] = I;
     d.G[i] = G;
 }
 
 // ----------------------------------------------------------------- solve
-// Assembly of the backward-Euler cable system and Hines elimination in
-// descending CV order, one lane per cell.
+// Assembly of the backward-Euler cable system and Hines elimination, one
+// lane per cell.
 __global__ void k_solve(DevNet d) {
     uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= d.n_cells) return;
@@ -106,23 +168,8 @@ __global__ void k_solve(DevNet d) {
         d.D[i] = d.d0[i] + G;
         d.b[i] = ((d.cdt[i] * v + d.gpas_e[i]) - d.I[i]) + G * v;
     }
-    for (uint32_t i = b1 - 1; i > b0; --i) {
-        int32_t p = d.parent[i];
-        double u = -d.axial[i];
-        double f = u / d.D[i];
-        d.D[p] -= f * u;
-        d.b[p] -= f * d.b[i];
-    }
-    bool ok = true;
-    double v0 = d.b[b0] / d.D[b0];
-    d.V[b0] = v0;
-    ok = ok && isfinite(v0);
-    for (uint32_t i = b0 + 1; i < b1; ++i) {
-        double u = -d.axial[i];
-        double v = (d.b[i] - u * d.V[d.parent[i]]) / d.D[i];
-        d.V[i] = v;
-        ok = ok && isfinite(v);
-    }
+    const bool ok = d.mixed ? hines_solve<false>(d.D, d.b, d.V, d.parent, d.axial, d.run, b0, b1)
+                            : hines_solve<true>(d.D, d.b, d.V, d.parent, d.axial, d.run, b0, b1);
     if (!ok) raise_flag(d, FLAG_NONFINITE, cell);
 }
 
@@ -131,7 +178,8 @@ template <class T>
 __global__ void k_cellpre(DevNet d) {
     uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= d.n_cells) return;
-    for (uint32_t k = d.hh_off[cell]; k < d.hh_off[cell + 1]; ++k) gate_update<T>(d, k, d.V[d.hh_cv[k]]);
+    const GateView<T> gv = global_gates<T>(d);
+    for (uint32_t k = d.hh_off[cell]; k < d.hh_off[cell + 1]; ++k) gate_update<T>(d, k, d.V[d.hh_cv[k]], gv);
     const double h0 = d.stc.h0;
     double S = 0.0;
     for (uint32_t s = d.syn_off[cell]; s < d.syn_off[cell + 1]; ++s)
@@ -144,15 +192,16 @@ template <class T>
 __global__ void k_syn(DevNet d, uint64_t n) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.n_syn) return;
-    syn_update<T>(d, s, n, d.p[d.syn_cell[s]]);
+    const uint32_t cell = d.syn_cell[s];
+    (void)syn_update<T>(d, s, n, d.p[cell], d.post[cell] != 0, global_syn<T>(d), global_const<T>(d));
 }
 
 // ----------------------------------------------------------------- cells
 __global__ void k_cellpost(DevNet d, uint64_t n) {
     uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= d.n_cells) return;
-    prp_update(d, cell);
-    detect(d, cell, n, d.vdet_old[cell], d.V[d.det_cv[cell]]);
+    d.p[cell] = prp_next(d, d.p[cell], d.S[cell]);
+    d.post[cell] = detect(d, cell, n, d.vdet_old[cell], d.V[d.det_cv[cell]]) ? 1 : 0;
 }
 
 // ----------------------------------------------------------------- exchange
@@ -241,16 +290,17 @@ static inline dim3 grid_for(uint64_t n, uint32_t block) {
 
 int launch_init(const DevNet &d, void *stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (d.n_hh == 0) return 0;
+    if (d.n_pois) hipLaunchKernelGGL(k_init_poisson, grid_for(d.n_pois, 256), dim3(256), 0, s, d);
+    if (d.n_hh == 0) return (int)hipGetLastError();
     if (d.mixed) hipLaunchKernelGGL(k_init<float>, grid_for(d.n_hh, 256), dim3(256), 0, s, d);
     else hipLaunchKernelGGL(k_init<double>, grid_for(d.n_hh, 256), dim3(256), 0, s, d);
     return (int)hipGetLastError();
 }
 
 int launch_inject(const DevNet &d, uint32_t nsteps, void *stream) {
-    if (d.n_trains == 0) return 0;
-    hipLaunchKernelGGL(k_inject, grid_for(d.n_trains, 256), dim3(256), 0, (hipStream_t)stream, d,
-                       nsteps);
+    if (d.n_trains + d.n_pois == 0) return 0;
+    hipLaunchKernelGGL(k_inject, grid_for((uint64_t)d.n_trains + d.n_pois, 256), dim3(256), 0,
+                       (hipStream_t)stream, d, nsteps);
     return (int)hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "../../include/plasticarbor.h"
@@ -32,118 +33,394 @@
 
 namespace pa {
 
-constexpr uint32_t FUSED_THREADS = 256;
+// LDS layout of a workgroup owning nv CVs, ns synapses, nh HH CVs and nc
+// cells for an epoch of at most K steps; gates, conductance, calcium and
+// decay factors take tsize bytes.  The same arithmetic sizes the launch on
+// the host and places the arrays on the device.
+struct FusedLayout {
+    // doubles
+    uint32_t V, D, B, Ax, D0, Cdt, Gpe, H, Z, Erev, Abs, P, Vold;
+    // T
+    uint32_t G, C, Dec, M, HH, N;
+    // 32-bit
+    uint32_t Par, HHk, CvSyn, CvCl, Cb0, Cs0, Det, HHcv, EvN, EvOff, Scan;
+    // events of the epoch, sorted: {w, syn, port}
+    uint32_t EvBuf, ev_cap;
+    // 16-bit, 8-bit
+    uint32_t SynCell, Run, Kind, Post;
+    // branch segments
+    uint32_t Cu, Cb, SegA, SegB, SegCell, KidOff, Kids, SegLvl;
+    // HH constants: 6 channel parameters and the area factor per HH CV
+    uint32_t HHp;
+    uint32_t total;
+    __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
+                                    uint32_t tsize, uint32_t ng) {
+        uint32_t o = 0;
+        auto take = [&](uint32_t bytes, uint32_t align) {
+            o = (o + align - 1) / align * align;
+            const uint32_t r = o;
+            o += bytes;
+            return r;
+        };
+        V = take(8 * nv, 16); D = take(8 * nv, 8); B = take(8 * nv, 8); Ax = take(8 * nv, 8);
+        D0 = take(8 * nv, 8); Cdt = take(8 * nv, 8); Gpe = take(8 * nv, 8);
+        H = take(8 * ns, 8); Z = take(8 * ns, 8); Erev = take(8 * ns, 8); Abs = take(8 * ns, 8);
+        P = take(8 * nc, 8); Vold = take(8 * nc, 8);
+        G = take(tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
+        M = take(tsize * nh, 8); HH = take(tsize * nh, 8); N = take(tsize * nh, 8);
+        Par = take(4 * nv, 4); HHk = take(4 * nv, 4); CvSyn = take(4 * (nv + 1), 4);
+        CvCl = take(4 * (nv + 1), 4); Cb0 = take(4 * (nc + 1), 4); Cs0 = take(4 * (nc + 1), 4);
+        Det = take(4 * nc, 4); HHcv = take(4 * nh, 4); EvN = take(4 * nc * K, 4);
+        EvOff = take(4 * nc * K, 4); Scan = take(4 * 257, 4);
+        ev_cap = 2 * nc * K + 32;
+        EvBuf = take(16 * ev_cap, 16);
+        Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
+        SynCell = take(2 * ns, 2); Run = take(2 * nv, 2);
+        SegA = take(2 * ng, 2); SegB = take(2 * ng, 2); SegCell = take(2 * ng, 2);
+        KidOff = take(2 * (ng + 1), 2); Kids = take(2 * ng, 2);
+        Kind = take(ns, 1); Post = take(nc, 1); SegLvl = take(ng, 1);
+        total = (o + 15) / 16 * 16;
+    }
+};
 
-// LDS bytes of a workgroup owning nv CVs, ns synapses and nc cells.
-__host__ __device__ inline size_t fused_lds_bytes(uint32_t nv, uint32_t ns, uint32_t nc) {
-    return (size_t)nv * (4 * 8 + 4) + (size_t)ns * 8 + (size_t)nc * 16;
+#ifdef PA_STAGE_TIMING
+// Diagnostic build only: wall-clock ticks per stage summed over workgroups.
+__device__ unsigned long long pa_stage_ticks[8];
+#define STAGE_INIT() uint64_t st_prev_ = wall_clock64(); uint64_t st_acc_[8] = {0, 0, 0, 0, 0, 0, 0, 0}
+#define STAGE_MARK(k_) do { if (tid == 0) { const uint64_t t_ = wall_clock64(); st_acc_[k_] += t_ - st_prev_; st_prev_ = t_; } } while (0)
+#define STAGE_FLUSH() do { if (tid == 0) for (int k_ = 0; k_ < 8; ++k_) atomicAdd(&pa_stage_ticks[k_], (unsigned long long)st_acc_[k_]); } while (0)
+#else
+#define STAGE_INIT() do {} while (0)
+#define STAGE_MARK(k_) do {} while (0)
+#define STAGE_FLUSH() do {} while (0)
+#endif
+
+__device__ __forceinline__ double wave_sum_down(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+    return x;
 }
 
-template <class T>
-__global__ __launch_bounds__(FUSED_THREADS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk,
-                                                         uint32_t nsteps) {
+// One epoch of nsteps (<= K) steps for the cells blk[b] .. blk[b+1]-1 of
+// workgroup b.  Mutable state of those cells (V, gates, g, c, h, z, p, post
+// flag), their constants and the epoch's event counts live in LDS, so a
+// step touches global memory only for events, spikes and rare noise keys.
+template <class T, uint32_t BS>
+__global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk,
+                                              const uint32_t *__restrict__ blk_lvl, uint32_t nsteps) {
     extern __shared__ double lds[];
-    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    uint8_t *L = (uint8_t *)lds;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    constexpr uint32_t NW = BS / 64;
     const uint32_t c0 = blk[blockIdx.x], c1 = blk[blockIdx.x + 1];
     const uint32_t ncb = c1 - c0;
     const uint32_t v0 = d.cv_off[c0], nv = d.cv_off[c1] - v0;
     const uint32_t s0 = d.syn_off[c0], ns = d.syn_off[c1] - s0;
     const uint32_t k0 = d.hh_off[c0], nhh = d.hh_off[c1] - k0;
-    double *sV = lds;
-    double *sD = sV + nv;
-    double *sB = sD + nv;
-    double *sAx = sB + nv;
-    double *sAbs = sAx + nv;
-    double *sP = sAbs + ns;
-    double *sVold = sP + ncb;
-    int32_t *sPar = (int32_t *)(sVold + ncb);
-
-    for (uint32_t i = tid; i < nv; i += nt) {
-        sV[i] = d.V[v0 + i];
-        sAx[i] = d.axial[v0 + i];
-        const int32_t p = d.parent[v0 + i];
-        sPar[i] = p < 0 ? -1 : p - (int32_t)v0;
-    }
-    for (uint32_t c = tid; c < ncb; c += nt) sP[c] = d.p[c0 + c];
+    const uint32_t g0 = d.seg_off[c0], ng = d.seg_off[c1] - g0;
+    const uint32_t nlev = blk_lvl[blockIdx.x];
+    const uint32_t K = d.K;
+    constexpr bool EXACT = sizeof(T) == 8;
+    const FusedLayout lay(nv, ns, nhh, ncb, K, sizeof(T), ng);
+    double *sV = (double *)(L + lay.V), *sD = (double *)(L + lay.D), *sB = (double *)(L + lay.B);
+    double *sAx = (double *)(L + lay.Ax), *sD0 = (double *)(L + lay.D0), *sCdt = (double *)(L + lay.Cdt);
+    double *sGpe = (double *)(L + lay.Gpe), *sH = (double *)(L + lay.H), *sZ = (double *)(L + lay.Z);
+    double *sErev = (double *)(L + lay.Erev), *sAbs = (double *)(L + lay.Abs);
+    double *sP = (double *)(L + lay.P), *sVold = (double *)(L + lay.Vold);
+    T *sG = (T *)(L + lay.G), *sC = (T *)(L + lay.C), *sDec = (T *)(L + lay.Dec);
+    T *sM = (T *)(L + lay.M), *sHH = (T *)(L + lay.HH), *sN = (T *)(L + lay.N);
+    int32_t *sPar = (int32_t *)(L + lay.Par), *sHHk = (int32_t *)(L + lay.HHk);
+    uint32_t *sCvSyn = (uint32_t *)(L + lay.CvSyn), *sCvCl = (uint32_t *)(L + lay.CvCl);
+    uint32_t *sCb0 = (uint32_t *)(L + lay.Cb0), *sCs0 = (uint32_t *)(L + lay.Cs0);
+    uint32_t *sDet = (uint32_t *)(L + lay.Det), *sHHcv = (uint32_t *)(L + lay.HHcv);
+    uint32_t *sEvN = (uint32_t *)(L + lay.EvN), *sEvOff = (uint32_t *)(L + lay.EvOff);
+    uint32_t *sScan = (uint32_t *)(L + lay.Scan);
+    uint16_t *sSynCell = (uint16_t *)(L + lay.SynCell), *sRun = (uint16_t *)(L + lay.Run);
+    uint8_t *sKind = L + lay.Kind, *sPost = L + lay.Post, *sSegLvl = L + lay.SegLvl;
+    double *sCu = (double *)(L + lay.Cu), *sCb = (double *)(L + lay.Cb), *sHHp = (double *)(L + lay.HHp);
+    uint16_t *sSegA = (uint16_t *)(L + lay.SegA), *sSegB = (uint16_t *)(L + lay.SegB);
+    uint16_t *sSegCell = (uint16_t *)(L + lay.SegCell), *sKidOff = (uint16_t *)(L + lay.KidOff);
+    uint16_t *sKids = (uint16_t *)(L + lay.Kids);
+    const SynView<T> sv{sG, sC, sH, sZ, s0};
+    const SynConst<T> sc{sErev, sDec, sKind, s0};
+    const GateView<T> gv{sM, sHH, sN, k0};
     const uint64_t n0 = d.ctr->step;
-    const double h0 = d.stc.h0;
+    STAGE_INIT();
+
+    // ---- stage in: state, constants, this epoch's events
+    for (uint32_t i = tid; i < nv; i += BS) {
+        const uint32_t g = v0 + i;
+        sV[i] = d.V[g];
+        sAx[i] = d.axial[g];
+        sD0[i] = d.d0[g];
+        sCdt[i] = d.cdt[g];
+        sGpe[i] = d.gpas_e[g];
+        const int32_t p = d.parent[g];
+        sPar[i] = p < 0 ? -1 : p - (int32_t)v0;
+        sRun[i] = d.run[g];
+        sHHk[i] = d.hh_of[g];
+        sCvSyn[i] = d.cv_syn_off[g];
+        sCvCl[i] = d.cv_cl_off[g];
+        if (i == nv - 1) {
+            sCvSyn[nv] = d.cv_syn_off[g + 1];
+            sCvCl[nv] = d.cv_cl_off[g + 1];
+        }
+    }
+    for (uint32_t s = tid; s < ns; s += BS) {
+        const uint32_t q = s0 + s;
+        sG[s] = ((const T *)d.g)[q];
+        sC[s] = ((const T *)d.c)[q];
+        sH[s] = d.h[q];
+        sZ[s] = d.z[q];
+        sErev[s] = d.syn_erev[q];
+        if constexpr (sizeof(T) == 8) sDec[s] = (T)d.syn_decay[q];
+        else sDec[s] = d.syn_decay_f[q];
+        sKind[s] = d.syn_kind[q];
+        sSynCell[s] = (uint16_t)(d.syn_cell[q] - c0);
+    }
+    for (uint32_t k = tid; k < nhh; k += BS) {
+        sM[k] = ((const T *)d.gm)[k0 + k];
+        sHH[k] = ((const T *)d.gh)[k0 + k];
+        sN[k] = ((const T *)d.gn)[k0 + k];
+        sHHcv[k] = d.hh_cv[k0 + k] - v0;
+        for (int j = 0; j < 6; ++j) sHHp[7 * k + j] = d.hh_par[6 * (size_t)(k0 + k) + j];
+        sHHp[7 * k + 6] = d.hh_scale[k0 + k];
+    }
+    for (uint32_t c = tid; c <= ncb; c += BS) {
+        sCb0[c] = d.cv_off[c0 + c] - v0;
+        sCs0[c] = d.syn_off[c0 + c] - s0;
+        if (c < ncb) {
+            sP[c] = d.p[c0 + c];
+            sPost[c] = d.post[c0 + c];
+            sDet[c] = d.det_cv[c0 + c] - v0;
+        }
+    }
+    for (uint32_t g = tid; g < ng; g += BS) {
+        sSegA[g] = (uint16_t)(d.seg_a[g0 + g] - v0);
+        sSegB[g] = (uint16_t)(d.seg_b[g0 + g] - v0);
+        sSegLvl[g] = d.seg_lvl[g0 + g];
+        const uint32_t k0g = d.kid_off[g0];
+        sKidOff[g] = (uint16_t)(d.kid_off[g0 + g] - k0g);
+        if (g == ng - 1) sKidOff[ng] = (uint16_t)(d.kid_off[g0 + ng] - k0g);
+        for (uint32_t q = d.kid_off[g0 + g]; q < d.kid_off[g0 + g + 1]; ++q) sKids[q - k0g] = (uint16_t)(d.kids[q] - g0);
+    }
+    for (uint32_t c = tid; c < ncb; c += BS)
+        for (uint32_t g = d.seg_off[c0 + c]; g < d.seg_off[c0 + c + 1]; ++g) sSegCell[g - g0] = (uint16_t)c;
+    // events of the epoch: counts per (cell, step) slot, an exclusive scan
+    // over the slots, then each slot sorted into delivery order and copied
+    // to LDS (slots beyond the LDS buffer stay in the ring, sorted); the
+    // delivery statistics are counted here, in parallel
+    const uint32_t nslot = ncb * nsteps;
+    const uint32_t chunk = (nslot + BS - 1) / BS;
+    uint32_t part = 0;
+    for (uint32_t x = tid * chunk; x < min(nslot, (tid + 1) * chunk); ++x) {
+        const uint32_t c = x / nsteps, st = x - c * nsteps;
+        const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
+        const uint32_t cnt = min(d.ev_n[ring], d.Q);
+        sEvN[c * K + st] = cnt;
+        part += cnt;
+    }
+    sScan[tid] = part;
     __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (uint32_t t = 0; t < BS; ++t) {
+            const uint32_t v = sScan[t];
+            sScan[t] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t off = sScan[tid];
+        for (uint32_t x = tid * chunk; x < min(nslot, (tid + 1) * chunk); ++x) {
+            const uint32_t c = x / nsteps, st = x - c * nsteps;
+            const uint32_t cnt = sEvN[c * K + st];
+            sEvOff[c * K + st] = (off + cnt <= lay.ev_cap) ? off : 0xffffffffu;
+            off += cnt;
+        }
+    }
+    __syncthreads();
+    for (uint32_t x = tid; x < nslot; x += BS) {
+        const uint32_t c = x / nsteps, st = x - c * nsteps;
+        const uint32_t cnt = sEvN[c * K + st];
+        const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
+        d.ev_n[ring] = 0;
+        if (!cnt) continue;
+        Event *ev = d.ev + ring * d.Q;
+        sort_slot(ev, cnt);
+        const uint32_t off = sEvOff[c * K + st];
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const Event e = ev[i];
+            if (off != 0xffffffffu) {
+                double *rec = (double *)(L + lay.EvBuf) + 2 * (size_t)(off + i);
+                rec[0] = e.w;
+                ((uint32_t *)(rec + 1))[0] = e.syn;
+                ((uint32_t *)(rec + 1))[1] = e.port;
+            }
+            atomicAdd(&d.ev_cnt[2 * e.syn + e.port - 1], 1ull);
+            atomicAdd(&d.ev_sum[2 * e.syn + e.port - 1], (unsigned long long)(n0 + st));
+        }
+    }
+    unsigned long long delivered = 0;
+    __syncthreads();
+    STAGE_MARK(6);
 
     for (uint32_t st = 0; st < nsteps; ++st) {
         const uint64_t n = n0 + st;
         const double tn = (double)n * d.dt;
-        // A. events due at step n, then the post-synaptic hook
-        for (uint32_t c = tid; c < ncb; c += nt) deliver_cell<T>(d, c0 + c, n);
+        // A. events due at step n, already in delivery order
+        for (uint32_t c = tid; c < ncb; c += BS) {
+            const uint32_t cnt = sEvN[c * K + st];
+            if (!cnt) continue;
+            const uint32_t off = sEvOff[c * K + st];
+            if (off != 0xffffffffu) {
+                const double *rec = (const double *)(L + lay.EvBuf) + 2 * (size_t)off;
+                for (uint32_t i = 0; i < cnt; ++i, rec += 2) {
+                    const uint32_t *u = (const uint32_t *)(rec + 1);
+                    apply_event<T>(d, u[0], u[1], rec[0], sv, sc);
+                }
+            } else {
+                const Event *ev = d.ev + ((uint64_t)(c0 + c) * d.R + (uint32_t)(n % d.R)) * d.Q;
+                for (uint32_t i = 0; i < cnt; ++i) apply_event<T>(d, ev[i].syn, ev[i].port, ev[i].w, sv, sc);
+            }
+            delivered += cnt;
+        }
         __syncthreads();
+        STAGE_MARK(0);
         // B. currents at V^n and assembly of the cable system
-        for (uint32_t i = tid; i < nv; i += nt) {
+        for (uint32_t i = tid; i < nv; i += BS) {
             const double v = sV[i];
             double I, G;
-            cv_current<T>(d, v0 + i, v, tn, I, G);
-            sD[i] = d.d0[v0 + i] + G;
-            sB[i] = ((d.cdt[v0 + i] * v + d.gpas_e[v0 + i]) - I) + G * v;
+            const int32_t hk = sHHk[i];
+            const double *P = hk >= 0 ? sHHp + 7 * (hk - (int32_t)k0) : nullptr;
+            cv_current<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, sv, sc, sCvSyn[i], sCvSyn[i + 1], sCvCl[i],
+                          sCvCl[i + 1], I, G);
+            sD[i] = sD0[i] + G;
+            sB[i] = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
         }
         __syncthreads();
-        // C. Hines elimination, one lane per cell
-        for (uint32_t c = tid; c < ncb; c += nt) {
-            const uint32_t b0 = d.cv_off[c0 + c] - v0, b1 = d.cv_off[c0 + c + 1] - v0;
-            sVold[c] = sV[d.det_cv[c0 + c] - v0];
-            for (uint32_t i = b1 - 1; i > b0; --i) {
-                const int32_t p = sPar[i];
-                const double u = -sAx[i];
-                const double f = u / sD[i];
-                sD[p] -= f * u;
-                sB[p] -= f * sB[i];
+        STAGE_MARK(1);
+        // C. Hines elimination on wavefront 0, level-scheduled over branch
+        //    segments: the segments of one level are eliminated in parallel
+        //    lanes, deepest level first; a branch point takes its children's
+        //    contributions in descending child order, as in the sequential
+        //    elimination.  Meanwhile the other wavefronts update the synapses
+        //    (decay, post-synaptic hook, plasticity from step-start values),
+        //    which do not depend on the new voltage.
+        if (wave == 0) {
+            for (uint32_t c = lane; c < ncb; c += 64) sVold[c] = sV[sDet[c]];
+            for (int lv = (int)nlev - 1; lv >= 0; --lv) {
+                for (uint32_t g = lane; g < ng; g += 64) {
+                    if (sSegLvl[g] != (uint32_t)lv) continue;
+                    const uint32_t a = sSegA[g], b = sSegB[g];
+                    double dc = sD[b], bc = sB[b];
+                    for (uint32_t q = sKidOff[g]; q < sKidOff[g + 1]; ++q) {
+                        const uint32_t kd = sKids[q];
+                        dc -= sCu[kd];
+                        bc -= sCb[kd];
+                    }
+                    seg_backward<EXACT>(sD, sB, sAx, a, b, dc, bc);
+                    if (sPar[a] >= 0) {
+                        const double u = -sAx[a];
+                        const double f = qdiv<EXACT>(u, dc);
+                        sCu[g] = f * u;
+                        sCb[g] = f * bc;
+                    }
+                }
+                wave_sync();
             }
-            bool ok = true;
-            const double vr = sB[b0] / sD[b0];
-            sV[b0] = vr;
-            ok = ok && isfinite(vr);
-            for (uint32_t i = b0 + 1; i < b1; ++i) {
-                const double u = -sAx[i];
-                const double v = (sB[i] - u * sV[sPar[i]]) / sD[i];
-                sV[i] = v;
-                ok = ok && isfinite(v);
+            for (uint32_t lv = 0; lv < nlev; ++lv) {
+                for (uint32_t g = lane; g < ng; g += 64) {
+                    if (sSegLvl[g] != lv) continue;
+                    const uint32_t a = sSegA[g], b = sSegB[g];
+                    const int32_t p = sPar[a];
+                    sV[a] = (p < 0) ? qdiv<EXACT>(sB[a], sD[a]) : qdiv<EXACT>(sB[a] - (-sAx[a]) * sV[p], sD[a]);
+                    if (!seg_forward<EXACT>(sD, sB, sV, sAx, a, b)) raise_flag(d, FLAG_NONFINITE, c0 + sSegCell[g]);
+                }
+                wave_sync();
             }
-            if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + c);
+        }
+        {
+            // synapses on wavefronts 1.. (all lanes when there is one wavefront)
+            const uint32_t first = NW > 1 ? 64u : 0u;
+            if (tid >= first) {
+                for (uint32_t s = tid - first; s < ns; s += BS - first) {
+                    const uint32_t cl = sSynCell[s];
+                    sAbs[s] = syn_update<T>(d, s0 + s, n, sP[cl], sPost[cl] != 0, sv, sc);
+                }
+            }
         }
         __syncthreads();
-        // D. gates at V^{n+1}; synapses (decay, plasticity from step-start
-        //    values); |h - h0| of step start for the protein trigger
-        for (uint32_t k = tid; k < nhh; k += nt) gate_update<T>(d, k0 + k, sV[d.hh_cv[k0 + k] - v0]);
-        for (uint32_t s = tid; s < ns; s += nt) {
-            const uint32_t q = s0 + s;
-            sAbs[s] = (d.syn_kind[q] == 1) ? fabs(d.h[q] - h0) : 0.0;
-            syn_update<T>(d, q, n, sP[d.syn_cell[q] - c0]);
-        }
-        __syncthreads();
-        // E. protein synthesis and threshold detection, one lane per cell
-        for (uint32_t c = tid; c < ncb; c += nt) {
+        STAGE_MARK(2);
+        // D. gates at V^{n+1}
+        for (uint32_t k = tid; k < nhh; k += BS) gate_update<T>(d, k0 + k, sV[sHHcv[k]], gv);
+        STAGE_MARK(3);
+        // E. protein trigger sum (one wavefront per cell: strided lane sums,
+        //    then a fixed shuffle tree), protein synthesis, detection
+        for (uint32_t c = wave; c < ncb; c += NW) {
+            const uint32_t a = sCs0[c], e = sCs0[c + 1];
             double S = 0.0;
-            for (uint32_t s = d.syn_off[c0 + c] - s0; s < d.syn_off[c0 + c + 1] - s0; ++s) S += sAbs[s];
-            const double ap = d.dt / d.stc.tau_p;
-            const double trig = (S - d.stc.theta_pro > 0.0) ? 1.0 : 0.0;
-            const double p = sP[c];
-            sP[c] = p + ap * (-p + d.stc.p_max * trig);
-            detect(d, c0 + c, n, sVold[c], sV[d.det_cv[c0 + c] - v0]);
+            for (uint32_t s = a + lane; s < e; s += 64) S += sAbs[s];
+            S = wave_sum_down(S);
+            if (lane == 0) {
+                sP[c] = prp_next(d, sP[c], S);
+                sPost[c] = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]) ? 1 : 0;
+            }
         }
         __syncthreads();
+        STAGE_MARK(4);
     }
-    for (uint32_t i = tid; i < nv; i += nt) d.V[v0 + i] = sV[i];
-    for (uint32_t c = tid; c < ncb; c += nt) d.p[c0 + c] = sP[c];
+    // ---- stage out
+    for (uint32_t i = tid; i < nv; i += BS) d.V[v0 + i] = sV[i];
+    for (uint32_t s = tid; s < ns; s += BS) {
+        ((T *)d.g)[s0 + s] = sG[s];
+        ((T *)d.c)[s0 + s] = sC[s];
+        d.h[s0 + s] = sH[s];
+        d.z[s0 + s] = sZ[s];
+    }
+    for (uint32_t k = tid; k < nhh; k += BS) {
+        ((T *)d.gm)[k0 + k] = sM[k];
+        ((T *)d.gh)[k0 + k] = sHH[k];
+        ((T *)d.gn)[k0 + k] = sN[k];
+    }
+    for (uint32_t c = tid; c < ncb; c += BS) {
+        d.p[c0 + c] = sP[c];
+        d.post[c0 + c] = sPost[c];
+    }
+    if (delivered) atomicAdd((unsigned long long *)&d.ctr->events, delivered);
+    __syncthreads();
+    STAGE_MARK(5);
+    STAGE_FLUSH();
 }
 
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, uint32_t n_blocks,
-                       size_t lds_bytes, void *stream) {
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, const uint32_t *blk_lvl,
+                       uint32_t n_blocks, size_t lds_bytes, uint32_t block_threads, void *stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (d.mixed)
-        hipLaunchKernelGGL(k_epoch<float>, dim3(n_blocks), dim3(FUSED_THREADS), lds_bytes, s, d, blk, nsteps);
-    else
-        hipLaunchKernelGGL(k_epoch<double>, dim3(n_blocks), dim3(FUSED_THREADS), lds_bytes, s, d, blk, nsteps);
+    if (block_threads == 64) {
+        if (d.mixed) hipLaunchKernelGGL((k_epoch<float, 64>), dim3(n_blocks), dim3(64), lds_bytes, s, d, blk, blk_lvl, nsteps);
+        else hipLaunchKernelGGL((k_epoch<double, 64>), dim3(n_blocks), dim3(64), lds_bytes, s, d, blk, blk_lvl, nsteps);
+    } else {
+        if (d.mixed) hipLaunchKernelGGL((k_epoch<float, 256>), dim3(n_blocks), dim3(256), lds_bytes, s, d, blk, blk_lvl, nsteps);
+        else hipLaunchKernelGGL((k_epoch<double, 256>), dim3(n_blocks), dim3(256), lds_bytes, s, d, blk, blk_lvl, nsteps);
+    }
     return (int)hipGetLastError();
 }
 
 }  // namespace pa
+
+#ifdef PA_STAGE_TIMING
+extern "C" int pa_debug_stage_ticks(unsigned long long *out, int reset) {
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(pa::pa_stage_ticks), 8 * sizeof(unsigned long long)) != hipSuccess)
+        return -1;
+    if (reset) {
+        unsigned long long z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(pa::pa_stage_ticks), z, sizeof z) != hipSuccess) return -1;
+    }
+    return 0;
+}
+#endif
 
 // ======================================================================
 // Host side of the batched form.
@@ -158,9 +435,11 @@ pa_status pa_snapshot(pa_sim *s, int restore);
 
 struct BatchedPlan {
     std::vector<uint32_t> blk;  // cell boundaries, n_blocks + 1
-    uint32_t *d_blk = nullptr;
+    std::vector<uint32_t> lvl;  // branch levels per block
+    uint32_t *d_blk = nullptr, *d_lvl = nullptr;
     size_t lds = 0;
     uint32_t cells_per_block = 0;
+    uint32_t threads = 256;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t graph_epochs = 0;
@@ -170,23 +449,32 @@ BatchedPlan *&pa_plan(pa_sim *s);
 
 namespace {
 
-constexpr size_t LDS_BUDGET = 64 * 1024;   // per workgroup: 2 resident per CU
 constexpr size_t LDS_MAX = 160 * 1024;
 
-// Packs consecutive cells, at most cpb per workgroup, within the LDS budget.
-bool pack(const std::vector<uint32_t> &cv_off, const std::vector<uint32_t> &syn_off, uint32_t cpb,
-          std::vector<uint32_t> &blk, size_t &lds) {
-    const uint32_t nc = (uint32_t)cv_off.size() - 1;
+struct Offsets {
+    std::vector<uint32_t> cv, syn, hh, seg, nlev;  // nlev: branch levels per cell
+    uint32_t tsize, K;
+};
+
+// Packs consecutive cells, at most cpb per workgroup, within an LDS budget
+// that leaves room for several resident workgroups per CU.
+bool pack(const Offsets &o, uint32_t cpb, uint32_t threads, std::vector<uint32_t> &blk, size_t &lds) {
+    const size_t budget = threads == 64 ? 32 * 1024 : 64 * 1024;
+    const uint32_t nc = (uint32_t)o.cv.size() - 1;
+    auto bytes = [&](uint32_t a, uint32_t e) {
+        return (size_t)FusedLayout(o.cv[e] - o.cv[a], o.syn[e] - o.syn[a], o.hh[e] - o.hh[a], e - a, o.K,
+                                   o.tsize, o.seg[e] - o.seg[a]).total;
+    };
     blk.assign(1, 0);
     lds = 0;
     uint32_t c = 0;
     while (c < nc) {
         uint32_t e = c + 1;
-        size_t b = fused_lds_bytes(cv_off[e] - cv_off[c], syn_off[e] - syn_off[c], 1);
+        size_t b = bytes(c, e);
         if (b > LDS_MAX) return false;
-        while (e < nc && e - c < cpb) {
-            size_t b2 = fused_lds_bytes(cv_off[e + 1] - cv_off[c], syn_off[e + 1] - syn_off[c], e + 1 - c);
-            if (b2 > LDS_BUDGET) break;
+        while (e < nc && e - c < cpb && e - c < 65535) {
+            size_t b2 = bytes(c, e + 1);
+            if (b2 > budget) break;
             b = b2;
             ++e;
         }
@@ -197,10 +485,15 @@ bool pack(const std::vector<uint32_t> &cv_off, const std::vector<uint32_t> &syn_
     return true;
 }
 
-pa_status upload_plan(pa_sim *s, BatchedPlan &P) {
+pa_status upload_plan(pa_sim *s, BatchedPlan &P, const Offsets &o) {
+    P.lvl.assign(P.blk.size() - 1, 1);
+    for (size_t b = 0; b + 1 < P.blk.size(); ++b)
+        for (uint32_t c = P.blk[b]; c < P.blk[b + 1]; ++c) P.lvl[b] = std::max(P.lvl[b], o.nlev[c]);
     P.d_blk = (uint32_t *)pa_dev_alloc(s, P.blk.size() * 4);
-    if (!P.d_blk) return pa_fail(s, PA_ENOMEM, "block table");
-    if (hipMemcpy(P.d_blk, P.blk.data(), P.blk.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    P.d_lvl = (uint32_t *)pa_dev_alloc(s, P.lvl.size() * 4);
+    if (!P.d_blk || !P.d_lvl) return pa_fail(s, PA_ENOMEM, "block table");
+    if (hipMemcpy(P.d_blk, P.blk.data(), P.blk.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P.d_lvl, P.lvl.data(), P.lvl.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         return pa_fail(s, PA_EDEVICE, "block table upload");
     return PA_OK;
 }
@@ -209,7 +502,7 @@ int enqueue_epoch(const DevNet &d, const BatchedPlan &P, uint32_t nsteps, hipStr
                   hipEvent_t e0, hipEvent_t e1) {
     int r = launch_inject(d, nsteps, st);
     if (e0) (void)hipEventRecord(e0, st);
-    r |= launch_epoch_fused(d, nsteps, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, st);
+    r |= launch_epoch_fused(d, nsteps, P.d_blk, P.d_lvl, (uint32_t)P.blk.size() - 1, P.lds, P.threads, st);
     if (e1) (void)hipEventRecord(e1, st);
     r |= launch_expand(d, nsteps, st);
     return r;
@@ -223,28 +516,47 @@ pa_status batched_setup(pa_sim *s) {
     BatchedPlan *&plan = pa_plan(s);
     plan = new BatchedPlan();
     // host copies of the offsets for packing
-    std::vector<uint32_t> cv_off(d.n_cells + 1), syn_off(d.n_cells + 1);
-    if (hipMemcpy(cv_off.data(), d.cv_off, cv_off.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(syn_off.data(), d.syn_off, syn_off.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    Offsets o;
+    o.cv.resize(d.n_cells + 1);
+    o.syn.resize(d.n_cells + 1);
+    o.hh.resize(d.n_cells + 1);
+    o.tsize = d.mixed ? 4 : 8;
+    o.K = d.K;
+    o.seg.resize(d.n_cells + 1);
+    o.nlev.assign(d.n_cells, 1);
+    {
+        std::vector<uint8_t> lvl(d.n_seg);
+        if (hipMemcpy(o.seg.data(), d.seg_off, o.seg.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            (d.n_seg && hipMemcpy(lvl.data(), d.seg_lvl, d.n_seg, hipMemcpyDeviceToHost) != hipSuccess))
+            return pa_fail(s, PA_EDEVICE, "segments");
+        for (uint32_t c = 0; c < d.n_cells; ++c)
+            for (uint32_t g = o.seg[c]; g < o.seg[c + 1]; ++g) o.nlev[c] = std::max<uint32_t>(o.nlev[c], lvl[g] + 1u);
+    }
+    if (hipMemcpy(o.cv.data(), d.cv_off, o.cv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(o.syn.data(), d.syn_off, o.syn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(o.hh.data(), d.hh_off, o.hh.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
         return pa_fail(s, PA_EDEVICE, "offsets");
-    std::vector<uint32_t> cands;
+    struct Cand { uint32_t threads, cpb; };
+    std::vector<Cand> cands;
     const uint32_t fixed = pa_cfg(s).cells_per_block;
-    if (fixed) cands.push_back(fixed);
-    else
-        for (uint32_t c : {1u, 2u, 4u, 8u, 16u, 32u, 64u})
-            if (c <= std::max<uint32_t>(1, d.n_cells)) cands.push_back(c);
+    if (fixed) cands.push_back({fixed >= 4 ? 256u : 64u, fixed});
+    else {
+        for (uint32_t c : {1u, 2u, 4u}) cands.push_back({64u, c});
+        for (uint32_t c : {4u, 8u, 16u, 32u, 64u}) cands.push_back({256u, c});
+    }
     double best_ms = INFINITY;
-    uint32_t best = 0;
+    Cand best{0, 0};
     const bool tune = cands.size() > 1;
     if (tune && pa_snapshot(s, 0) != PA_OK) return PA_EDEVICE;
-    for (uint32_t cpb : cands) {
+    for (const Cand &cd : cands) {
         BatchedPlan P;
-        if (!pack(cv_off, syn_off, cpb, P.blk, P.lds)) continue;
+        P.threads = cd.threads;
+        if (!pack(o, cd.cpb, cd.threads, P.blk, P.lds)) continue;
         if (!tune) {
-            best = cpb;
+            best = cd;
             break;
         }
-        if (upload_plan(s, P) != PA_OK) return PA_EDEVICE;
+        if (upload_plan(s, P, o) != PA_OK) return PA_EDEVICE;
         // trial: 1 warm epoch, then time 4 epochs of K steps
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
@@ -258,16 +570,20 @@ pa_status batched_setup(pa_sim *s) {
         (void)hipEventElapsedTime(&ms, a, b);
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
+        if (getenv("PA_AUTOTUNE_VERBOSE"))
+            fprintf(stderr, "[autotune] threads %u cells/block %u blocks %zu lds %zu: %.3f ms / 4 epochs\n",
+                    cd.threads, cd.cpb, P.blk.size() - 1, P.lds, ms);
         if (ms < best_ms) {
             best_ms = ms;
-            best = cpb;
+            best = cd;
         }
         if (pa_snapshot(s, 1) != PA_OK) return PA_EDEVICE;
     }
-    if (!best) return pa_fail(s, PA_EINVAL, "a cell does not fit the LDS of one workgroup");
-    plan->cells_per_block = best;
-    pack(cv_off, syn_off, best, plan->blk, plan->lds);
-    if (upload_plan(s, *plan) != PA_OK) return PA_EDEVICE;
+    if (!best.cpb) return pa_fail(s, PA_EINVAL, "a cell does not fit the LDS of one workgroup");
+    plan->cells_per_block = best.cpb;
+    plan->threads = best.threads;
+    pack(o, best.cpb, best.threads, plan->blk, plan->lds);
+    if (upload_plan(s, *plan, o) != PA_OK) return PA_EDEVICE;
     // graph of G full epochs
     plan->graph_epochs = 8;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)

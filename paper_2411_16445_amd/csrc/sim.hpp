@@ -62,6 +62,15 @@ struct DevNet {
 
     // CVs
     const int32_t *parent;       // global parent, -1 at roots
+    const uint16_t *run;         // consecutive nodes ending here whose parent is their predecessor
+    // branch segments: maximal runs [a, b] in which every node after a has
+    // its predecessor as parent and only child; per cell contiguous
+    uint32_t n_seg;
+    const uint32_t *seg_off;     // n_cells + 1
+    const uint32_t *seg_a, *seg_b;  // global CV of head and bottom node
+    const uint8_t *seg_lvl;      // depth in the segment tree (root segment 0)
+    const uint32_t *kid_off;     // n_seg + 1, into kids
+    const uint32_t *kids;        // child segments of each segment's bottom node, descending head
     const double *cdt, *d0, *gpas_e, *axial;
     const int32_t *hh_of;        // HH slot or -1
     const uint32_t *cv_syn_off;  // n_cv + 1
@@ -97,6 +106,14 @@ struct DevNet {
     const uint64_t *tr_off;
     uint64_t *tr_cur;            // 2 per train: conductance and calcium cursors
 
+    // Poisson sources
+    uint32_t n_pois;
+    const uint32_t *pois_syn, *pois_cell;
+    const uint8_t *pois_ports;
+    const double *pois_w, *pois_rate;
+    double *pois_t;              // next arrival time
+    uint64_t *pois_j;            // its index
+
     // clamps, sorted by (CV, id)
     const double *cl_t0, *cl_dur, *cl_amp;
 
@@ -129,9 +146,9 @@ int launch_inject(const DevNet &d, uint32_t nsteps, void *stream);
 int launch_step_plain(const DevNet &d, uint64_t n, void *stream, void *ev_begin, void *ev_end);
 int launch_expand(const DevNet &d, uint32_t nsteps, void *stream);
 int launch_probe(const DevNet &d, uint64_t row, void *stream);
-// Fused epoch: block b owns cells blk[4b] .. blk[4b+1]-1 (see BlockPlan).
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, uint32_t n_blocks,
-                       size_t lds_bytes, void *stream);
+// Fused epoch: workgroup b owns cells blk[b] .. blk[b+1]-1.
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, const uint32_t *blk_lvl,
+                       uint32_t n_blocks, size_t lds_bytes, uint32_t block_threads, void *stream);
 int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream);
 
 }  // namespace pa

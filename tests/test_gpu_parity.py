@@ -72,6 +72,36 @@ def test_uneven_trees_full_size_short_horizon(mode):
     assert_state_close(o, s)
 
 
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_heavy_input_matches_oracle(mode):
+    """Several events per cell and step (20 kHz of external arrivals per
+    cell): the epoch's events exceed the fused kernel's LDS event buffer, so
+    part of them are delivered from the ring in global memory."""
+    net = netgen.tiny(seed=12, n_cells=9, t_end=60.0, ext_rate=20000.0, w_ext=0.0005)
+    _say(f"heavy input mode={mode}")
+    o, s = run_pair(net, 300, chunks=2, mode=mode, slot_capacity=64)
+    assert_raster_equal(o, s)
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+    assert s.stats()["events"] > 300 * 9 * 4
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_device_poisson_sources_match_oracle(mode):
+    """Poisson drive drawn on the device from the counter-based generator:
+    the same arrivals as the oracle's (identical rasters and deliveries)."""
+    net = netgen.tiny(seed=14, n_cells=11, t_end=150.0, poisson=True, ext_rate=300.0)
+    for k in ("train_dst", "train_ports", "train_w"):
+        net[k] = net[k][:0]
+    net["train_off"] = net["train_off"][:1]
+    net["train_times"] = net["train_times"][:0]
+    _say(f"poisson mode={mode}")
+    o, s = run_pair(net, 750, chunks=3, mode=mode)
+    assert assert_raster_equal(o, s) > 10
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
 def test_probes_sample_the_oracle_trajectory():
     net = netgen.tiny(seed=5, n_cells=7, t_end=100.0)
     probes = [("V", 0), ("V", int(net["cv_off"][3]) + 1), ("p", 2)]

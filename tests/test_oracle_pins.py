@@ -576,3 +576,27 @@ def test_oracle_rejects_invalid_networks():
     b.add_conns([0], [s], netgen.PORT_G, 0.1, 0.05)  # delay below dt
     with pytest.raises(oracle.OracleError):
         oracle.Oracle(_net(b))
+
+
+# ------------------------------------------------------------------ Poisson drive
+def test_poisson_source_is_a_poisson_process():
+    """Counter-based Poisson sources: inter-arrival times are exponential with
+    mean 1000/rate ms (KS test), and the arrivals delivered to a synapse over
+    T count like Poisson(rate T)."""
+    from scipy import stats
+    rate = 80.0
+    isi = np.array([oracle.poisson_isi(99, 3, j, rate) for j in range(20000)])
+    assert stats.kstest(isi, "expon", args=(0, 1000.0 / rate)).pvalue > 1e-3
+    b = netgen._Builder()
+    b.add_cell([-1], [20.0], [20.0], [netgen.MECH_PAS])
+    s = b.add_syn(0, 0, netgen.KIND_STC, 5.0, 0.0)
+    b.add_poisson(s, netgen.PORT_G | netgen.PORT_CA, 0.0, rate)
+    b.add_poisson(s, netgen.PORT_G, 0.0, 0.0)  # rate 0: silent
+    o = oracle.Oracle(_net(b))
+    n_steps = 25000  # 5 s
+    o.run(n_steps)
+    cnt, ssum = o.event_stats()
+    lam = rate * 5.0
+    assert abs(int(cnt[0, 0]) - lam) < 5 * math.sqrt(lam)
+    # calcium events trail the conductance events by t_c,delay (94 steps)
+    assert int(cnt[0, 0]) - int(cnt[0, 1]) <= 8
