@@ -627,6 +627,20 @@ pa_status build(pa_sim *s) {
         po_cell[k] = s->syn_cell[s->po_dst[k]];
     }
 
+    // ---- trains and Poisson sources grouped by target cell
+    std::vector<uint32_t> tr_cell_off(nc + 1, 0), tr_by_cell(ntr), po_cell_off(nc + 1, 0), po_by_cell(npo);
+    for (uint32_t k = 0; k < ntr; ++k) tr_cell_off[tr_cell[k] + 1]++;
+    for (uint32_t k = 0; k < npo; ++k) po_cell_off[po_cell[k] + 1]++;
+    for (uint32_t c = 0; c < nc; ++c) {
+        tr_cell_off[c + 1] += tr_cell_off[c];
+        po_cell_off[c + 1] += po_cell_off[c];
+    }
+    {
+        std::vector<uint32_t> ft(tr_cell_off.begin(), tr_cell_off.end() - 1), fp(po_cell_off.begin(), po_cell_off.end() - 1);
+        for (uint32_t k = 0; k < ntr; ++k) tr_by_cell[ft[tr_cell[k]]++] = k;
+        for (uint32_t k = 0; k < npo; ++k) po_by_cell[fp[po_cell[k]]++] = k;
+    }
+
     // ---- probes: internal indices
     std::vector<uint64_t> pr_idx(d.n_probes);
     for (uint32_t k = 0; k < d.n_probes; ++k) {
@@ -746,6 +760,10 @@ pa_status build(pa_sim *s) {
         for (uint32_t k = 0; k < ntr; ++k) cur[2 * k] = cur[2 * k + 1] = s->tr_off[k];
         d.tr_cur = upload(s, cur, ok);
     }
+    d.tr_cell_off = upload(s, tr_cell_off, ok);
+    d.tr_by_cell = upload(s, tr_by_cell, ok);
+    d.po_cell_off = upload(s, po_cell_off, ok);
+    d.po_by_cell = upload(s, po_by_cell, ok);
     d.pois_syn = upload(s, po_syn, ok);
     d.pois_cell = upload(s, po_cell, ok);
     d.pois_ports = upload(s, s->po_ports, ok);

@@ -177,6 +177,12 @@ __device__ inline void push_event(const DevNet &d, uint32_t cell, uint64_t s, co
     else raise_flag(d, FLAG_OVERFLOW, cell);
 }
 
+// Moves the arrivals of explicit train tr whose delivery step falls before
+// epoch_end into the target cell's ring.
+__device__ inline void inject_train(const DevNet &d, uint32_t tr, uint64_t epoch_start, uint64_t epoch_end);
+// Draws the arrivals of Poisson source k due before epoch_end into the ring.
+__device__ inline void inject_poisson(const DevNet &d, uint32_t k, uint64_t epoch_start, uint64_t epoch_end);
+
 __device__ __forceinline__ bool ev_before(const Event &a, const Event &b) {
     if (a.t != b.t) return a.t < b.t;
     if (a.src != b.src) return a.src < b.src;
@@ -230,6 +236,67 @@ __device__ inline void deliver_slot(const DevNet &d, uint32_t cell, uint64_t n, 
         d.ev_cnt[2 * e.syn + e.port - 1] += 1ull;
         d.ev_sum[2 * e.syn + e.port - 1] += (unsigned long long)n;
     }
+}
+
+__device__ inline void inject_train(const DevNet &d, uint32_t tr, uint64_t epoch_start, uint64_t epoch_end) {
+    const uint32_t cell = d.tr_cell[tr];
+    const uint64_t end = d.tr_off[tr + 1];
+    Event e;
+    e.w = d.tr_w[tr];
+    e.syn = d.tr_syn[tr];
+    e.src = d.n_cells + tr;
+    e.conn = 0;
+    if (d.tr_ports[tr] & 1) {
+        uint64_t j = d.tr_cur[2 * tr];
+        for (; j < end; ++j) {
+            const double t = d.tr_t[j];
+            const uint64_t s = (uint64_t)floor(t / d.dt);
+            if (s >= epoch_end) break;
+            e.t = t;
+            e.port = 1;
+            push_event(d, cell, s, e, epoch_start);
+        }
+        d.tr_cur[2 * tr] = j;
+    }
+    if (d.tr_ports[tr] & 2) {
+        uint64_t j = d.tr_cur[2 * tr + 1];
+        for (; j < end; ++j) {
+            const double t = d.tr_t[j] + d.stc.t_cd;
+            const uint64_t s = (uint64_t)floor(t / d.dt);
+            if (s >= epoch_end) break;
+            e.t = t;
+            e.port = 2;
+            push_event(d, cell, s, e, epoch_start);
+        }
+        d.tr_cur[2 * tr + 1] = j;
+    }
+}
+
+__device__ inline void inject_poisson(const DevNet &d, uint32_t k, uint64_t epoch_start, uint64_t epoch_end) {
+    double t = d.pois_t[k];
+    uint64_t j = d.pois_j[k];
+    const uint32_t cell = d.pois_cell[k];
+    Event e;
+    e.w = d.pois_w[k];
+    e.syn = d.pois_syn[k];
+    e.src = d.n_cells + d.n_trains + k;
+    e.conn = 0;
+    while (floor(t / d.dt) < (double)epoch_end) {
+        if (d.pois_ports[k] & 1) {
+            e.t = t;
+            e.port = 1;
+            push_event(d, cell, (uint64_t)floor(t / d.dt), e, epoch_start);
+        }
+        if (d.pois_ports[k] & 2) {
+            e.t = t + d.stc.t_cd;
+            e.port = 2;
+            push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, epoch_start);
+        }
+        ++j;
+        t = t + poisson_isi(d.seed, k, j, d.pois_rate[k]);
+    }
+    d.pois_t[k] = t;
+    d.pois_j[k] = j;
 }
 
 // --------------------------------------------------------------- currents

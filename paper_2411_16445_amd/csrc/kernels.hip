@@ -43,72 +43,10 @@ __global__ void k_init_poisson(DevNet d) {
 // At the start of an epoch ending at `epoch_end`, move every train arrival
 // whose delivery step falls before epoch_end into the target cell's ring.
 __global__ void k_inject(DevNet d, uint32_t nsteps) {
-    uint32_t tr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tr >= d.n_trains) {
-        // Poisson sources: draw the arrivals due before the epoch's end
-        const uint32_t k = tr - d.n_trains;
-        if (k >= d.n_pois) return;
-        const uint64_t epoch_start = d.ctr->step;
-        const uint64_t epoch_end = epoch_start + nsteps;
-        double t = d.pois_t[k];
-        uint64_t j = d.pois_j[k];
-        const uint32_t cell = d.pois_cell[k];
-        Event e;
-        e.w = d.pois_w[k];
-        e.syn = d.pois_syn[k];
-        e.src = d.n_cells + d.n_trains + k;
-        e.conn = 0;
-        while (floor(t / d.dt) < (double)epoch_end) {
-            if (d.pois_ports[k] & 1) {
-                e.t = t;
-                e.port = 1;
-                push_event(d, cell, (uint64_t)floor(t / d.dt), e, epoch_start);
-            }
-            if (d.pois_ports[k] & 2) {
-                e.t = t + d.stc.t_cd;
-                e.port = 2;
-                push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, epoch_start);
-            }
-            ++j;
-            t = t + poisson_isi(d.seed, k, j, d.pois_rate[k]);
-        }
-        d.pois_t[k] = t;
-        d.pois_j[k] = j;
-        return;
-    }
-    const uint32_t cell = d.tr_cell[tr];
-    const uint64_t end = d.tr_off[tr + 1];
-    const uint64_t epoch_start = d.ctr->step;
-    const uint64_t epoch_end = epoch_start + nsteps;
-    Event e;
-    e.w = d.tr_w[tr];
-    e.syn = d.tr_syn[tr];
-    e.src = d.n_cells + tr;
-    e.conn = 0;
-    if (d.tr_ports[tr] & 1) {
-        uint64_t j = d.tr_cur[2 * tr];
-        for (; j < end; ++j) {
-            double t = d.tr_t[j];
-            uint64_t s = (uint64_t)floor(t / d.dt);
-            if (s >= epoch_end) break;
-            e.t = t;
-            e.port = 1;
-            push_event(d, cell, s, e, epoch_start);
-        }
-        d.tr_cur[2 * tr] = j;
-    }
-    if (d.tr_ports[tr] & 2) {
-        uint64_t j = d.tr_cur[2 * tr + 1];
-        for (; j < end; ++j) {
-            double t = d.tr_t[j] + d.stc.t_cd;
-            uint64_t s = (uint64_t)floor(t / d.dt);
-            if (s >= epoch_end) break;
-            e.t = t;
-            e.port = 2;
-            push_event(d, cell, s, e, epoch_start);
-        }
-        d.tr_cur[2 * tr + 1] = j;
-    }
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t epoch_start = d.ctr->step, epoch_end = epoch_start + nsteps;
+    if (x < d.n_trains) inject_train(d, x, epoch_start, epoch_end);
+    else if (x - d.n_trains < d.n_pois) inject_poisson(d, x - d.n_trains, epoch_start, epoch_end);
 }
 
 // ----------------------------------------------------------------- views
@@ -249,15 +187,24 @@ __global__ void k_expand(DevNet d, uint32_t nsteps) {
             }
         }
     }
-}
-
-__global__ void k_epoch_close(DevNet d, uint32_t nsteps) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        d.ctr->hist_n += d.ctr->ep_n;
-        d.ctr->ep_n = 0;
-        d.ctr->step += nsteps;
+    // the last workgroup to finish closes the epoch: the spikes join the
+    // history and the epoch's first step advances
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(&d.ctr->blocks_done, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            d.ctr->hist_n += n_sp;
+            d.ctr->ep_n = 0;
+            d.ctr->step += nsteps;
+            d.ctr->blocks_done = 0;
+            __threadfence();
+        }
     }
 }
+
+
 
 // ----------------------------------------------------------------- probes
 template <class T>
@@ -332,7 +279,6 @@ int launch_expand(const DevNet &d, uint32_t nsteps, void *stream) {
     if (waves > 4096) waves = 4096;
     if (waves < 4) waves = 4;
     hipLaunchKernelGGL(k_expand, grid_for(waves * 64, 256), dim3(256), 0, s, d, nsteps);
-    hipLaunchKernelGGL(k_epoch_close, dim3(1), dim3(64), 0, s, d, nsteps);
     return (int)hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ struct FusedLayout {
     uint32_t G, C, Dec, M, HH, N;
     // 32-bit
     uint32_t Par, HHk, CvSyn, CvCl, Cb0, Cs0, Det, HHcv, EvN, EvOff, Scan;
-    // events of the epoch, sorted: {w, syn, port}
+    // events of the epoch, each slot's records sorted into delivery order
     uint32_t EvBuf, ev_cap;
     // 16-bit, 8-bit
     uint32_t SynCell, Run, Kind, Post;
@@ -52,6 +52,9 @@ struct FusedLayout {
     uint32_t Cu, Cb, SegA, SegB, SegCell, KidOff, Kids, SegLvl;
     // HH constants: 6 channel parameters and the area factor per HH CV
     uint32_t HHp;
+    // cyclic-reduction work arrays (mixed form): lower, upper, and a second
+    // copy of lower, diagonal, upper, right-hand side
+    uint32_t Pa, Pc, Qa, Qd, Qc, Qr;
     uint32_t total;
     __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
                                     uint32_t tsize, uint32_t ng) {
@@ -73,8 +76,11 @@ struct FusedLayout {
         Det = take(4 * nc, 4); HHcv = take(4 * nh, 4); EvN = take(4 * nc * K, 4);
         EvOff = take(4 * nc * K, 4); Scan = take(4 * 257, 4);
         ev_cap = 2 * nc * K + 32;
-        EvBuf = take(16 * ev_cap, 16);
+        EvBuf = take(32 * ev_cap, 16);
         Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
+        const uint32_t np = tsize == 4 ? nv : 0;
+        Pa = take(8 * np, 8); Pc = take(8 * np, 8); Qa = take(8 * np, 8); Qd = take(8 * np, 8);
+        Qc = take(8 * np, 8); Qr = take(8 * np, 8);
         SynCell = take(2 * ns, 2); Run = take(2 * nv, 2);
         SegA = take(2 * ng, 2); SegB = take(2 * ng, 2); SegCell = take(2 * ng, 2);
         KidOff = take(2 * (ng + 1), 2); Kids = take(2 * ng, 2);
@@ -142,6 +148,14 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     uint16_t *sSegA = (uint16_t *)(L + lay.SegA), *sSegB = (uint16_t *)(L + lay.SegB);
     uint16_t *sSegCell = (uint16_t *)(L + lay.SegCell), *sKidOff = (uint16_t *)(L + lay.KidOff);
     uint16_t *sKids = (uint16_t *)(L + lay.Kids);
+    // blocks whose cells are all unbranched (one segment per cell)
+    const bool chains = (ng == ncb);
+    uint32_t pcr_steps = 0;
+    if (!EXACT && chains) {
+        uint32_t len = 1;
+        for (uint32_t c = 0; c < ncb; ++c) len = max(len, d.cv_off[c0 + c + 1] - d.cv_off[c0 + c]);
+        while ((1u << pcr_steps) < len) ++pcr_steps;
+    }
     const SynView<T> sv{sG, sC, sH, sZ, s0};
     const SynConst<T> sc{sErev, sDec, sKind, s0};
     const GateView<T> gv{sM, sHH, sN, k0};
@@ -207,86 +221,83 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     }
     for (uint32_t c = tid; c < ncb; c += BS)
         for (uint32_t g = d.seg_off[c0 + c]; g < d.seg_off[c0 + c + 1]; ++g) sSegCell[g - g0] = (uint16_t)c;
-    // events of the epoch: counts per (cell, step) slot, an exclusive scan
-    // over the slots, then each slot sorted into delivery order and copied
-    // to LDS (slots beyond the LDS buffer stay in the ring, sorted); the
-    // delivery statistics are counted here, in parallel
+    // external arrivals of this epoch for the workgroup's cells enter the
+    // rings (trains and Poisson sources grouped by target cell)
+    {
+        const uint64_t epoch_end = n0 + nsteps;
+        const uint32_t t0 = d.tr_cell_off[c0], t1 = d.tr_cell_off[c1];
+        for (uint32_t x = t0 + tid; x < t1; x += BS) inject_train(d, d.tr_by_cell[x], n0, epoch_end);
+        const uint32_t p0 = d.po_cell_off[c0], p1 = d.po_cell_off[c1];
+        for (uint32_t x = p0 + tid; x < p1; x += BS) inject_poisson(d, d.po_by_cell[x], n0, epoch_end);
+    }
+    if (tid == 0) sScan[0] = 0;
+    __syncthreads();
+    // events of the epoch: one lane per (cell, step) slot takes the slot's
+    // count, claims room in the LDS event buffer, copies the records there
+    // and sorts them into delivery order (a slot that does not fit is
+    // sorted in place in the ring); the delivery statistics are counted
+    // here, in parallel
     const uint32_t nslot = ncb * nsteps;
-    const uint32_t chunk = (nslot + BS - 1) / BS;
-    uint32_t part = 0;
-    for (uint32_t x = tid * chunk; x < min(nslot, (tid + 1) * chunk); ++x) {
+    Event *sEv = (Event *)(L + lay.EvBuf);
+    for (uint32_t x = tid; x < nslot; x += BS) {
         const uint32_t c = x / nsteps, st = x - c * nsteps;
         const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
         const uint32_t cnt = min(d.ev_n[ring], d.Q);
         sEvN[c * K + st] = cnt;
-        part += cnt;
-    }
-    sScan[tid] = part;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (uint32_t t = 0; t < BS; ++t) {
-            const uint32_t v = sScan[t];
-            sScan[t] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
-    {
-        uint32_t off = sScan[tid];
-        for (uint32_t x = tid * chunk; x < min(nslot, (tid + 1) * chunk); ++x) {
-            const uint32_t c = x / nsteps, st = x - c * nsteps;
-            const uint32_t cnt = sEvN[c * K + st];
-            sEvOff[c * K + st] = (off + cnt <= lay.ev_cap) ? off : 0xffffffffu;
-            off += cnt;
-        }
-    }
-    __syncthreads();
-    for (uint32_t x = tid; x < nslot; x += BS) {
-        const uint32_t c = x / nsteps, st = x - c * nsteps;
-        const uint32_t cnt = sEvN[c * K + st];
-        const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
-        d.ev_n[ring] = 0;
         if (!cnt) continue;
+        d.ev_n[ring] = 0;
         Event *ev = d.ev + ring * d.Q;
-        sort_slot(ev, cnt);
-        const uint32_t off = sEvOff[c * K + st];
+        const uint32_t off = atomicAdd(&sScan[0], cnt);
+        Event *dst;
+        if (off + cnt <= lay.ev_cap) {
+            dst = sEv + off;
+            for (uint32_t i = 0; i < cnt; ++i) dst[i] = ev[i];
+            sEvOff[c * K + st] = off;
+        } else {
+            dst = ev;
+            sEvOff[c * K + st] = 0xffffffffu;
+        }
+        sort_slot(dst, cnt);
         for (uint32_t i = 0; i < cnt; ++i) {
-            const Event e = ev[i];
-            if (off != 0xffffffffu) {
-                double *rec = (double *)(L + lay.EvBuf) + 2 * (size_t)(off + i);
-                rec[0] = e.w;
-                ((uint32_t *)(rec + 1))[0] = e.syn;
-                ((uint32_t *)(rec + 1))[1] = e.port;
-            }
-            atomicAdd(&d.ev_cnt[2 * e.syn + e.port - 1], 1ull);
-            atomicAdd(&d.ev_sum[2 * e.syn + e.port - 1], (unsigned long long)(n0 + st));
+            const uint32_t sy = dst[i].syn, po = dst[i].port;
+            atomicAdd(&d.ev_cnt[2 * sy + po - 1], 1ull);
+            atomicAdd(&d.ev_sum[2 * sy + po - 1], (unsigned long long)(n0 + st));
         }
     }
     unsigned long long delivered = 0;
     __syncthreads();
     STAGE_MARK(6);
 
+    // protein trigger sum of step m (one wavefront per cell: strided lane
+    // sums, then a fixed shuffle tree), protein synthesis, detection
+    auto stage_e = [&](uint64_t m) {
+        for (uint32_t c = wave; c < ncb; c += NW) {
+            const uint32_t a = sCs0[c], e = sCs0[c + 1];
+            double S = 0.0;
+            for (uint32_t s = a + lane; s < e; s += 64) S += sAbs[s];
+            S = wave_sum_down(S);
+            if (lane == 0) {
+                sP[c] = prp_next(d, sP[c], S);
+                sPost[c] = detect(d, c0 + c, m, sVold[c], sV[sDet[c]]) ? 1 : 0;
+            }
+        }
+    };
+
     for (uint32_t st = 0; st < nsteps; ++st) {
         const uint64_t n = n0 + st;
         const double tn = (double)n * d.dt;
-        // A. events due at step n, already in delivery order
+        // A. events due at step n, already in delivery order; the protein
+        //    update and detection of step n-1 (independent of them)
         for (uint32_t c = tid; c < ncb; c += BS) {
             const uint32_t cnt = sEvN[c * K + st];
             if (!cnt) continue;
             const uint32_t off = sEvOff[c * K + st];
-            if (off != 0xffffffffu) {
-                const double *rec = (const double *)(L + lay.EvBuf) + 2 * (size_t)off;
-                for (uint32_t i = 0; i < cnt; ++i, rec += 2) {
-                    const uint32_t *u = (const uint32_t *)(rec + 1);
-                    apply_event<T>(d, u[0], u[1], rec[0], sv, sc);
-                }
-            } else {
-                const Event *ev = d.ev + ((uint64_t)(c0 + c) * d.R + (uint32_t)(n % d.R)) * d.Q;
-                for (uint32_t i = 0; i < cnt; ++i) apply_event<T>(d, ev[i].syn, ev[i].port, ev[i].w, sv, sc);
-            }
+            const Event *ev = off != 0xffffffffu ? sEv + off
+                                                 : d.ev + ((uint64_t)(c0 + c) * d.R + (uint32_t)(n % d.R)) * d.Q;
+            for (uint32_t i = 0; i < cnt; ++i) apply_event<T>(d, ev[i].syn, ev[i].port, ev[i].w, sv, sc);
             delivered += cnt;
         }
+        if (st > 0) stage_e(n - 1);
         __syncthreads();
         STAGE_MARK(0);
         // B. currents at V^n and assembly of the cable system
@@ -309,7 +320,59 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         //    elimination.  Meanwhile the other wavefronts update the synapses
         //    (decay, post-synaptic hook, plasticity from step-start values),
         //    which do not depend on the new voltage.
-        if (wave == 0) {
+        if (wave == 0 && !EXACT && chains) {
+            // mixed form, unbranched cells: parallel cyclic reduction of each
+            // cell's tridiagonal system across the wavefront's lanes (FP64;
+            // equal to the elimination up to rounding)
+            double *pa = (double *)(L + lay.Pa), *pc = (double *)(L + lay.Pc);
+            double *qa = (double *)(L + lay.Qa), *qd = (double *)(L + lay.Qd);
+            double *qc = (double *)(L + lay.Qc), *qr = (double *)(L + lay.Qr);
+            for (uint32_t c = lane; c < ncb; c += 64) sVold[c] = sV[sDet[c]];
+            for (uint32_t i = lane; i < nv; i += 64) {
+                pa[i] = sPar[i] >= 0 ? -sAx[i] : 0.0;
+                pc[i] = (i + 1 < nv && sPar[i + 1] == (int32_t)i) ? -sAx[i + 1] : 0.0;
+            }
+            wave_sync();
+            double *A = pa, *Dd = sD, *Cc = pc, *Rr = sB;
+            double *A2 = qa, *D2 = qd, *C2 = qc, *R2 = qr;
+            for (uint32_t k = 0, sft = 1; k < pcr_steps; ++k, sft <<= 1) {
+                for (uint32_t i = lane; i < nv; i += 64) {
+                    const double ai = A[i], ci = Cc[i];
+                    double na = 0.0, nc2 = 0.0, nd = Dd[i], nr = Rr[i];
+                    // neighbours at distance sft inside the same cell: a
+                    // nonzero coupling marks a neighbour
+                    if (ai != 0.0 && i >= sft) {
+                        const uint32_t im = i - sft;
+                        const double al = -qdiv<false>(ai, Dd[im]);
+                        na = al * A[im];
+                        nd += al * Cc[im];
+                        nr += al * Rr[im];
+                    }
+                    if (ci != 0.0 && i + sft < nv) {
+                        const uint32_t ip = i + sft;
+                        const double ga = -qdiv<false>(ci, Dd[ip]);
+                        nc2 = ga * Cc[ip];
+                        nd += ga * A[ip];
+                        nr += ga * Rr[ip];
+                    }
+                    A2[i] = na;
+                    D2[i] = nd;
+                    C2[i] = nc2;
+                    R2[i] = nr;
+                }
+                wave_sync();
+                double *t;
+                t = A; A = A2; A2 = t;
+                t = Dd; Dd = D2; D2 = t;
+                t = Cc; Cc = C2; C2 = t;
+                t = Rr; Rr = R2; R2 = t;
+            }
+            for (uint32_t i = lane; i < nv; i += 64) {
+                const double v = qdiv<false>(Rr[i], Dd[i]);
+                sV[i] = v;
+                if (!isfinite(v)) raise_flag(d, FLAG_NONFINITE, c0);
+            }
+        } else if (wave == 0) {
             for (uint32_t c = lane; c < ncb; c += 64) sVold[c] = sV[sDet[c]];
             for (int lv = (int)nlev - 1; lv >= 0; --lv) {
                 for (uint32_t g = lane; g < ng; g += 64) {
@@ -342,6 +405,7 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
                 wave_sync();
             }
         }
+        STAGE_MARK(7);
         {
             // synapses on wavefronts 1.. (all lanes when there is one wavefront)
             const uint32_t first = NW > 1 ? 64u : 0u;
@@ -357,21 +421,11 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         // D. gates at V^{n+1}
         for (uint32_t k = tid; k < nhh; k += BS) gate_update<T>(d, k0 + k, sV[sHHcv[k]], gv);
         STAGE_MARK(3);
-        // E. protein trigger sum (one wavefront per cell: strided lane sums,
-        //    then a fixed shuffle tree), protein synthesis, detection
-        for (uint32_t c = wave; c < ncb; c += NW) {
-            const uint32_t a = sCs0[c], e = sCs0[c + 1];
-            double S = 0.0;
-            for (uint32_t s = a + lane; s < e; s += 64) S += sAbs[s];
-            S = wave_sum_down(S);
-            if (lane == 0) {
-                sP[c] = prp_next(d, sP[c], S);
-                sPost[c] = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]) ? 1 : 0;
-            }
-        }
-        __syncthreads();
-        STAGE_MARK(4);
     }
+    // E of the epoch's last step
+    stage_e(n0 + nsteps - 1);
+    __syncthreads();
+    STAGE_MARK(4);
     // ---- stage out
     for (uint32_t i = tid; i < nv; i += BS) d.V[v0 + i] = sV[i];
     for (uint32_t s = tid; s < ns; s += BS) {
@@ -500,7 +554,7 @@ pa_status upload_plan(pa_sim *s, BatchedPlan &P, const Offsets &o) {
 
 int enqueue_epoch(const DevNet &d, const BatchedPlan &P, uint32_t nsteps, hipStream_t st,
                   hipEvent_t e0, hipEvent_t e1) {
-    int r = launch_inject(d, nsteps, st);
+    int r = 0;
     if (e0) (void)hipEventRecord(e0, st);
     r |= launch_epoch_fused(d, nsteps, P.d_blk, P.d_lvl, (uint32_t)P.blk.size() - 1, P.lds, P.threads, st);
     if (e1) (void)hipEventRecord(e1, st);

@@ -33,7 +33,7 @@ struct Counters {
     uint64_t hist_n;    // spikes in the history buffer of the current chunk
     uint64_t events;    // events delivered
     uint32_t bad_cell;  // first cell that raised a flag
-    uint32_t pad;
+    uint32_t blocks_done;  // workgroups of the exchange kernel that finished
 };
 
 struct Stc {
@@ -105,6 +105,8 @@ struct DevNet {
     const double *tr_w, *tr_t;
     const uint64_t *tr_off;
     uint64_t *tr_cur;            // 2 per train: conductance and calcium cursors
+    const uint32_t *tr_cell_off, *tr_by_cell;   // trains grouped by target cell
+    const uint32_t *po_cell_off, *po_by_cell;   // Poisson sources grouped by target cell
 
     // Poisson sources
     uint32_t n_pois;

@@ -1,0 +1,87 @@
+"""Accuracy of the mixed-precision form against the FP64 oracle, per
+workload: max |dV| over the run, first raster divergence, spike-count
+difference, crossing-time shift of matched spikes before the divergence,
+max |dh| and |dz|.  A report with sanity bounds, not a parity test: FP32
+gates, conductances and calcium make the recurrent dynamics diverge after a
+while.  The figures are written to gpurun_out/mixed_report.json when that
+directory exists.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import netgen
+import oracle
+from paper_2411_16445_amd import Simulation
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+REPORT = {}
+
+
+def _compare(name, net, n_steps, chunk):
+    print(f"[case] mixed report {name} {n_steps} steps", flush=True)
+    o = oracle.Oracle(net)
+    s = Simulation(net, mode="batched", precision="mixed")
+    dv_max = 0.0
+    done = 0
+    while done < n_steps:
+        m = min(chunk, n_steps - done)
+        o.run(m)
+        s.advance_steps(m)
+        done += m
+        dv_max = max(dv_max, float(np.abs(s.read("V") - o.read("V")).max()))
+    og, ost, ot = o.spikes()
+    sg, sst, stt = s.spikes()
+    n = min(og.size, sg.size)
+    same = (og[:n] == sg[:n]) & (ost[:n] == sst[:n])
+    first_div = int(np.argmin(same)) if not same.all() else n
+    if first_div < n:
+        t_div = float(min(ost[first_div], sst[first_div]) * net["dt"])
+    elif og.size != sg.size:
+        t_div = float((ost[n] if og.size > n else sst[n]) * net["dt"])
+    else:
+        t_div = None
+    shift = np.abs(stt[:first_div] - ot[:first_div])
+    kinds = net["syn_kind"] == 1
+    rep = dict(steps=n_steps, t_ms=n_steps * net["dt"], max_abs_dV_mV=dv_max,
+               spikes_fp64_oracle=int(og.size), spikes_mixed=int(sg.size),
+               first_divergence_index=first_div, first_divergence_ms=t_div,
+               max_spike_time_shift_ms=float(shift.max()) if shift.size else 0.0,
+               mean_spike_time_shift_ms=float(shift.mean()) if shift.size else 0.0,
+               max_abs_dh_mV=float(np.abs(s.read("h") - o.read("h"))[kinds].max()) if kinds.any() else 0.0,
+               max_abs_dz=float(np.abs(s.read("z") - o.read("z"))[kinds].max()) if kinds.any() else 0.0)
+    REPORT[name] = rep
+    print(json.dumps({name: rep}), flush=True)
+    d = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(d):
+        with open(os.path.join(d, "mixed_report.json"), "w") as f:
+            json.dump(REPORT, f, indent=1)
+    return rep
+
+
+def test_mixed_report_single_synapse():
+    rep = _compare("single-synapse 10 s", netgen.config1(), 50000, 25000)
+    assert rep["max_spike_time_shift_ms"] < 0.05
+    assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) <= 3
+
+
+def test_mixed_report_ei_network():
+    rep = _compare("E/I 2000x21 200 ms", netgen.config2(t_end=500.0), 1000, 250)
+    assert rep["max_spike_time_shift_ms"] < 0.2
+    assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) < 0.1 * rep["spikes_fp64_oracle"] + 10
+
+
+def test_mixed_report_long_dendrites():
+    rep = _compare("E/I 2000x101 60 ms", netgen.config4(t_end=200.0), 300, 150)
+    assert rep["max_spike_time_shift_ms"] < 0.2
+    assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) < 0.1 * rep["spikes_fp64_oracle"] + 10
+
+
+def test_mixed_report_uneven_trees():
+    rep = _compare("trees 4096 30 ms", netgen.config3(t_end=60.0), 150, 150)
+    assert rep["max_spike_time_shift_ms"] < 0.2
+    assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) < 0.1 * rep["spikes_fp64_oracle"] + 10
