@@ -85,7 +85,11 @@ typedef struct {
     uint32_t probe_stride;   /* steps between probe samples, >= 1 */
     uint32_t slot_capacity;  /* events per (cell, step) slot; 0 = automatic */
     uint32_t cells_per_block;/* batched form: cells per workgroup; 0 = autotune */
-    uint32_t reserved;
+    uint16_t block_threads;  /* batched form: 64, 128 or 256 lanes per workgroup;
+                                0 = autotune */
+    uint16_t solver_waves;   /* batched form: wavefronts of a workgroup that run the
+                                cable solve (1 .. lanes/64 - 1; the others update
+                                synapses); 0 = autotune */
 } pa_config;
 
 /* Table 5 of the paper (h0 = 10 mV * 0.5 gamma_p/(gamma_p + gamma_d),
@@ -121,6 +125,8 @@ typedef struct {
     uint32_t cells_per_block;
     double advance_ms;       /* wall time inside pa_advance* so far */
     uint64_t device_bytes;   /* device memory held */
+    uint32_t block_threads;  /* batched form: lanes per workgroup chosen */
+    uint32_t solver_waves;   /* batched form: solver wavefronts chosen */
 } pa_stats;
 
 /* Creates a simulation in the BUILD state.  cfg and stc are copied.

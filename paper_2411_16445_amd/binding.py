@@ -11,8 +11,10 @@ built; there is no other execution path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -41,7 +43,7 @@ class pa_config(C.Structure):
     _fields_ = [("dt_ms", C.c_double), ("threshold_mV", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("mode", C.c_int32), ("probe_stride", C.c_uint32),
                 ("slot_capacity", C.c_uint32), ("cells_per_block", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("block_threads", C.c_uint16), ("solver_waves", C.c_uint16)]
 
 
 STC_FIELDS = ["tau_c", "tau_h", "tau_p", "tau_z", "gamma_p", "gamma_d", "theta_p", "theta_d",
@@ -63,13 +65,24 @@ class pa_stats(C.Structure):
                                           "n_trains", "n_probes", "n_poisson", "steps", "spikes",
                                           "events")] + \
         [("epoch_steps", C.c_uint32), ("ring_slots", C.c_uint32), ("slot_capacity", C.c_uint32),
-         ("cells_per_block", C.c_uint32), ("advance_ms", C.c_double), ("device_bytes", C.c_uint64)]
+         ("cells_per_block", C.c_uint32), ("advance_ms", C.c_double), ("device_bytes", C.c_uint64),
+         ("block_threads", C.c_uint32), ("solver_waves", C.c_uint32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 _lib = None
+
+# Simulations still open at interpreter exit are destroyed while torch (whose
+# caching allocator owns their device memory) is still intact.
+_LIVE: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for sim in list(_LIVE):
+        sim.close()
 _P = C.c_void_p
 
 
@@ -150,7 +163,7 @@ class Simulation:
     """
 
     def __init__(self, net: dict, precision="fp64", mode="plain", probes=(), probe_stride=1,
-                 slot_capacity=0, cells_per_block=0, use_torch=True):
+                 slot_capacity=0, cells_per_block=0, block_threads=0, solver_waves=0, use_torch=True):
         lib = load_library()
         self._lib = lib
         cfg = pa_config()
@@ -162,12 +175,15 @@ class Simulation:
         cfg.probe_stride = int(probe_stride)
         cfg.slot_capacity = int(slot_capacity)
         cfg.cells_per_block = int(cells_per_block)
+        cfg.block_threads = int(block_threads)
+        cfg.solver_waves = int(solver_waves)
         stc = stc_params(net["stc"])
         h = _P()
         st = lib.pa_sim_create(C.byref(cfg), C.byref(stc), C.byref(h))
         if st != PA_OK:
             raise PAError(st, "pa_sim_create rejected the configuration")
         self._h = h
+        _LIVE.add(self)
         self.dt = cfg.dt_ms
         self._torch_cb = None
         if use_torch:
@@ -203,8 +219,10 @@ class Simulation:
         release = torch.cuda.caching_allocator_delete
 
         def _free(ptr, ctx):
-            if release is not None:
+            try:
                 release(ptr)
+            except Exception:
+                pass  # interpreter shutdown: the process returns the memory
 
         self._torch_cb = (ALLOC_FN(_alloc), FREE_FN(_free), stream)
         self._check(self._lib.pa_set_stream(self._h, C.c_void_p(stream.cuda_stream)))

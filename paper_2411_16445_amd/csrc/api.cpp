@@ -193,6 +193,12 @@ pa_status pa_sim_create(const pa_config *cfg, const pa_stc_params *stc, pa_sim *
     if (cfg->precision != PA_FP64 && cfg->precision != PA_MIXED) return PA_EINVAL;
     if (cfg->mode != PA_PLAIN && cfg->mode != PA_BATCHED) return PA_EINVAL;
     if (cfg->probe_stride == 0) return PA_EINVAL;
+    if (cfg->block_threads != 0 && cfg->block_threads != 64 && cfg->block_threads != 128 &&
+        cfg->block_threads != 256)
+        return PA_EINVAL;
+    if (cfg->solver_waves > 3 || (cfg->block_threads && cfg->solver_waves &&
+                                  cfg->block_threads > 64 && cfg->solver_waves >= cfg->block_threads / 64))
+        return PA_EINVAL;
     const double taus[] = {stc->tau_c, stc->tau_h, stc->tau_p, stc->tau_z};
     for (double t : taus)
         if (!finite_pos(t)) return PA_EINVAL;
@@ -562,6 +568,14 @@ pa_status build(pa_sim *s) {
     }
     for (uint32_t i = 0; i < ncv; ++i) cv_syn_off[i + 1] += cv_syn_off[i];
     for (uint32_t c = 0; c < nc; ++c) syn_off[c + 1] += syn_off[c];
+    // per-CV decay factor where all of a CV's synapses share one
+    std::vector<double> cv_dec(ncv, 1.0);
+    bool dec_uniform = true;
+    for (uint32_t i = 0; i < ncv; ++i)
+        for (uint32_t q = cv_syn_off[i]; q < cv_syn_off[i + 1]; ++q) {
+            if (q == cv_syn_off[i]) cv_dec[i] = sdecay[q];
+            else if (sdecay[q] != cv_dec[i]) dec_uniform = false;
+        }
 
     // ---- clamps sorted by (CV, id)
     const uint32_t ncl = (uint32_t)s->cl_cell.size();
@@ -715,6 +729,8 @@ pa_status build(pa_sim *s) {
     d.axial = upload(s, axial, ok);
     d.hh_of = upload(s, hh_of, ok);
     d.cv_syn_off = upload(s, cv_syn_off, ok);
+    d.cv_dec = upload(s, cv_dec, ok);
+    d.cv_dec_uniform = dec_uniform ? 1u : 0u;
     d.cv_cl_off = upload(s, cv_cl_off, ok);
     d.V = upload(s, V, ok);
     d.I = zeros<double>(s, ncv, ok);
@@ -807,6 +823,7 @@ struct BatchedPlan;
 pa_status batched_setup(pa_sim *s);
 void batched_release(pa_sim *s);
 uint32_t batched_cells_per_block(pa_sim *s);
+void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves);
 pa_status run_epoch_batched(pa_sim *s, uint32_t nsteps, hipEvent_t e0, hipEvent_t e1);
 pa_status run_graph_batched(pa_sim *s, uint32_t &steps_done);
 uint32_t batched_graph_steps(pa_sim *s);
@@ -1135,6 +1152,7 @@ extern "C" pa_status pa_stats_get(const pa_sim *s, pa_stats *o) {
     o->ring_slots = s->d.R;
     o->slot_capacity = s->d.Q;
     o->cells_per_block = batched_cells_per_block(const_cast<pa_sim *>(s));
+    batched_plan_shape(const_cast<pa_sim *>(s), o->block_threads, o->solver_waves);
     o->advance_ms = s->advance_ms;
     o->device_bytes = s->device_bytes;
     if (s->state != 0) {

@@ -92,20 +92,33 @@ __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ double dexpm1(double x) { return expm1(x); }
 __device__ __forceinline__ float dexpm1(float x) { return expm1f(x); }
 
+// Hodgkin-Huxley (1952) rates in 1/ms, rest at -65 mV, q10 factor 1:
+// opening and closing rate (alpha, beta) of gate j (0 = m, 1 = h, 2 = n),
+//   alpha_m = exprelr(x1), alpha_h = 0.07 exp(x1), alpha_n = 0.1 exprelr(x1),
+//   beta_m = 4 exp(x2), beta_h = 1 / (exp(x2) + 1), beta_n = 0.125 exp(x2),
+// with x1 = -(v + c1) / d1, x2 = -(v + c2) / d2 and the gate's constants.
+// Written without branches on j, so that lanes integrating different
+// gates of one wavefront do not serialise; each rate is the same expression
+// as the gate-specific form.
 template <class T>
-__device__ __forceinline__ T exprelr(T x) {
-    return (x == T(0)) ? T(1) : x / dexpm1(x);
+__device__ __forceinline__ void hh_rate_pair(T v, int j, T &a, T &b) {
+    const bool h = (j == 1);
+    const T c1 = j == 0 ? T(40) : (h ? T(65) : T(55));
+    const T d1 = h ? T(20) : T(10);
+    const T c2 = h ? T(35) : T(65);
+    const T d2 = j == 0 ? T(18) : (h ? T(10) : T(80));
+    const T x1 = -(v + c1) / d1;
+    const T x2 = -(v + c2) / d2;
+    const T em1 = dexpm1(x1), e1 = dexp(x1), e2 = dexp(x2);
+    const T rel = (x1 == T(0)) ? T(1) : x1 / em1;
+    a = h ? T(0.07) * e1 : (j == 0 ? rel : T(0.1) * rel);
+    b = h ? T(1) / (e2 + T(1)) : (j == 0 ? T(4) : T(0.125)) * e2;
 }
 
-// Hodgkin-Huxley (1952) rates in 1/ms, rest at -65 mV, q10 factor 1.
 template <class T>
 __device__ __forceinline__ void hh_rates(T v, T r[6]) {
-    r[0] = exprelr<T>(-(v + T(40)) / T(10));
-    r[1] = T(4) * dexp(-(v + T(65)) / T(18));
-    r[2] = T(0.07) * dexp(-(v + T(65)) / T(20));
-    r[3] = T(1) / (dexp(-(v + T(35)) / T(10)) + T(1));
-    r[4] = T(0.1) * exprelr<T>(-(v + T(55)) / T(10));
-    r[5] = T(0.125) * dexp(-(v + T(65)) / T(80));
+#pragma unroll
+    for (int j = 0; j < 3; ++j) hh_rate_pair<T>(v, j, r[2 * j], r[2 * j + 1]);
 }
 
 // State views: the same device functions update state held in global
@@ -134,21 +147,25 @@ struct SynConst {
     uint32_t base;
 };
 
-// Exact exponential integration of the three gates at the new voltage.
+// Exact exponential integration of gate j (0 = m, 1 = h, 2 = n) at the new
+// voltage: x <- x_inf + (x - x_inf) exp(-dt (alpha + beta)).
+template <class T>
+__device__ __forceinline__ T gate_next(T x, T v, T dt, int j) {
+    T a, b;
+    hh_rate_pair<T>(v, j, a, b);
+    const T xinf = a / (a + b);
+    return xinf + (x - xinf) * dexp(-dt * (a + b));
+}
+
+// The three gates of HH slot k (the gates are independent of each other).
 template <class T>
 __device__ inline void gate_update(const DevNet &d, uint32_t k, double vnew, const GateView<T> &gv) {
     const uint32_t j0 = k - gv.base;
     const T v = (T)vnew;
     const T dt = (T)d.dt;
-    T r[6];
-    hh_rates<T>(v, r);
-    T *x[3] = {gv.m + j0, gv.h + j0, gv.n + j0};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const T a = r[2 * j], b = r[2 * j + 1];
-        const T xinf = a / (a + b);
-        *x[j] = xinf + (*x[j] - xinf) * dexp(-dt * (a + b));
-    }
+    gv.m[j0] = gate_next<T>(gv.m[j0], v, dt, 0);
+    gv.h[j0] = gate_next<T>(gv.h[j0], v, dt, 1);
+    gv.n[j0] = gate_next<T>(gv.n[j0], v, dt, 2);
 }
 
 // --------------------------------------------------------------- flags
@@ -190,21 +207,25 @@ __device__ __forceinline__ bool ev_before(const Event &a, const Event &b) {
     return a.port < b.port;
 }
 
-// Applies one event (synapse s, port, weight w) to the synapse state.
+// Applies one event (synapse s, port, weight w) to the synapse state;
+// returns the conductance added (0 for the calcium port).
 template <class T>
-__device__ __forceinline__ void apply_event(const DevNet &d, uint32_t s, uint32_t port, double w,
-                                            const SynView<T> &sv, const SynConst<T> &sc) {
+__device__ __forceinline__ T apply_event(const DevNet &d, uint32_t s, uint32_t port, double w,
+                                         const SynView<T> &sv, const SynConst<T> &sc) {
     const uint32_t j = s - sv.base;
     if (port == 1) {
+        T dg;
         if (sc.kind[s - sc.base] == 1) {
             const double h0 = d.stc.h0;
-            sv.g[j] = sv.g[j] + (T)(w * ((sv.h[j] + h0 * sv.z[j]) / h0));
+            dg = (T)(w * ((sv.h[j] + h0 * sv.z[j]) / h0));
         } else {
-            sv.g[j] = sv.g[j] + (T)w;
+            dg = (T)w;
         }
-    } else {
-        sv.c[j] = sv.c[j] + (T)d.stc.c_pre;
+        sv.g[j] = sv.g[j] + dg;
+        return dg;
     }
+    sv.c[j] = sv.c[j] + (T)d.stc.c_pre;
+    return T(0);
 }
 
 // Sorts the cnt events of a ring slot in place into delivery order.
@@ -346,12 +367,67 @@ __device__ inline void cv_current(const DevNet &d, int32_t k, const double *P, d
     Gout = G;
 }
 
+// Membrane current and dI/dV of one CV from HH (slot k, -1 if none), the
+// CV's summed synaptic conductance gs = sum g and gs_e = sum g E (so that
+// sum g (v - E) = gs v - gs_e), then its clamps active at t_n.
+template <class T>
+__device__ inline void cv_current_sums(const DevNet &d, int32_t k, const double *P, double sca, double v, double tn,
+                                       const GateView<T> &gv, double gs, double gs_e, uint32_t cl0, uint32_t cl1,
+                                       double &Iout, double &Gout) {
+    double I = 0.0, G = 0.0;
+    if (k >= 0) {
+        const uint32_t j = (uint32_t)k - gv.base;
+        const double m = (double)gv.m[j];
+        const double hh = (double)gv.h[j];
+        const double nn = (double)gv.n[j];
+        const double gna = P[0] * m * m * m * hh;
+        const double gk = P[1] * nn * nn * nn * nn;
+        const double idens = gna * (v - P[3]) + gk * (v - P[4]) + P[2] * (v - P[5]);
+        I = sca * idens;
+        G = sca * (gna + gk + P[2]);
+    }
+    I += gs * v - gs_e;
+    G += gs;
+    for (uint32_t q = cl0; q < cl1; ++q) {
+        if (d.cl_t0[q] <= tn && tn < d.cl_t0[q] + d.cl_dur[q]) I -= d.cl_amp[q];
+    }
+    Iout = I;
+    Gout = G;
+}
+
 // Orders the LDS accesses of the lanes of one wavefront (a barrier among
 // the wavefront's own lanes).
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum of x over the 64 lanes of a wavefront with data-parallel-primitive
+// lane shifts (no LDS traffic): an inclusive scan inside each row of 16
+// lanes (shifts by 1, 2, 4, 8), then row 0's total added into row 1 and
+// row 2's into row 3, then the first half's total into the second half;
+// lane 63 ends with the sum, which is broadcast.  The summation order is
+// fixed, so the result is deterministic.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_shift_add(double x) {
+    const uint64_t u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+    return x + __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+    x = dpp_shift_add<0x111, 0xf>(x);  // row_shr:1
+    x = dpp_shift_add<0x112, 0xf>(x);  // row_shr:2
+    x = dpp_shift_add<0x114, 0xf>(x);  // row_shr:4
+    x = dpp_shift_add<0x118, 0xf>(x);  // row_shr:8
+    x = dpp_shift_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x = dpp_shift_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    const uint64_t u = __double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // --------------------------------------------------------------- cable
@@ -533,13 +609,14 @@ __device__ inline bool seg_forward(const double *D, const double *B, double *V, 
 // Conductance decay, then for tagging-and-capture synapses one step of
 // Eqs. 17-20 from step-start h, z, c and the cell's step-start p.  If the
 // cell fired in the previous step, the post-synaptic calcium jump is added
-// first (after this step's events, as in the sequential definition).
-// Returns |h - h0| of step start (0 for plain synapses).
+// first (after this step's events, as in the sequential definition).  The
+// decayed conductance goes to gout (sv.g itself, or the other half of a
+// double buffer).  Returns |h - h0| of step start (0 for plain synapses).
 template <class T>
 __device__ inline double syn_update(const DevNet &d, uint32_t s, uint64_t n, double p, bool post,
-                                    const SynView<T> &sv, const SynConst<T> &sc) {
+                                    const SynView<T> &sv, const SynConst<T> &sc, T *gout) {
     const uint32_t j = s - sv.base, jc = s - sc.base;
-    sv.g[j] = sv.g[j] * sc.decay[jc];
+    gout[j] = sv.g[j] * sc.decay[jc];
     if (sc.kind[jc] != 1) return 0.0;
     const Stc &P = d.stc;
     T c = sv.c[j];

@@ -131,7 +131,8 @@ __global__ void k_syn(DevNet d, uint64_t n) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.n_syn) return;
     const uint32_t cell = d.syn_cell[s];
-    (void)syn_update<T>(d, s, n, d.p[cell], d.post[cell] != 0, global_syn<T>(d), global_const<T>(d));
+    const SynView<T> sv = global_syn<T>(d);
+    (void)syn_update<T>(d, s, n, d.p[cell], d.post[cell] != 0, sv, global_const<T>(d), sv.g);
 }
 
 // ----------------------------------------------------------------- cells

@@ -5,19 +5,23 @@
 // that caused it.  Within an epoch every cell therefore evolves on its own:
 // a workgroup owns a packed run of consecutive cells (their CVs, HH CVs
 // and synapses are contiguous in memory) and advances them through all K
-// steps of the epoch, synchronising only with __syncthreads between the
-// stages of a step.  The per-cell serial work (Hines elimination, the
-// protein trigger sum, event delivery) reads and writes the cable system in
-// LDS: voltage, diagonal, right-hand side, axial conductance, parent, the
-// |h - h0| terms and the per-cell p stay on chip for the whole epoch.
+// steps of the epoch with their state and constants held in LDS.
 //
-// Every stage calls the same device functions as the plain form in the
-// same order, so the two forms give bitwise identical results.
+// Wavefronts take one of two roles for the whole epoch.  Solver wavefronts
+// own a share of the cells' CVs: currents and assembly, the cable solve,
+// the HH gates and spike detection.  Synapse wavefronts own a share of the
+// cells' synapses: decay and plasticity, the protein trigger sum and p,
+// the delivery of the next step's events and, in the mixed form, the next
+// step's per-CV conductance sums.  The two chains of a step only meet
+// through the synaptic conductance (double-buffered: step n reads one half
+// while the synapse wavefronts write step n+1 into the other) and the
+// post-synaptic flag (also double-buffered), so a step needs one workgroup
+// barrier.  A 64-lane workgroup plays both roles in turn.
 //
 // The host part packs cells into workgroups under an LDS budget and picks
-// the number of cells per workgroup by timing trial epochs (autotuning),
-// then captures a graph of several epochs (inject, fused step kernel,
-// expand, close) that the advance loop replays.
+// the workgroup size, cells per workgroup and the split of roles by timing
+// trial epochs (autotuning), then captures a graph of several epochs (fused
+// step kernel, spike exchange) that the advance loop replays.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,28 +37,26 @@
 
 namespace pa {
 
-// LDS layout of a workgroup owning nv CVs, ns synapses, nh HH CVs and nc
-// cells for an epoch of at most K steps; gates, conductance, calcium and
-// decay factors take tsize bytes.  The same arithmetic sizes the launch on
-// the host and places the arrays on the device.
+// LDS layout of a workgroup owning nv CVs, ns synapses, nh HH CVs, nc cells
+// and ng branch segments for an epoch of at most K steps; gates,
+// conductance, calcium and decay factors take tsize bytes (4 selects the
+// mixed form).  The same arithmetic sizes the launch on the host and places
+// the arrays on the device.
 struct FusedLayout {
     // doubles
-    uint32_t V, D, B, Ax, D0, Cdt, Gpe, H, Z, Erev, Abs, P, Vold;
+    uint32_t V, D, B, Ax, D0, Cdt, Gpe, DecCv, H, Z, Erev, P, Vold, Cu, Cb, HHp;
+    // mixed form: per-CV conductance sums (two halves) and the cyclic
+    // reduction's published lower, upper, right-hand side and inverse
+    // diagonal (two halves)
+    uint32_t Gs, GsE, Xa, Xc, Xr, Xi;
     // T
     uint32_t G, C, Dec, M, HH, N;
     // 32-bit
-    uint32_t Par, HHk, CvSyn, CvCl, Cb0, Cs0, Det, HHcv, EvN, EvOff, Scan;
+    uint32_t Par, HHk, CvSyn, CvCl, Cb0, Cs0, Cg0, Ch0, Det, HHcv, EvN, EvOff, Scan;
     // events of the epoch, each slot's records sorted into delivery order
     uint32_t EvBuf, ev_cap;
     // 16-bit, 8-bit
-    uint32_t SynCell, Run, Kind, Post;
-    // branch segments
-    uint32_t Cu, Cb, SegA, SegB, SegCell, KidOff, Kids, SegLvl;
-    // HH constants: 6 channel parameters and the area factor per HH CV
-    uint32_t HHp;
-    // cyclic-reduction work arrays (mixed form): lower, upper, and a second
-    // copy of lower, diagonal, upper, right-hand side
-    uint32_t Pa, Pc, Qa, Qd, Qc, Qr;
+    uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, Kind, Post, SegLvl;
     uint32_t total;
     __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
                                     uint32_t tsize, uint32_t ng) {
@@ -67,96 +69,189 @@ struct FusedLayout {
         };
         V = take(8 * nv, 16); D = take(8 * nv, 8); B = take(8 * nv, 8); Ax = take(8 * nv, 8);
         D0 = take(8 * nv, 8); Cdt = take(8 * nv, 8); Gpe = take(8 * nv, 8);
-        H = take(8 * ns, 8); Z = take(8 * ns, 8); Erev = take(8 * ns, 8); Abs = take(8 * ns, 8);
+        DecCv = take(8 * (tsize == 4 ? nv : 0), 8);
+        H = take(8 * ns, 8); Z = take(8 * ns, 8); Erev = take(8 * ns, 8);
         P = take(8 * nc, 8); Vold = take(8 * nc, 8);
-        G = take(tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
+        Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
+        const uint32_t nm = tsize == 4 ? nv : 0;
+        Gs = take(16 * nm, 8); GsE = take(16 * nm, 8);
+        Xa = take(16 * nm, 8); Xc = take(16 * nm, 8); Xr = take(16 * nm, 8); Xi = take(16 * nm, 8);
+        G = take(2 * tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
         M = take(tsize * nh, 8); HH = take(tsize * nh, 8); N = take(tsize * nh, 8);
         Par = take(4 * nv, 4); HHk = take(4 * nv, 4); CvSyn = take(4 * (nv + 1), 4);
         CvCl = take(4 * (nv + 1), 4); Cb0 = take(4 * (nc + 1), 4); Cs0 = take(4 * (nc + 1), 4);
+        Cg0 = take(4 * (nc + 1), 4); Ch0 = take(4 * (nc + 1), 4);
         Det = take(4 * nc, 4); HHcv = take(4 * nh, 4); EvN = take(4 * nc * K, 4);
-        EvOff = take(4 * nc * K, 4); Scan = take(4 * 257, 4);
+        EvOff = take(4 * nc * K, 4); Scan = take(4, 4);
         ev_cap = 2 * nc * K + 32;
         EvBuf = take(32 * ev_cap, 16);
-        Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
-        const uint32_t np = tsize == 4 ? nv : 0;
-        Pa = take(8 * np, 8); Pc = take(8 * np, 8); Qa = take(8 * np, 8); Qd = take(8 * np, 8);
-        Qc = take(8 * np, 8); Qr = take(8 * np, 8);
-        SynCell = take(2 * ns, 2); Run = take(2 * nv, 2);
+        SynCv = take(2 * (tsize == 4 ? ns : 0), 2);
         SegA = take(2 * ng, 2); SegB = take(2 * ng, 2); SegCell = take(2 * ng, 2);
         KidOff = take(2 * (ng + 1), 2); Kids = take(2 * ng, 2);
-        Kind = take(ns, 1); Post = take(nc, 1); SegLvl = take(ng, 1);
+        Kind = take(ns, 1); Post = take(2 * nc, 1); SegLvl = take(ng, 1);
         total = (o + 15) / 16 * 16;
     }
 };
 
 #ifdef PA_STAGE_TIMING
-// Diagnostic build only: wall-clock ticks per stage summed over workgroups.
-__device__ unsigned long long pa_stage_ticks[8];
+// Diagnostic build only: wall-clock ticks per stage, summed over the solver
+// wavefronts (entries 0-7) and the synapse wavefronts (8-15).
+__device__ unsigned long long pa_stage_ticks[16];
 #define STAGE_INIT() uint64_t st_prev_ = wall_clock64(); uint64_t st_acc_[8] = {0, 0, 0, 0, 0, 0, 0, 0}
-#define STAGE_MARK(k_) do { if (tid == 0) { const uint64_t t_ = wall_clock64(); st_acc_[k_] += t_ - st_prev_; st_prev_ = t_; } } while (0)
-#define STAGE_FLUSH() do { if (tid == 0) for (int k_ = 0; k_ < 8; ++k_) atomicAdd(&pa_stage_ticks[k_], (unsigned long long)st_acc_[k_]); } while (0)
+#define STAGE_MARK(k_) do { if (lane == 0) { const uint64_t t_ = wall_clock64(); st_acc_[k_] += t_ - st_prev_; st_prev_ = t_; } } while (0)
+#define STAGE_FLUSH() do { if (lane == 0) for (int k_ = 0; k_ < 8; ++k_) atomicAdd(&pa_stage_ticks[k_ + (solver ? 0 : 8)], (unsigned long long)st_acc_[k_]); } while (0)
 #else
 #define STAGE_INIT() do {} while (0)
 #define STAGE_MARK(k_) do {} while (0)
 #define STAGE_FLUSH() do {} while (0)
 #endif
 
-__device__ __forceinline__ double wave_sum_down(double x) {
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+    for (int off = 32; off >= 1; off >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, off, 64));
     return x;
+}
+
+// Number of cells c < nc with off[c] < t (off increasing), over the lanes of
+// one wavefront.
+__device__ __forceinline__ uint32_t count_below(const uint32_t *off, uint32_t nc, uint32_t t, uint32_t lane) {
+    uint32_t cnt = 0;
+    for (uint32_t b = 0; b < nc; b += 64) {
+        const uint32_t c = b + lane;
+        cnt += (uint32_t)__popcll(__ballot(c < nc && off[c] < t));
+    }
+    return cnt;
+}
+
+// Cells [lo, hi) of part `part` of `parts` when the cells are split by the
+// running count off[] (CVs or synapses) of total `tot`: a cell belongs to the
+// part its first element falls in; the last part takes the rest.
+__device__ __forceinline__ void split_cells(const uint32_t *off, uint32_t nc, uint32_t tot, uint32_t part,
+                                            uint32_t parts, uint32_t lane, uint32_t &lo, uint32_t &hi) {
+    lo = part == 0 ? 0u : count_below(off, nc, (uint32_t)((uint64_t)tot * part / parts), lane);
+    hi = part + 1 == parts ? nc : count_below(off, nc, (uint32_t)((uint64_t)tot * (part + 1) / parts), lane);
+}
+
+// FP64 parallel cyclic reduction of the tridiagonal systems of the
+// unbranched cells whose CVs are [va, vb) (at most 64 NPL), on the lanes of
+// one wavefront, lane l holding CVs va + l + 64 j.  Equal to the elimination
+// up to rounding.  In each of `levels` rounds every node publishes its
+// lower and upper coupling, right-hand side and inverse diagonal (two
+// alternating halves of xa, xc, xr, xi), then folds in its neighbours at
+// distance 2^k; a zero coupling marks the end of a cell, so neighbours
+// never cross cells.  Writes V = x.
+template <uint32_t NPL>
+__device__ __forceinline__ bool pcr_cells(const DevNet &d, uint32_t va, uint32_t vb, uint32_t nv, uint32_t levels,
+                                          uint32_t lane, const int32_t *par, const double *ax, const double *D,
+                                          const double *B, double *V, double *xa, double *xc, double *xr,
+                                          double *xi) {
+    double ra[NPL], rc[NPL], rd[NPL], rr[NPL];
+#pragma unroll
+    for (uint32_t j = 0; j < NPL; ++j) {
+        const uint32_t i = va + lane + 64 * j;
+        const bool act = i < vb;
+        const uint32_t ic = act ? i : va;
+        const bool up = act && i + 1 < vb && par[ic + (i + 1 < vb ? 1 : 0)] == (int32_t)i;
+        const double axi = ax[ic], axn = ax[i + 1 < vb ? i + 1 : ic];
+        ra[j] = act && par[ic] >= 0 ? -axi : 0.0;
+        rc[j] = up ? -axn : 0.0;
+        rd[j] = act ? D[ic] : 1.0;
+        rr[j] = act ? B[ic] : 0.0;
+    }
+    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) {
+        const uint32_t h = (k & 1u) * nv;
+#pragma unroll
+        for (uint32_t j = 0; j < NPL; ++j) {
+            const uint32_t i = va + lane + 64 * j;
+            if (i < vb) {
+                xa[h + i] = ra[j];
+                xc[h + i] = rc[j];
+                xr[h + i] = rr[j];
+                xi[h + i] = qdiv<false>(1.0, rd[j]);
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (uint32_t j = 0; j < NPL; ++j) {
+            const uint32_t i = va + lane + 64 * j;
+            const bool act = i < vb;
+            const bool hm = act && ra[j] != 0.0 && i >= va + sft;
+            const bool hp = act && rc[j] != 0.0 && i + sft < vb;
+            const uint32_t im = h + (hm ? i - sft : va), ip = h + (hp ? i + sft : va);
+            const double ima = xi[im], am = xa[im], cm = xc[im], rm = xr[im];
+            const double ipa = xi[ip], ap = xa[ip], cp = xc[ip], rp = xr[ip];
+            const double al = -ra[j] * ima, ga = -rc[j] * ipa;
+            const double d1 = hm ? rd[j] + al * cm : rd[j];
+            const double r1 = hm ? rr[j] + al * rm : rr[j];
+            rd[j] = hp ? d1 + ga * ap : d1;
+            rr[j] = hp ? r1 + ga * rp : r1;
+            ra[j] = hm ? al * am : 0.0;
+            rc[j] = hp ? ga * cp : 0.0;
+        }
+    }
+    bool ok = true;
+#pragma unroll
+    for (uint32_t j = 0; j < NPL; ++j) {
+        const uint32_t i = va + lane + 64 * j;
+        if (i < vb) {
+            const double v = qdiv<false>(rr[j], rd[j]);
+            V[i] = v;
+            ok = ok && isfinite(v);
+        }
+    }
+    return ok;
 }
 
 // One epoch of nsteps (<= K) steps for the cells blk[b] .. blk[b+1]-1 of
 // workgroup b.  Mutable state of those cells (V, gates, g, c, h, z, p, post
-// flag), their constants and the epoch's event counts live in LDS, so a
-// step touches global memory only for events, spikes and rare noise keys.
+// flag), their constants and the epoch's events live in LDS, so a step
+// touches global memory only for spikes, clamps and rare noise keys.
 template <class T, uint32_t BS>
-__global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk,
-                                              const uint32_t *__restrict__ blk_lvl, uint32_t nsteps) {
+__global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk, uint32_t nsteps,
+                                              uint32_t solver_waves) {
     extern __shared__ double lds[];
     uint8_t *L = (uint8_t *)lds;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
     constexpr uint32_t NW = BS / 64;
+    constexpr bool EXACT = sizeof(T) == 8;
     const uint32_t c0 = blk[blockIdx.x], c1 = blk[blockIdx.x + 1];
     const uint32_t ncb = c1 - c0;
     const uint32_t v0 = d.cv_off[c0], nv = d.cv_off[c1] - v0;
     const uint32_t s0 = d.syn_off[c0], ns = d.syn_off[c1] - s0;
     const uint32_t k0 = d.hh_off[c0], nhh = d.hh_off[c1] - k0;
     const uint32_t g0 = d.seg_off[c0], ng = d.seg_off[c1] - g0;
-    const uint32_t nlev = blk_lvl[blockIdx.x];
     const uint32_t K = d.K;
-    constexpr bool EXACT = sizeof(T) == 8;
+    // roles: wavefronts 0 .. SW-1 solve, SW .. NW-1 update synapses
+    const uint32_t SW = NW == 1 ? 1u : min(max(solver_waves, 1u), NW - 1);
+    const bool solver = wave < SW;
+    const bool synw = NW == 1 || wave >= SW;
     const FusedLayout lay(nv, ns, nhh, ncb, K, sizeof(T), ng);
     double *sV = (double *)(L + lay.V), *sD = (double *)(L + lay.D), *sB = (double *)(L + lay.B);
     double *sAx = (double *)(L + lay.Ax), *sD0 = (double *)(L + lay.D0), *sCdt = (double *)(L + lay.Cdt);
     double *sGpe = (double *)(L + lay.Gpe), *sH = (double *)(L + lay.H), *sZ = (double *)(L + lay.Z);
-    double *sErev = (double *)(L + lay.Erev), *sAbs = (double *)(L + lay.Abs);
+    double *sErev = (double *)(L + lay.Erev);
     double *sP = (double *)(L + lay.P), *sVold = (double *)(L + lay.Vold);
+    double *sGs = (double *)(L + lay.Gs), *sGsE = (double *)(L + lay.GsE);
+    double *sDecCv = (double *)(L + lay.DecCv);
+    uint16_t *sSynCv = (uint16_t *)(L + lay.SynCv);
     T *sG = (T *)(L + lay.G), *sC = (T *)(L + lay.C), *sDec = (T *)(L + lay.Dec);
     T *sM = (T *)(L + lay.M), *sHH = (T *)(L + lay.HH), *sN = (T *)(L + lay.N);
     int32_t *sPar = (int32_t *)(L + lay.Par), *sHHk = (int32_t *)(L + lay.HHk);
     uint32_t *sCvSyn = (uint32_t *)(L + lay.CvSyn), *sCvCl = (uint32_t *)(L + lay.CvCl);
     uint32_t *sCb0 = (uint32_t *)(L + lay.Cb0), *sCs0 = (uint32_t *)(L + lay.Cs0);
+    uint32_t *sCg0 = (uint32_t *)(L + lay.Cg0), *sCh0 = (uint32_t *)(L + lay.Ch0);
     uint32_t *sDet = (uint32_t *)(L + lay.Det), *sHHcv = (uint32_t *)(L + lay.HHcv);
     uint32_t *sEvN = (uint32_t *)(L + lay.EvN), *sEvOff = (uint32_t *)(L + lay.EvOff);
     uint32_t *sScan = (uint32_t *)(L + lay.Scan);
-    uint16_t *sSynCell = (uint16_t *)(L + lay.SynCell), *sRun = (uint16_t *)(L + lay.Run);
     uint8_t *sKind = L + lay.Kind, *sPost = L + lay.Post, *sSegLvl = L + lay.SegLvl;
     double *sCu = (double *)(L + lay.Cu), *sCb = (double *)(L + lay.Cb), *sHHp = (double *)(L + lay.HHp);
     uint16_t *sSegA = (uint16_t *)(L + lay.SegA), *sSegB = (uint16_t *)(L + lay.SegB);
     uint16_t *sSegCell = (uint16_t *)(L + lay.SegCell), *sKidOff = (uint16_t *)(L + lay.KidOff);
     uint16_t *sKids = (uint16_t *)(L + lay.Kids);
+    Event *sEv = (Event *)(L + lay.EvBuf);
     // blocks whose cells are all unbranched (one segment per cell)
     const bool chains = (ng == ncb);
-    uint32_t pcr_steps = 0;
-    if (!EXACT && chains) {
-        uint32_t len = 1;
-        for (uint32_t c = 0; c < ncb; ++c) len = max(len, d.cv_off[c0 + c + 1] - d.cv_off[c0 + c]);
-        while ((1u << pcr_steps) < len) ++pcr_steps;
-    }
-    const SynView<T> sv{sG, sC, sH, sZ, s0};
     const SynConst<T> sc{sErev, sDec, sKind, s0};
     const GateView<T> gv{sM, sHH, sN, k0};
     const uint64_t n0 = d.ctr->step;
@@ -172,10 +267,10 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         sGpe[i] = d.gpas_e[g];
         const int32_t p = d.parent[g];
         sPar[i] = p < 0 ? -1 : p - (int32_t)v0;
-        sRun[i] = d.run[g];
         sHHk[i] = d.hh_of[g];
         sCvSyn[i] = d.cv_syn_off[g];
         sCvCl[i] = d.cv_cl_off[g];
+        if constexpr (!EXACT) sDecCv[i] = d.cv_dec[g];
         if (i == nv - 1) {
             sCvSyn[nv] = d.cv_syn_off[g + 1];
             sCvCl[nv] = d.cv_cl_off[g + 1];
@@ -188,10 +283,10 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         sH[s] = d.h[q];
         sZ[s] = d.z[q];
         sErev[s] = d.syn_erev[q];
-        if constexpr (sizeof(T) == 8) sDec[s] = (T)d.syn_decay[q];
+        if constexpr (EXACT) sDec[s] = (T)d.syn_decay[q];
         else sDec[s] = d.syn_decay_f[q];
         sKind[s] = d.syn_kind[q];
-        sSynCell[s] = (uint16_t)(d.syn_cell[q] - c0);
+        if constexpr (!EXACT) sSynCv[s] = (uint16_t)(d.syn_cv[q] - v0);
     }
     for (uint32_t k = tid; k < nhh; k += BS) {
         sM[k] = ((const T *)d.gm)[k0 + k];
@@ -204,6 +299,8 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     for (uint32_t c = tid; c <= ncb; c += BS) {
         sCb0[c] = d.cv_off[c0 + c] - v0;
         sCs0[c] = d.syn_off[c0 + c] - s0;
+        sCg0[c] = d.seg_off[c0 + c] - g0;
+        sCh0[c] = d.hh_off[c0 + c] - k0;
         if (c < ncb) {
             sP[c] = d.p[c0 + c];
             sPost[c] = d.post[c0 + c];
@@ -238,7 +335,6 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     // sorted in place in the ring); the delivery statistics are counted
     // here, in parallel
     const uint32_t nslot = ncb * nsteps;
-    Event *sEv = (Event *)(L + lay.EvBuf);
     for (uint32_t x = tid; x < nslot; x += BS) {
         const uint32_t c = x / nsteps, st = x - c * nsteps;
         const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
@@ -264,172 +360,214 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
             atomicAdd(&d.ev_sum[2 * sy + po - 1], (unsigned long long)(n0 + st));
         }
     }
-    unsigned long long delivered = 0;
     __syncthreads();
     STAGE_MARK(6);
 
-    // protein trigger sum of step m (one wavefront per cell: strided lane
-    // sums, then a fixed shuffle tree), protein synthesis, detection
-    auto stage_e = [&](uint64_t m) {
-        for (uint32_t c = wave; c < ncb; c += NW) {
-            const uint32_t a = sCs0[c], e = sCs0[c + 1];
-            double S = 0.0;
-            for (uint32_t s = a + lane; s < e; s += 64) S += sAbs[s];
-            S = wave_sum_down(S);
-            if (lane == 0) {
-                sP[c] = prp_next(d, sP[c], S);
-                sPost[c] = detect(d, c0 + c, m, sVold[c], sV[sDet[c]]) ? 1 : 0;
+    // the cells of this wavefront: a solver wavefront's share split by CV
+    // count, a synapse wavefront's share split by synapse count
+    uint32_t wc0 = 0, wc1 = 0, uc0 = 0, uc1 = 0;
+    if (solver) split_cells(sCb0, ncb, nv, wave, SW, lane, wc0, wc1);
+    if (synw) {
+        const uint32_t nu = NW == 1 ? 1u : NW - SW, u = NW == 1 ? 0u : wave - SW;
+        split_cells(sCs0, ncb, ns, u, nu, lane, uc0, uc1);
+    }
+    const uint32_t wva = sCb0[wc0], wvb = sCb0[wc1], wga = sCg0[wc0], wgb = sCg0[wc1];
+    const uint32_t wha = sCh0[wc0], whb = sCh0[wc1];
+    const uint32_t uva = sCb0[uc0], uvb = sCb0[uc1];
+    // branch levels of the solver share, and cyclic-reduction steps for its
+    // longest cell
+    uint32_t wlev = 0, wlen = 1;
+    for (uint32_t g = wga + lane; g < wgb; g += 64) wlev = max(wlev, (uint32_t)sSegLvl[g] + 1u);
+    for (uint32_t c = wc0 + lane; c < wc1; c += 64) wlen = max(wlen, sCb0[c + 1] - sCb0[c]);
+    wlev = wave_max(wlev);
+    wlen = wave_max(wlen);
+    uint32_t wpcr = 0;
+    while ((1u << wpcr) < wlen) ++wpcr;
+    constexpr uint32_t PCR_NPL = 4;  // CVs per lane held in registers
+    const bool use_pcr = !EXACT && chains && wvb - wva <= 64 * PCR_NPL;
+    unsigned long long delivered = 0;
+
+    // mixed form with one decay factor per CV: the per-CV conductance sums
+    // are carried from step to step (decayed, plus each event's increment)
+    // instead of being summed again
+    const bool carry_sums = !EXACT && d.cv_dec_uniform != 0;
+    // events of step index st (relative to n0) of the synapse share's cells
+    // into conductance half gh (and, when carried, sum half `half`), in
+    // delivery order
+    auto deliver = [&](uint32_t st, T *gh, uint32_t half) {
+        const SynView<T> sv{gh, sC, sH, sZ, s0};
+        for (uint32_t c = uc0 + lane; c < uc1; c += 64) {
+            const uint32_t cnt = sEvN[c * K + st];
+            if (!cnt) continue;
+            const uint32_t off = sEvOff[c * K + st];
+            const Event *ev = off != 0xffffffffu
+                                  ? sEv + off
+                                  : d.ev + ((uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R)) * d.Q;
+            for (uint32_t i = 0; i < cnt; ++i) {
+                const uint32_t sy = ev[i].syn;
+                const T dg = apply_event<T>(d, sy, ev[i].port, ev[i].w, sv, sc);
+                if (carry_sums && dg != T(0)) {
+                    const uint32_t q = sy - s0, cv = sSynCv[q];
+                    sGs[half * nv + cv] += (double)dg;
+                    sGsE[half * nv + cv] += (double)dg * sErev[q];
+                }
             }
+            delivered += cnt;
         }
     };
+    // mixed form: summed conductance and conductance x reversal potential
+    // of every CV of the synapse share, from conductance half gh
+    auto cv_sums = [&](const T *gh, uint32_t half) {
+        for (uint32_t i = uva + lane; i < uvb; i += 64) {
+            double gs = 0.0, ge = 0.0;
+            for (uint32_t q = sCvSyn[i] - s0; q < sCvSyn[i + 1] - s0; ++q) {
+                const double g = (double)gh[q];
+                gs += g;
+                ge += g * sErev[q];
+            }
+            sGs[half * nv + i] = gs;
+            sGsE[half * nv + i] = ge;
+        }
+    };
+
+    // the first step's events, and its conductance sums
+    if (synw) {
+        deliver(0, sG, 0);
+        if constexpr (!EXACT) {
+            wave_sync();
+            cv_sums(sG, 0);
+        }
+    }
+    __syncthreads();
 
     for (uint32_t st = 0; st < nsteps; ++st) {
         const uint64_t n = n0 + st;
         const double tn = (double)n * d.dt;
-        // A. events due at step n, already in delivery order; the protein
-        //    update and detection of step n-1 (independent of them)
-        for (uint32_t c = tid; c < ncb; c += BS) {
-            const uint32_t cnt = sEvN[c * K + st];
-            if (!cnt) continue;
-            const uint32_t off = sEvOff[c * K + st];
-            const Event *ev = off != 0xffffffffu ? sEv + off
-                                                 : d.ev + ((uint64_t)(c0 + c) * d.R + (uint32_t)(n % d.R)) * d.Q;
-            for (uint32_t i = 0; i < cnt; ++i) apply_event<T>(d, ev[i].syn, ev[i].port, ev[i].w, sv, sc);
-            delivered += cnt;
-        }
-        if (st > 0) stage_e(n - 1);
-        __syncthreads();
-        STAGE_MARK(0);
-        // B. currents at V^n and assembly of the cable system
-        for (uint32_t i = tid; i < nv; i += BS) {
-            const double v = sV[i];
-            double I, G;
-            const int32_t hk = sHHk[i];
-            const double *P = hk >= 0 ? sHHp + 7 * (hk - (int32_t)k0) : nullptr;
-            cv_current<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, sv, sc, sCvSyn[i], sCvSyn[i + 1], sCvCl[i],
-                          sCvCl[i + 1], I, G);
-            sD[i] = sD0[i] + G;
-            sB[i] = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
-        }
-        __syncthreads();
-        STAGE_MARK(1);
-        // C. Hines elimination on wavefront 0, level-scheduled over branch
-        //    segments: the segments of one level are eliminated in parallel
-        //    lanes, deepest level first; a branch point takes its children's
-        //    contributions in descending child order, as in the sequential
-        //    elimination.  Meanwhile the other wavefronts update the synapses
-        //    (decay, post-synaptic hook, plasticity from step-start values),
-        //    which do not depend on the new voltage.
-        if (wave == 0 && !EXACT && chains) {
-            // mixed form, unbranched cells: parallel cyclic reduction of each
-            // cell's tridiagonal system across the wavefront's lanes (FP64;
-            // equal to the elimination up to rounding)
-            double *pa = (double *)(L + lay.Pa), *pc = (double *)(L + lay.Pc);
-            double *qa = (double *)(L + lay.Qa), *qd = (double *)(L + lay.Qd);
-            double *qc = (double *)(L + lay.Qc), *qr = (double *)(L + lay.Qr);
-            for (uint32_t c = lane; c < ncb; c += 64) sVold[c] = sV[sDet[c]];
-            for (uint32_t i = lane; i < nv; i += 64) {
-                pa[i] = sPar[i] >= 0 ? -sAx[i] : 0.0;
-                pc[i] = (i + 1 < nv && sPar[i + 1] == (int32_t)i) ? -sAx[i + 1] : 0.0;
+        const uint32_t cur = st & 1u, nxt = cur ^ 1u;
+        T *gc = sG + cur * ns, *gn = sG + nxt * ns;
+        uint8_t *postc = sPost + cur * ncb, *postn = sPost + nxt * ncb;
+        STAGE_MARK(5);
+        if (solver) {
+            // currents at V^n and assembly of the cable system
+            const SynView<T> svc{gc, sC, sH, sZ, s0};
+            for (uint32_t i = wva + lane; i < wvb; i += 64) {
+                const double v = sV[i];
+                double I, G;
+                const int32_t hk = sHHk[i];
+                const double *P = hk >= 0 ? sHHp + 7 * (hk - (int32_t)k0) : nullptr;
+                if constexpr (EXACT)
+                    cv_current<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, svc, sc, sCvSyn[i], sCvSyn[i + 1],
+                                  sCvCl[i], sCvCl[i + 1], I, G);
+                else
+                    cv_current_sums<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, sGs[cur * nv + i],
+                                       sGsE[cur * nv + i], sCvCl[i], sCvCl[i + 1], I, G);
+                sD[i] = sD0[i] + G;
+                sB[i] = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
+            }
+            for (uint32_t c = wc0 + lane; c < wc1; c += 64) sVold[c] = sV[sDet[c]];
+            wave_sync();
+            STAGE_MARK(0);
+            // the cable solve of the share's cells
+            if (wva == wvb) {
+                // no cells of this share
+            } else if (use_pcr) {
+                // unbranched cells, mixed form: cyclic reduction on the lanes
+                double *xa = (double *)(L + lay.Xa), *xc = (double *)(L + lay.Xc);
+                double *xr = (double *)(L + lay.Xr), *xi = (double *)(L + lay.Xi);
+                const bool ok = wvb - wva <= 64
+                                    ? pcr_cells<1>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr, xi)
+                                    : pcr_cells<PCR_NPL>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr,
+                                                         xi);
+                if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + wc0);
+            } else {
+                // Hines elimination level-scheduled over branch segments,
+                // deepest level first; a branch point takes its children's
+                // contributions in descending child order, as in the
+                // sequential elimination
+                for (int lv = (int)wlev - 1; lv >= 0; --lv) {
+                    for (uint32_t g = wga + lane; g < wgb; g += 64) {
+                        if (sSegLvl[g] != (uint32_t)lv) continue;
+                        const uint32_t a = sSegA[g], b = sSegB[g];
+                        double dc = sD[b], bc = sB[b];
+                        for (uint32_t q = sKidOff[g]; q < sKidOff[g + 1]; ++q) {
+                            const uint32_t kd = sKids[q];
+                            dc -= sCu[kd];
+                            bc -= sCb[kd];
+                        }
+                        seg_backward<EXACT>(sD, sB, sAx, a, b, dc, bc);
+                        if (sPar[a] >= 0) {
+                            const double u = -sAx[a];
+                            const double f = qdiv<EXACT>(u, dc);
+                            sCu[g] = f * u;
+                            sCb[g] = f * bc;
+                        }
+                    }
+                    wave_sync();
+                }
+                for (uint32_t lv = 0; lv < wlev; ++lv) {
+                    for (uint32_t g = wga + lane; g < wgb; g += 64) {
+                        if (sSegLvl[g] != lv) continue;
+                        const uint32_t a = sSegA[g], b = sSegB[g];
+                        const int32_t p = sPar[a];
+                        sV[a] = (p < 0) ? qdiv<EXACT>(sB[a], sD[a]) : qdiv<EXACT>(sB[a] - (-sAx[a]) * sV[p], sD[a]);
+                        if (!seg_forward<EXACT>(sD, sB, sV, sAx, a, b)) raise_flag(d, FLAG_NONFINITE, c0 + sSegCell[g]);
+                    }
+                    wave_sync();
+                }
             }
             wave_sync();
-            double *A = pa, *Dd = sD, *Cc = pc, *Rr = sB;
-            double *A2 = qa, *D2 = qd, *C2 = qc, *R2 = qr;
-            for (uint32_t k = 0, sft = 1; k < pcr_steps; ++k, sft <<= 1) {
-                for (uint32_t i = lane; i < nv; i += 64) {
-                    const double ai = A[i], ci = Cc[i];
-                    double na = 0.0, nc2 = 0.0, nd = Dd[i], nr = Rr[i];
-                    // neighbours at distance sft inside the same cell: a
-                    // nonzero coupling marks a neighbour
-                    if (ai != 0.0 && i >= sft) {
-                        const uint32_t im = i - sft;
-                        const double al = -qdiv<false>(ai, Dd[im]);
-                        na = al * A[im];
-                        nd += al * Cc[im];
-                        nr += al * Rr[im];
-                    }
-                    if (ci != 0.0 && i + sft < nv) {
-                        const uint32_t ip = i + sft;
-                        const double ga = -qdiv<false>(ci, Dd[ip]);
-                        nc2 = ga * Cc[ip];
-                        nd += ga * A[ip];
-                        nr += ga * Rr[ip];
-                    }
-                    A2[i] = na;
-                    D2[i] = nd;
-                    C2[i] = nc2;
-                    R2[i] = nr;
-                }
-                wave_sync();
-                double *t;
-                t = A; A = A2; A2 = t;
-                t = Dd; Dd = D2; D2 = t;
-                t = Cc; Cc = C2; C2 = t;
-                t = Rr; Rr = R2; R2 = t;
+            STAGE_MARK(1);
+            // HH gates at V^{n+1}, one lane per gate (the three gates of a
+            // CV are independent), and threshold detection
+            for (uint32_t t = lane; t < 3 * (whb - wha); t += 64) {
+                const uint32_t k = wha + t / 3, j = t % 3;
+                T *x = j == 0 ? sM + k : (j == 1 ? sHH + k : sN + k);
+                *x = gate_next<T>(*x, (T)sV[sHHcv[k]], (T)d.dt, (int)j);
             }
-            for (uint32_t i = lane; i < nv; i += 64) {
-                const double v = qdiv<false>(Rr[i], Dd[i]);
-                sV[i] = v;
-                if (!isfinite(v)) raise_flag(d, FLAG_NONFINITE, c0);
-            }
-        } else if (wave == 0) {
-            for (uint32_t c = lane; c < ncb; c += 64) sVold[c] = sV[sDet[c]];
-            for (int lv = (int)nlev - 1; lv >= 0; --lv) {
-                for (uint32_t g = lane; g < ng; g += 64) {
-                    if (sSegLvl[g] != (uint32_t)lv) continue;
-                    const uint32_t a = sSegA[g], b = sSegB[g];
-                    double dc = sD[b], bc = sB[b];
-                    for (uint32_t q = sKidOff[g]; q < sKidOff[g + 1]; ++q) {
-                        const uint32_t kd = sKids[q];
-                        dc -= sCu[kd];
-                        bc -= sCb[kd];
-                    }
-                    seg_backward<EXACT>(sD, sB, sAx, a, b, dc, bc);
-                    if (sPar[a] >= 0) {
-                        const double u = -sAx[a];
-                        const double f = qdiv<EXACT>(u, dc);
-                        sCu[g] = f * u;
-                        sCb[g] = f * bc;
-                    }
-                }
-                wave_sync();
-            }
-            for (uint32_t lv = 0; lv < nlev; ++lv) {
-                for (uint32_t g = lane; g < ng; g += 64) {
-                    if (sSegLvl[g] != lv) continue;
-                    const uint32_t a = sSegA[g], b = sSegB[g];
-                    const int32_t p = sPar[a];
-                    sV[a] = (p < 0) ? qdiv<EXACT>(sB[a], sD[a]) : qdiv<EXACT>(sB[a] - (-sAx[a]) * sV[p], sD[a]);
-                    if (!seg_forward<EXACT>(sD, sB, sV, sAx, a, b)) raise_flag(d, FLAG_NONFINITE, c0 + sSegCell[g]);
-                }
-                wave_sync();
-            }
+            for (uint32_t c = wc0 + lane; c < wc1; c += 64)
+                postn[c] = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]) ? 1 : 0;
+            STAGE_MARK(2);
         }
-        STAGE_MARK(7);
-        {
-            // synapses on wavefronts 1.. (all lanes when there is one wavefront)
-            const uint32_t first = NW > 1 ? 64u : 0u;
-            if (tid >= first) {
-                for (uint32_t s = tid - first; s < ns; s += BS - first) {
-                    const uint32_t cl = sSynCell[s];
-                    sAbs[s] = syn_update<T>(d, s0 + s, n, sP[cl], sPost[cl] != 0, sv, sc);
+        if (synw) {
+            // synapse updates of step n (from step-start values) with the
+            // cell's protein trigger sum: lane l sums the cell's synapses
+            // l, l+64, ..., then a fixed lane-shift tree; then p of the cell
+            const SynView<T> svc{gc, sC, sH, sZ, s0};
+            for (uint32_t c = uc0; c < uc1; ++c) {
+                const uint32_t a = sCs0[c], e = sCs0[c + 1];
+                const double p = sP[c];
+                const bool post = postc[c] != 0;
+                double S = 0.0;
+                for (uint32_t s = a + lane; s < e; s += 64) S += syn_update<T>(d, s0 + s, n, p, post, svc, sc, gn);
+                S = wave_sum(S);
+                if (lane == 0) sP[c] = prp_next(d, p, S);
+            }
+            STAGE_MARK(3);
+            if (st + 1 < nsteps) {
+                if (carry_sums) {
+                    for (uint32_t i = uva + lane; i < uvb; i += 64) {
+                        sGs[nxt * nv + i] = sGs[cur * nv + i] * sDecCv[i];
+                        sGsE[nxt * nv + i] = sGsE[cur * nv + i] * sDecCv[i];
+                    }
+                }
+                wave_sync();
+                deliver(st + 1, gn, nxt);
+                if (!EXACT && !carry_sums) {
+                    wave_sync();
+                    cv_sums(gn, nxt);
                 }
             }
+            STAGE_MARK(4);
         }
         __syncthreads();
-        STAGE_MARK(2);
-        // D. gates at V^{n+1}
-        for (uint32_t k = tid; k < nhh; k += BS) gate_update<T>(d, k0 + k, sV[sHHcv[k]], gv);
-        STAGE_MARK(3);
     }
-    // E of the epoch's last step
-    stage_e(n0 + nsteps - 1);
-    __syncthreads();
-    STAGE_MARK(4);
+    STAGE_MARK(5);
     // ---- stage out
+    const T *gfin = sG + (nsteps & 1u) * ns;
+    const uint8_t *pfin = sPost + (nsteps & 1u) * ncb;
     for (uint32_t i = tid; i < nv; i += BS) d.V[v0 + i] = sV[i];
     for (uint32_t s = tid; s < ns; s += BS) {
-        ((T *)d.g)[s0 + s] = sG[s];
+        ((T *)d.g)[s0 + s] = gfin[s];
         ((T *)d.c)[s0 + s] = sC[s];
         d.h[s0 + s] = sH[s];
         d.z[s0 + s] = sZ[s];
@@ -441,24 +579,32 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     }
     for (uint32_t c = tid; c < ncb; c += BS) {
         d.p[c0 + c] = sP[c];
-        d.post[c0 + c] = sPost[c];
+        d.post[c0 + c] = pfin[c];
     }
     if (delivered) atomicAdd((unsigned long long *)&d.ctr->events, delivered);
-    __syncthreads();
-    STAGE_MARK(5);
+    STAGE_MARK(7);
     STAGE_FLUSH();
 }
 
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, const uint32_t *blk_lvl,
-                       uint32_t n_blocks, size_t lds_bytes, uint32_t block_threads, void *stream) {
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, uint32_t n_blocks, size_t lds_bytes,
+                       uint32_t block_threads, uint32_t solver_waves, void *stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (block_threads == 64) {
-        if (d.mixed) hipLaunchKernelGGL((k_epoch<float, 64>), dim3(n_blocks), dim3(64), lds_bytes, s, d, blk, blk_lvl, nsteps);
-        else hipLaunchKernelGGL((k_epoch<double, 64>), dim3(n_blocks), dim3(64), lds_bytes, s, d, blk, blk_lvl, nsteps);
-    } else {
-        if (d.mixed) hipLaunchKernelGGL((k_epoch<float, 256>), dim3(n_blocks), dim3(256), lds_bytes, s, d, blk, blk_lvl, nsteps);
-        else hipLaunchKernelGGL((k_epoch<double, 256>), dim3(n_blocks), dim3(256), lds_bytes, s, d, blk, blk_lvl, nsteps);
+#define PA_LAUNCH_EPOCH(BS_)                                                                                    \
+    do {                                                                                                        \
+        if (d.mixed)                                                                                            \
+            hipLaunchKernelGGL((k_epoch<float, BS_>), dim3(n_blocks), dim3(BS_), lds_bytes, s, d, blk, nsteps,   \
+                               solver_waves);                                                                   \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_epoch<double, BS_>), dim3(n_blocks), dim3(BS_), lds_bytes, s, d, blk, nsteps,  \
+                               solver_waves);                                                                   \
+    } while (0)
+    switch (block_threads) {
+    case 64: PA_LAUNCH_EPOCH(64); break;
+    case 128: PA_LAUNCH_EPOCH(128); break;
+    case 256: PA_LAUNCH_EPOCH(256); break;
+    default: return (int)hipErrorInvalidValue;
     }
+#undef PA_LAUNCH_EPOCH
     return (int)hipGetLastError();
 }
 
@@ -466,10 +612,10 @@ int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, co
 
 #ifdef PA_STAGE_TIMING
 extern "C" int pa_debug_stage_ticks(unsigned long long *out, int reset) {
-    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(pa::pa_stage_ticks), 8 * sizeof(unsigned long long)) != hipSuccess)
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(pa::pa_stage_ticks), 16 * sizeof(unsigned long long)) != hipSuccess)
         return -1;
     if (reset) {
-        unsigned long long z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned long long z[16] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(pa::pa_stage_ticks), z, sizeof z) != hipSuccess) return -1;
     }
     return 0;
@@ -489,11 +635,11 @@ pa_status pa_snapshot(pa_sim *s, int restore);
 
 struct BatchedPlan {
     std::vector<uint32_t> blk;  // cell boundaries, n_blocks + 1
-    std::vector<uint32_t> lvl;  // branch levels per block
-    uint32_t *d_blk = nullptr, *d_lvl = nullptr;
+    uint32_t *d_blk = nullptr;
     size_t lds = 0;
     uint32_t cells_per_block = 0;
     uint32_t threads = 256;
+    uint32_t solver_waves = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t graph_epochs = 0;
@@ -506,14 +652,14 @@ namespace {
 constexpr size_t LDS_MAX = 160 * 1024;
 
 struct Offsets {
-    std::vector<uint32_t> cv, syn, hh, seg, nlev;  // nlev: branch levels per cell
+    std::vector<uint32_t> cv, syn, hh, seg;
     uint32_t tsize, K;
 };
 
 // Packs consecutive cells, at most cpb per workgroup, within an LDS budget
 // that leaves room for several resident workgroups per CU.
 bool pack(const Offsets &o, uint32_t cpb, uint32_t threads, std::vector<uint32_t> &blk, size_t &lds) {
-    const size_t budget = threads == 64 ? 32 * 1024 : 64 * 1024;
+    const size_t budget = threads == 64 ? 32 * 1024 : (threads == 128 ? 48 * 1024 : 64 * 1024);
     const uint32_t nc = (uint32_t)o.cv.size() - 1;
     auto bytes = [&](uint32_t a, uint32_t e) {
         return (size_t)FusedLayout(o.cv[e] - o.cv[a], o.syn[e] - o.syn[a], o.hh[e] - o.hh[a], e - a, o.K,
@@ -539,15 +685,10 @@ bool pack(const Offsets &o, uint32_t cpb, uint32_t threads, std::vector<uint32_t
     return true;
 }
 
-pa_status upload_plan(pa_sim *s, BatchedPlan &P, const Offsets &o) {
-    P.lvl.assign(P.blk.size() - 1, 1);
-    for (size_t b = 0; b + 1 < P.blk.size(); ++b)
-        for (uint32_t c = P.blk[b]; c < P.blk[b + 1]; ++c) P.lvl[b] = std::max(P.lvl[b], o.nlev[c]);
+pa_status upload_plan(pa_sim *s, BatchedPlan &P) {
     P.d_blk = (uint32_t *)pa_dev_alloc(s, P.blk.size() * 4);
-    P.d_lvl = (uint32_t *)pa_dev_alloc(s, P.lvl.size() * 4);
-    if (!P.d_blk || !P.d_lvl) return pa_fail(s, PA_ENOMEM, "block table");
-    if (hipMemcpy(P.d_blk, P.blk.data(), P.blk.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P.d_lvl, P.lvl.data(), P.lvl.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    if (!P.d_blk) return pa_fail(s, PA_ENOMEM, "block table");
+    if (hipMemcpy(P.d_blk, P.blk.data(), P.blk.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         return pa_fail(s, PA_EDEVICE, "block table upload");
     return PA_OK;
 }
@@ -556,7 +697,7 @@ int enqueue_epoch(const DevNet &d, const BatchedPlan &P, uint32_t nsteps, hipStr
                   hipEvent_t e0, hipEvent_t e1) {
     int r = 0;
     if (e0) (void)hipEventRecord(e0, st);
-    r |= launch_epoch_fused(d, nsteps, P.d_blk, P.d_lvl, (uint32_t)P.blk.size() - 1, P.lds, P.threads, st);
+    r |= launch_epoch_fused(d, nsteps, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, P.threads, P.solver_waves, st);
     if (e1) (void)hipEventRecord(e1, st);
     r |= launch_expand(d, nsteps, st);
     return r;
@@ -577,40 +718,50 @@ pa_status batched_setup(pa_sim *s) {
     o.tsize = d.mixed ? 4 : 8;
     o.K = d.K;
     o.seg.resize(d.n_cells + 1);
-    o.nlev.assign(d.n_cells, 1);
-    {
-        std::vector<uint8_t> lvl(d.n_seg);
-        if (hipMemcpy(o.seg.data(), d.seg_off, o.seg.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-            (d.n_seg && hipMemcpy(lvl.data(), d.seg_lvl, d.n_seg, hipMemcpyDeviceToHost) != hipSuccess))
-            return pa_fail(s, PA_EDEVICE, "segments");
-        for (uint32_t c = 0; c < d.n_cells; ++c)
-            for (uint32_t g = o.seg[c]; g < o.seg[c + 1]; ++g) o.nlev[c] = std::max<uint32_t>(o.nlev[c], lvl[g] + 1u);
-    }
-    if (hipMemcpy(o.cv.data(), d.cv_off, o.cv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+    if (hipMemcpy(o.seg.data(), d.seg_off, o.seg.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(o.cv.data(), d.cv_off, o.cv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(o.syn.data(), d.syn_off, o.syn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(o.hh.data(), d.hh_off, o.hh.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
         return pa_fail(s, PA_EDEVICE, "offsets");
-    struct Cand { uint32_t threads, cpb; };
+    // candidates: workgroup size, cells per workgroup, and how many of its
+    // wavefronts solve (the others update synapses; a 64-lane workgroup does
+    // both in turn); the caller may fix any of the three
+    struct Cand { uint32_t threads, cpb, sw; };
     std::vector<Cand> cands;
-    const uint32_t fixed = pa_cfg(s).cells_per_block;
-    if (fixed) cands.push_back({fixed >= 4 ? 256u : 64u, fixed});
-    else {
-        for (uint32_t c : {1u, 2u, 4u}) cands.push_back({64u, c});
-        for (uint32_t c : {4u, 8u, 16u, 32u, 64u}) cands.push_back({256u, c});
+    {
+        const pa_config &cf = pa_cfg(s);
+        std::vector<Cand> all;
+        for (uint32_t c : {1u, 2u, 4u}) all.push_back({64u, c, 1u});
+        for (uint32_t c : {2u, 4u, 8u}) all.push_back({128u, c, 1u});
+        for (uint32_t c : {4u, 8u, 16u, 32u})
+            for (uint32_t w : {1u, 2u, 3u}) all.push_back({256u, c, w});
+        for (Cand cd : all) {
+            if (cf.block_threads && cd.threads != cf.block_threads) continue;
+            if (cf.solver_waves && cd.threads > 64 && cd.sw != cf.solver_waves) continue;
+            if (cf.cells_per_block) {
+                cd.cpb = cf.cells_per_block;
+                bool dup = false;
+                for (const Cand &e : cands) dup |= e.threads == cd.threads && e.sw == cd.sw;
+                if (dup) continue;
+            }
+            cands.push_back(cd);
+        }
+        if (cands.empty()) return pa_fail(s, PA_EINVAL, "no workgroup shape matches the configuration");
     }
     double best_ms = INFINITY;
-    Cand best{0, 0};
+    Cand best{0, 0, 0};
     const bool tune = cands.size() > 1;
     if (tune && pa_snapshot(s, 0) != PA_OK) return PA_EDEVICE;
     for (const Cand &cd : cands) {
         BatchedPlan P;
         P.threads = cd.threads;
+        P.solver_waves = cd.sw;
         if (!pack(o, cd.cpb, cd.threads, P.blk, P.lds)) continue;
         if (!tune) {
             best = cd;
             break;
         }
-        if (upload_plan(s, P, o) != PA_OK) return PA_EDEVICE;
+        if (upload_plan(s, P) != PA_OK) return PA_EDEVICE;
         // trial: 1 warm epoch, then time 4 epochs of K steps
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
@@ -625,8 +776,8 @@ pa_status batched_setup(pa_sim *s) {
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
         if (getenv("PA_AUTOTUNE_VERBOSE"))
-            fprintf(stderr, "[autotune] threads %u cells/block %u blocks %zu lds %zu: %.3f ms / 4 epochs\n",
-                    cd.threads, cd.cpb, P.blk.size() - 1, P.lds, ms);
+            fprintf(stderr, "[autotune] threads %u cells/block %u solver waves %u blocks %zu lds %zu: %.3f ms / 4 epochs\n",
+                    cd.threads, cd.cpb, cd.sw, P.blk.size() - 1, P.lds, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = cd;
@@ -636,8 +787,9 @@ pa_status batched_setup(pa_sim *s) {
     if (!best.cpb) return pa_fail(s, PA_EINVAL, "a cell does not fit the LDS of one workgroup");
     plan->cells_per_block = best.cpb;
     plan->threads = best.threads;
+    plan->solver_waves = best.sw;
     pack(o, best.cpb, best.threads, plan->blk, plan->lds);
-    if (upload_plan(s, *plan, o) != PA_OK) return PA_EDEVICE;
+    if (upload_plan(s, *plan) != PA_OK) return PA_EDEVICE;
     // graph of G full epochs
     plan->graph_epochs = 8;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -659,6 +811,12 @@ void batched_release(pa_sim *s) {
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     delete plan;
     plan = nullptr;
+}
+
+void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves) {
+    BatchedPlan *p = pa_plan(s);
+    threads = p ? p->threads : 0;
+    solver_waves = p ? (p->threads == 64 ? 1 : p->solver_waves) : 0;
 }
 
 uint32_t batched_cells_per_block(pa_sim *s) {

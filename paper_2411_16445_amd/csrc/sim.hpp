@@ -74,6 +74,8 @@ struct DevNet {
     const double *cdt, *d0, *gpas_e, *axial;
     const int32_t *hh_of;        // HH slot or -1
     const uint32_t *cv_syn_off;  // n_cv + 1
+    const double *cv_dec;        // per CV: the decay factor its synapses share (1 if none)
+    uint32_t cv_dec_uniform;     // every CV's synapses share one decay factor
     const uint32_t *cv_cl_off;   // n_cv + 1, into clamps sorted by (CV, id)
     double *V, *I, *G, *D, *b;
 
@@ -148,9 +150,10 @@ int launch_inject(const DevNet &d, uint32_t nsteps, void *stream);
 int launch_step_plain(const DevNet &d, uint64_t n, void *stream, void *ev_begin, void *ev_end);
 int launch_expand(const DevNet &d, uint32_t nsteps, void *stream);
 int launch_probe(const DevNet &d, uint64_t row, void *stream);
-// Fused epoch: workgroup b owns cells blk[b] .. blk[b+1]-1.
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, const uint32_t *blk_lvl,
-                       uint32_t n_blocks, size_t lds_bytes, uint32_t block_threads, void *stream);
+// Fused epoch: workgroup b owns cells blk[b] .. blk[b+1]-1; the first
+// solver_waves wavefronts of a 256-lane workgroup share its cable solves.
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, uint32_t n_blocks, size_t lds_bytes,
+                       uint32_t block_threads, uint32_t solver_waves, void *stream);
 int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream);
 
 }  // namespace pa

@@ -1,0 +1,179 @@
+"""Summaries of rocprofv3 output for the fused epoch kernel.
+
+Two uses:
+
+* ``python -m paper_2411_16445_amd.profiling counters FETCH_DIR WRITE_DIR
+  --kernel k_epoch --copy-mib 256 --command "..." > profiles/<name>.md``
+  turns two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
+  ``bench.py --copy-probe-mib 256`` into the HBM traffic per launch of the
+  kernel.  Both counters are in KiB per dispatch; each is scaled by what it
+  reads for the plain device copy of known size that the same run performs
+  (the copy moves exactly ``copy-mib`` MiB each way), so the figure is in
+  true bytes.
+* ``python -m paper_2411_16445_amd.profiling trace STATS_CSV --command "..."``
+  formats a ``--kernel-trace --stats`` kernel_stats.csv as a table.
+
+``traffic_for_bench`` reads a counters summary back for ``bench.py``; it
+returns None when the kernel sources changed since the counters were taken
+(the summary records a fingerprint of them).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+import sys
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/kernels_fused.hip", "csrc/device_common.hpp", "csrc/sim.hpp")
+
+
+def source_fingerprint() -> str:
+    """sha256 over the sources the fused kernel is compiled from."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(_HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _rows(d: str):
+    path = d if d.endswith(".csv") else None
+    if path is None:
+        for root, _, files in os.walk(d):
+            for fn in files:
+                if fn.endswith("counter_collection.csv"):
+                    path = os.path.join(root, fn)
+    if path is None:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_dispatch(rows, counter, pick):
+    """Counter value per dispatch of the kernels selected by pick(row)."""
+    out = {}
+    for r in rows:
+        if r["Counter_Name"] != counter or not pick(r):
+            continue
+        key = r["Dispatch_Id"]
+        out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
+    return list(out.values())
+
+
+def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command):
+    copy_bytes = copy_mib * 1024 * 1024
+    lines = []
+    res = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _rows(d)
+        kern = _per_dispatch(rows, name, lambda r: kernel in r["Kernel_Name"])
+        # the copy probe: the largest device-to-device copy dispatch of the run
+        copies = [r for r in rows if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"]]
+        if not kern or not copies:
+            raise SystemExit(f"{name}: no dispatches of {kernel} or of the copy probe in {d}")
+        big = max(int(r["Grid_Size"]) for r in copies)
+        cp = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big]
+        cp_kib = sum(cp) / len(cp)
+        factor = copy_bytes / (cp_kib * 1024.0)
+        k_kib = sum(kern) / len(kern)
+        res[name] = dict(kib=k_kib, n=len(kern), copy_kib=cp_kib, factor=factor,
+                         bytes=k_kib * 1024.0 * factor)
+    fp = source_fingerprint()
+    lines.append(f"# HBM traffic of `{kernel}` per launch (rocprofv3 counters)")
+    lines.append("")
+    lines.append("Commands (repository root on the MI355X box, one counter per run):")
+    lines.append("")
+    for c in command:
+        lines.append(f"    {c}")
+    lines.append("")
+    lines.append(f"The same run copies {copy_mib} MiB device to device (a plain copy kernel); the")
+    lines.append("factor scales each counter so that it reads that copy's true size.")
+    lines.append("")
+    lines.append("| counter | dispatches | KiB per dispatch | copy probe KiB | scale factor | bytes per launch |")
+    lines.append("|---|---|---|---|---|---|")
+    for name in ("FETCH_SIZE", "WRITE_SIZE"):
+        r = res[name]
+        lines.append(f"| {name} | {r['n']} | {r['kib']:.1f} | {r['copy_kib']:.1f} | {r['factor']:.3f} | "
+                     f"{r['bytes']:.0f} |")
+    total = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
+    lines.append("")
+    lines.append(f"traffic_bytes_per_launch: {total:.0f}")
+    lines.append(f"kernel: {kernel}")
+    lines.append(f"source_sha256: {fp}")
+    return "\n".join(lines) + "\n"
+
+
+def trace_summary(stats_csv, command, title):
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    lines = [f"# Kernel trace: {title}", "", "Command (repository root on the MI355X box):", ""]
+    for c in command:
+        lines.append(f"    {c}")
+    lines += ["", "Durations in microseconds (rocprofv3 kernel_stats.csv).", "",
+              "| kernel | calls | total us | average us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r.get("Name", "")
+        calls = int(r.get("Calls", 0))
+        tot = float(r.get("TotalDurationNs", 0)) / 1e3
+        avg = float(r.get("AverageNs", 0)) / 1e3
+        mn = float(r.get("MinNs", 0)) / 1e3
+        mx = float(r.get("MaxNs", 0)) / 1e3
+        pct = float(r.get("Percentage", 0))
+        lines.append(f"| {name} | {calls} | {tot:.1f} | {avg:.3f} | {mn:.3f} | {mx:.3f} | {pct:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+def traffic_for_bench(profiles_dir, kernel):
+    """(bytes per launch, summary file) from the newest matching counters
+    summary whose source fingerprint equals the present sources, else
+    (None, reason)."""
+    if not os.path.isdir(profiles_dir):
+        return None, "no profiles directory"
+    fp = source_fingerprint()
+    stale = None
+    for fn in sorted(os.listdir(profiles_dir)):
+        if not fn.startswith("counters_") or not fn.endswith(".md"):
+            continue
+        with open(os.path.join(profiles_dir, fn)) as f:
+            text = f.read()
+        m_k = re.search(r"^kernel: (.+)$", text, re.M)
+        m_t = re.search(r"^traffic_bytes_per_launch: ([0-9.]+)$", text, re.M)
+        m_s = re.search(r"^source_sha256: ([0-9a-f]+)$", text, re.M)
+        if not (m_k and m_t and m_s) or m_k.group(1).strip() not in kernel:
+            continue
+        if m_s.group(1) != fp:
+            stale = fn
+            continue
+        return float(m_t.group(1)), fn
+    return None, (f"{stale}: kernel sources changed since the counters were taken" if stale
+                  else "no counters summary for this kernel")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2411_16445_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("fetch_dir")
+    c.add_argument("write_dir")
+    c.add_argument("--kernel", default="k_epoch")
+    c.add_argument("--copy-mib", type=int, default=256)
+    c.add_argument("--command", action="append", default=[])
+    t = sub.add_parser("trace")
+    t.add_argument("stats_csv")
+    t.add_argument("--title", default="")
+    t.add_argument("--command", action="append", default=[])
+    sub.add_parser("fingerprint")
+    a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        sys.stdout.write(counters_summary(a.fetch_dir, a.write_dir, a.kernel, a.copy_mib, a.command))
+    elif a.cmd == "trace":
+        sys.stdout.write(trace_summary(a.stats_csv, a.command, a.title))
+    else:
+        print(source_fingerprint())
+
+
+if __name__ == "__main__":
+    main()
