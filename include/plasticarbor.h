@@ -90,7 +90,20 @@ typedef struct {
     uint16_t solver_waves;   /* batched form: wavefronts of a workgroup that run the
                                 cable solve (1 .. lanes/64 - 1; the others update
                                 synapses); 0 = autotune */
+    uint32_t exchange;       /* batched form: PA_EXCHANGE_AUTO, PA_EXCHANGE_KERNEL or
+                                PA_EXCHANGE_RESIDENT */
 } pa_config;
+
+/* Batched form, spike exchange between epochs.  KERNEL: one launch per epoch
+ * of the fused step kernel, then a separate exchange kernel (state staged
+ * in and out of LDS every epoch).  RESIDENT: many epochs per cooperative
+ * launch with every workgroup resident; the state stays in LDS and the
+ * workgroups exchange spikes themselves behind a grid barrier (needs all
+ * workgroups to fit on the device at once).  AUTO: the faster of the two in
+ * trial epochs where RESIDENT fits. */
+#define PA_EXCHANGE_AUTO 0
+#define PA_EXCHANGE_KERNEL 1
+#define PA_EXCHANGE_RESIDENT 2
 
 /* Table 5 of the paper (h0 = 10 mV * 0.5 gamma_p/(gamma_p + gamma_d),
  * theta_pro = 0.5 h0, theta_tag = 0.2 h0 are given explicitly). */
@@ -127,6 +140,7 @@ typedef struct {
     uint64_t device_bytes;   /* device memory held */
     uint32_t block_threads;  /* batched form: lanes per workgroup chosen */
     uint32_t solver_waves;   /* batched form: solver wavefronts chosen */
+    uint32_t exchange;       /* batched form: PA_EXCHANGE_KERNEL or PA_EXCHANGE_RESIDENT chosen */
 } pa_stats;
 
 /* Creates a simulation in the BUILD state.  cfg and stc are copied.

@@ -43,7 +43,7 @@ class pa_config(C.Structure):
     _fields_ = [("dt_ms", C.c_double), ("threshold_mV", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("mode", C.c_int32), ("probe_stride", C.c_uint32),
                 ("slot_capacity", C.c_uint32), ("cells_per_block", C.c_uint32),
-                ("block_threads", C.c_uint16), ("solver_waves", C.c_uint16)]
+                ("block_threads", C.c_uint16), ("solver_waves", C.c_uint16), ("exchange", C.c_uint32)]
 
 
 STC_FIELDS = ["tau_c", "tau_h", "tau_p", "tau_z", "gamma_p", "gamma_d", "theta_p", "theta_d",
@@ -66,7 +66,7 @@ class pa_stats(C.Structure):
                                           "events")] + \
         [("epoch_steps", C.c_uint32), ("ring_slots", C.c_uint32), ("slot_capacity", C.c_uint32),
          ("cells_per_block", C.c_uint32), ("advance_ms", C.c_double), ("device_bytes", C.c_uint64),
-         ("block_threads", C.c_uint32), ("solver_waves", C.c_uint32)]
+         ("block_threads", C.c_uint32), ("solver_waves", C.c_uint32), ("exchange", C.c_uint32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -163,7 +163,8 @@ class Simulation:
     """
 
     def __init__(self, net: dict, precision="fp64", mode="plain", probes=(), probe_stride=1,
-                 slot_capacity=0, cells_per_block=0, block_threads=0, solver_waves=0, use_torch=True):
+                 slot_capacity=0, cells_per_block=0, block_threads=0, solver_waves=0, exchange="auto",
+                 use_torch=True):
         lib = load_library()
         self._lib = lib
         cfg = pa_config()
@@ -177,6 +178,7 @@ class Simulation:
         cfg.cells_per_block = int(cells_per_block)
         cfg.block_threads = int(block_threads)
         cfg.solver_waves = int(solver_waves)
+        cfg.exchange = {"auto": 0, "kernel": 1, "resident": 2}[exchange]
         stc = stc_params(net["stc"])
         h = _P()
         st = lib.pa_sim_create(C.byref(cfg), C.byref(stc), C.byref(h))

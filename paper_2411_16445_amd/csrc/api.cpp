@@ -196,6 +196,7 @@ pa_status pa_sim_create(const pa_config *cfg, const pa_stc_params *stc, pa_sim *
     if (cfg->block_threads != 0 && cfg->block_threads != 64 && cfg->block_threads != 128 &&
         cfg->block_threads != 256)
         return PA_EINVAL;
+    if (cfg->exchange > PA_EXCHANGE_RESIDENT) return PA_EINVAL;
     if (cfg->solver_waves > 3 || (cfg->block_threads && cfg->solver_waves &&
                                   cfg->block_threads > 64 && cfg->solver_waves >= cfg->block_threads / 64))
         return PA_EINVAL;
@@ -791,6 +792,7 @@ pa_status build(pa_sim *s) {
     d.cl_dur = upload(s, cldur, ok);
     d.cl_amp = upload(s, clamp, ok);
     d.ev_n = zeros<uint32_t>(s, (size_t)nc * d.R, ok);
+    d.blk_done = zeros<uint64_t>(s, std::max<size_t>(1, nc), ok);
     d.ev = (Event *)dev_alloc(s, (size_t)nc * d.R * d.Q * sizeof(Event));
     if (!d.ev) ok = false;
     d.ep_gid = zeros<uint32_t>(s, (size_t)nc * K, ok);
@@ -823,7 +825,9 @@ struct BatchedPlan;
 pa_status batched_setup(pa_sim *s);
 void batched_release(pa_sim *s);
 uint32_t batched_cells_per_block(pa_sim *s);
-void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves);
+void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves, uint32_t &exchange);
+uint32_t batched_multi_epochs(pa_sim *s);
+pa_status run_multi_batched(pa_sim *s, uint32_t n_epochs, hipEvent_t e0, hipEvent_t e1);
 pa_status run_epoch_batched(pa_sim *s, uint32_t nsteps, hipEvent_t e0, hipEvent_t e1);
 pa_status run_graph_batched(pa_sim *s, uint32_t &steps_done);
 uint32_t batched_graph_steps(pa_sim *s);
@@ -887,6 +891,7 @@ pa_status drain(pa_sim *s, uint64_t rows) {
         s->state = 2;
         if (c.flags & FLAG_NONFINITE) return fail(s, PA_ENUMERIC, "non-finite voltage in cell %u", c.bad_cell);
         if (c.flags & FLAG_OVERFLOW) return fail(s, PA_EOVERFLOW, "event slot of cell %u overflowed (slot_capacity %u)", c.bad_cell, d.Q);
+        if (c.flags & FLAG_BARRIER) return fail(s, PA_EDEVICE, "grid barrier of the multi-epoch kernel timed out");
         return fail(s, PA_ERANGE, "event for cell %u scheduled in the past", c.bad_cell);
     }
     return PA_OK;
@@ -944,6 +949,18 @@ extern "C" pa_status pa_advance_steps(pa_sim *s, uint64_t n_steps) {
         while (s->step < c_end) {
             const uint64_t e0 = s->step;
             if (s->cfg.mode == PA_BATCHED) {
+                // whole epochs in one resident launch when nothing needs the
+                // host between steps
+                const uint32_t max_ep = batched_multi_epochs(s);
+                if (!d.n_probes && max_ep && c_end - e0 >= d.K) {
+                    const uint32_t ne = (uint32_t)std::min<uint64_t>((c_end - e0) / d.K, max_ep);
+                    hipEvent_t tb = nullptr, te = nullptr;
+                    if (s->timing && timing_events(s, tb, te) != PA_OK) return PA_EDEVICE;
+                    pa_status st = run_multi_batched(s, ne, tb, te);
+                    if (st != PA_OK) return st;
+                    s->step = e0 + (uint64_t)ne * d.K;
+                    continue;
+                }
                 // replay the captured graph of whole epochs when nothing needs
                 // the host between steps
                 const uint32_t gsteps = batched_graph_steps(s);
@@ -1152,7 +1169,7 @@ extern "C" pa_status pa_stats_get(const pa_sim *s, pa_stats *o) {
     o->ring_slots = s->d.R;
     o->slot_capacity = s->d.Q;
     o->cells_per_block = batched_cells_per_block(const_cast<pa_sim *>(s));
-    batched_plan_shape(const_cast<pa_sim *>(s), o->block_threads, o->solver_waves);
+    batched_plan_shape(const_cast<pa_sim *>(s), o->block_threads, o->solver_waves, o->exchange);
     o->advance_ms = s->advance_ms;
     o->device_bytes = s->device_bytes;
     if (s->state != 0) {
@@ -1202,7 +1219,8 @@ pa_status pa_snapshot(pa_sim *s, int restore) {
         {d.h, (size_t)d.n_syn * 8}, {d.z, (size_t)d.n_syn * 8}, {d.p, (size_t)d.n_cells * 8},
         {d.S, (size_t)d.n_cells * 8}, {d.vdet_old, (size_t)d.n_cells * 8}, {d.post, (size_t)d.n_cells},
         {d.ev_cnt, (size_t)d.n_syn * 16}, {d.ev_sum, (size_t)d.n_syn * 16},
-        {d.ev_n, (size_t)d.n_cells * d.R * 4}, {d.tr_cur, (size_t)d.n_trains * 16},
+        {d.ev_n, (size_t)d.n_cells * d.R * 4}, {d.blk_done, (size_t)d.n_cells * 8},
+        {d.tr_cur, (size_t)d.n_trains * 16},
         {d.pois_t, (size_t)d.n_pois * 8}, {d.pois_j, (size_t)d.n_pois * 8},
         {d.ctr, sizeof(Counters)}};
     size_t total = 0;

@@ -168,6 +168,38 @@ __device__ inline void gate_update(const DevNet &d, uint32_t k, double vnew, con
     gv.n[j0] = gate_next<T>(gv.n[j0], v, dt, 2);
 }
 
+// --------------------------------------------------------------- coherent access
+// Loads and stores that are coherent across the whole device (they do not
+// stop in the non-coherent per-XCD L2 cache).  Event rings and their counts
+// are written by one workgroup and read by another within a launch of the
+// resident multi-epoch kernel, so they are accessed only this way.
+template <class U>
+__device__ __forceinline__ U ld_coh(const U *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class U>
+__device__ __forceinline__ void st_coh(U *p, U v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ Event ld_event(const Event *p) {
+    const uint64_t *q = (const uint64_t *)p;
+    uint64_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = ld_coh(q + k);
+    Event e;
+    __builtin_memcpy(&e, w, sizeof e);
+    return e;
+}
+
+__device__ __forceinline__ void st_event(Event *p, const Event &e) {
+    uint64_t w[4];
+    __builtin_memcpy(w, &e, sizeof e);
+    uint64_t *q = (uint64_t *)p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st_coh(q + k, w[k]);
+}
+
 // --------------------------------------------------------------- flags
 __device__ inline void raise_flag(const DevNet &d, uint32_t flag, uint32_t cell) {
     uint32_t old = atomicOr(&d.ctr->flags, flag);
@@ -190,7 +222,7 @@ __device__ inline void push_event(const DevNet &d, uint32_t cell, uint64_t s, co
     const uint32_t slot = (uint32_t)(s % d.R);
     const uint64_t ring = (uint64_t)cell * d.R + slot;
     const uint32_t pos = atomicAdd(&d.ev_n[ring], 1u);
-    if (pos < d.Q) d.ev[ring * d.Q + pos] = e;
+    if (pos < d.Q) st_event(d.ev + ring * d.Q + pos, e);
     else raise_flag(d, FLAG_OVERFLOW, cell);
 }
 
@@ -238,6 +270,21 @@ __device__ inline void sort_slot(Event *ev, uint32_t cnt) {
             --j;
         }
         ev[j] = x;
+    }
+}
+
+// The same for a slot left in the ring (coherent accesses).
+__device__ inline void sort_slot_coh(Event *ev, uint32_t cnt) {
+    for (uint32_t i = 1; i < cnt; ++i) {
+        const Event x = ld_event(ev + i);
+        uint32_t j = i;
+        while (j > 0) {
+            const Event y = ld_event(ev + j - 1);
+            if (!ev_before(x, y)) break;
+            st_event(ev + j, y);
+            --j;
+        }
+        st_event(ev + j, x);
     }
 }
 
@@ -647,17 +694,53 @@ __device__ inline double prp_next(const DevNet &d, double p, double S) {
     return p + ap * (-p + d.stc.p_max * trig);
 }
 
-// Threshold crossing V^n < theta <= V^{n+1}: records the spike with the
-// linearly interpolated time; returns whether the cell fired.
-__device__ inline bool detect(const DevNet &d, uint32_t cell, uint64_t n, double v0, double v1) {
-    if (!(v0 < d.theta && v1 >= d.theta)) return false;
+// Threshold crossing V^n < theta <= V^{n+1} of the detector, and the
+// linearly interpolated crossing time.
+__device__ __forceinline__ bool crossed(const DevNet &d, double v0, double v1) {
+    return v0 < d.theta && v1 >= d.theta;
+}
+
+__device__ __forceinline__ double spike_time(const DevNet &d, uint64_t n, double v0, double v1) {
     const double tn = (double)n * d.dt;
-    const double ts = tn + d.dt * ((d.theta - v0) / (v1 - v0));
+    return tn + d.dt * ((d.theta - v0) / (v1 - v0));
+}
+
+// Threshold detection: records the spike in the epoch's spike buffer;
+// returns whether the cell fired.
+__device__ inline bool detect(const DevNet &d, uint32_t cell, uint64_t n, double v0, double v1) {
+    if (!crossed(d, v0, v1)) return false;
+    const double ts = spike_time(d, n, v0, v1);
     const uint32_t pos = atomicAdd(&d.ctr->ep_n, 1u);
     d.ep_gid[pos] = cell;
     d.ep_step[pos] = (uint32_t)n;
     d.ep_t[pos] = ts;
     return true;
+}
+
+// The events of one spike (source gid at time ts): lanes of a wavefront over
+// the source's outgoing connections; each connection port becomes one event
+// in the target cell's ring, due no earlier than min_step.
+__device__ inline void expand_spike(const DevNet &d, uint32_t gid, double ts, uint32_t lane, uint64_t min_step) {
+    for (uint64_t q = d.out_off[gid] + lane; q < d.out_off[gid + 1]; q += 64) {
+        Event e;
+        e.w = d.out_w[q];
+        e.syn = d.out_syn[q];
+        e.src = gid;
+        e.conn = d.out_cid[q];
+        const uint32_t cell = d.out_cell[q];
+        const uint8_t ports = d.out_ports[q];
+        const double te = ts + d.out_d[q];
+        if (ports & 1) {
+            e.t = te;
+            e.port = 1;
+            push_event(d, cell, (uint64_t)floor(te / d.dt), e, min_step);
+        }
+        if (ports & 2) {
+            e.t = te + d.stc.t_cd;
+            e.port = 2;
+            push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, min_step);
+        }
+    }
 }
 
 }  // namespace pa

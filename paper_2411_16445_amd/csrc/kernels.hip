@@ -167,26 +167,7 @@ __global__ void k_expand(DevNet d, uint32_t nsteps) {
                 raise_flag(d, FLAG_OVERFLOW, gid);
             }
         }
-        for (uint64_t q = d.out_off[gid] + lane; q < d.out_off[gid + 1]; q += 64) {
-            Event e;
-            e.w = d.out_w[q];
-            e.syn = d.out_syn[q];
-            e.src = gid;
-            e.conn = d.out_cid[q];
-            const uint32_t cell = d.out_cell[q];
-            const uint8_t ports = d.out_ports[q];
-            const double te = ts + d.out_d[q];
-            if (ports & 1) {
-                e.t = te;
-                e.port = 1;
-                push_event(d, cell, (uint64_t)floor(te / d.dt), e, epoch_end);
-            }
-            if (ports & 2) {
-                e.t = te + d.stc.t_cd;
-                e.port = 2;
-                push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, epoch_end);
-            }
-        }
+        expand_spike(d, gid, ts, lane, epoch_end);
     }
     // the last workgroup to finish closes the epoch: the spikes join the
     // history and the epoch's first step advances

@@ -53,6 +53,8 @@ struct FusedLayout {
     uint32_t G, C, Dec, M, HH, N;
     // 32-bit
     uint32_t Par, HHk, CvSyn, CvCl, Cb0, Cs0, Cg0, Ch0, Det, HHcv, EvN, EvOff, Scan;
+    // spikes of the workgroup's cells in the current epoch (multi-epoch form)
+    uint32_t SpkT, SpkC;
     // events of the epoch, each slot's records sorted into delivery order
     uint32_t EvBuf, ev_cap;
     // 16-bit, 8-bit
@@ -82,7 +84,8 @@ struct FusedLayout {
         CvCl = take(4 * (nv + 1), 4); Cb0 = take(4 * (nc + 1), 4); Cs0 = take(4 * (nc + 1), 4);
         Cg0 = take(4 * (nc + 1), 4); Ch0 = take(4 * (nc + 1), 4);
         Det = take(4 * nc, 4); HHcv = take(4 * nh, 4); EvN = take(4 * nc * K, 4);
-        EvOff = take(4 * nc * K, 4); Scan = take(4, 4);
+        EvOff = take(4 * nc * K, 4); Scan = take(12, 4);
+        SpkT = take(8 * nc * K, 8); SpkC = take(4 * nc * K, 4);
         ev_cap = 2 * nc * K + 32;
         EvBuf = take(32 * ev_cap, 16);
         SynCv = take(2 * (tsize == 4 ? ns : 0), 2);
@@ -202,13 +205,53 @@ __device__ __forceinline__ bool pcr_cells(const DevNet &d, uint32_t va, uint32_t
     return ok;
 }
 
+// Barrier across all workgroups of a cooperative launch (all resident).
+// Each workgroup publishes the token (the first step of the next epoch) in
+// its own word of blk_done; the first wavefront then reads every
+// workgroup's word until all hold the token.  Everything other workgroups
+// read after the barrier (event rings and counts) is written and read with
+// device-coherent accesses, so no cache write-back or invalidation is
+// needed; the publishing store is ordered after this workgroup's writes by
+// waiting for them to complete.  A wait that lasts about a second, or a
+// barrier failure raised elsewhere, makes the workgroup give up (returns
+// false) instead of hanging.
+__device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint64_t token, uint32_t *ok_word) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x;
+        if (lane == 0) st_coh(d.blk_done + blockIdx.x, token);
+        uint32_t ok = 1, spins = 0;
+        for (;;) {
+            bool mine = true;
+            for (uint32_t b = lane; b < nblocks; b += 64) mine = mine && ld_coh(d.blk_done + b) >= token;
+            if (__ballot(!mine) == 0) break;
+            __builtin_amdgcn_s_sleep(2);
+            if ((++spins & 255u) == 0 && (ld_coh(&d.ctr->flags) & FLAG_BARRIER)) {
+                ok = 0;
+                break;
+            }
+            if (spins == (1u << 22)) {
+                if (lane == 0) raise_flag(d, FLAG_BARRIER, blockIdx.x);
+                ok = 0;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) *ok_word = ok;
+    }
+    __syncthreads();
+    return *ok_word != 0;
+}
+
 // One epoch of nsteps (<= K) steps for the cells blk[b] .. blk[b+1]-1 of
 // workgroup b.  Mutable state of those cells (V, gates, g, c, h, z, p, post
 // flag), their constants and the epoch's events live in LDS, so a step
 // touches global memory only for spikes, clamps and rare noise keys.
 template <class T, uint32_t BS>
 __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk, uint32_t nsteps,
-                                              uint32_t solver_waves) {
+                                              uint32_t n_epochs, uint32_t solver_waves) {
     extern __shared__ double lds[];
     uint8_t *L = (uint8_t *)lds;
     const uint32_t tid = threadIdx.x;
@@ -254,7 +297,15 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     const bool chains = (ng == ncb);
     const SynConst<T> sc{sErev, sDec, sKind, s0};
     const GateView<T> gv{sM, sHH, sN, k0};
-    const uint64_t n0 = d.ctr->step;
+    // first step of the launch; the multi-epoch form runs n_epochs epochs of
+    // K steps, the single-epoch form one epoch of nsteps
+    const uint64_t nbase = d.ctr->step;
+    const bool multi = n_epochs > 0;
+    const uint32_t n_ep = multi ? n_epochs : 1u;
+    uint64_t n0 = nbase;
+    uint32_t *sSpkN = (uint32_t *)(L + lay.Scan) + 1;
+    double *sSpkT = (double *)(L + lay.SpkT);
+    uint32_t *sSpkC = (uint32_t *)(L + lay.SpkC);
     STAGE_INIT();
 
     // ---- stage in: state, constants, this epoch's events
@@ -318,51 +369,8 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     }
     for (uint32_t c = tid; c < ncb; c += BS)
         for (uint32_t g = d.seg_off[c0 + c]; g < d.seg_off[c0 + c + 1]; ++g) sSegCell[g - g0] = (uint16_t)c;
-    // external arrivals of this epoch for the workgroup's cells enter the
-    // rings (trains and Poisson sources grouped by target cell)
-    {
-        const uint64_t epoch_end = n0 + nsteps;
-        const uint32_t t0 = d.tr_cell_off[c0], t1 = d.tr_cell_off[c1];
-        for (uint32_t x = t0 + tid; x < t1; x += BS) inject_train(d, d.tr_by_cell[x], n0, epoch_end);
-        const uint32_t p0 = d.po_cell_off[c0], p1 = d.po_cell_off[c1];
-        for (uint32_t x = p0 + tid; x < p1; x += BS) inject_poisson(d, d.po_by_cell[x], n0, epoch_end);
-    }
-    if (tid == 0) sScan[0] = 0;
+    if (tid == 0) *sSpkN = 0;
     __syncthreads();
-    // events of the epoch: one lane per (cell, step) slot takes the slot's
-    // count, claims room in the LDS event buffer, copies the records there
-    // and sorts them into delivery order (a slot that does not fit is
-    // sorted in place in the ring); the delivery statistics are counted
-    // here, in parallel
-    const uint32_t nslot = ncb * nsteps;
-    for (uint32_t x = tid; x < nslot; x += BS) {
-        const uint32_t c = x / nsteps, st = x - c * nsteps;
-        const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
-        const uint32_t cnt = min(d.ev_n[ring], d.Q);
-        sEvN[c * K + st] = cnt;
-        if (!cnt) continue;
-        d.ev_n[ring] = 0;
-        Event *ev = d.ev + ring * d.Q;
-        const uint32_t off = atomicAdd(&sScan[0], cnt);
-        Event *dst;
-        if (off + cnt <= lay.ev_cap) {
-            dst = sEv + off;
-            for (uint32_t i = 0; i < cnt; ++i) dst[i] = ev[i];
-            sEvOff[c * K + st] = off;
-        } else {
-            dst = ev;
-            sEvOff[c * K + st] = 0xffffffffu;
-        }
-        sort_slot(dst, cnt);
-        for (uint32_t i = 0; i < cnt; ++i) {
-            const uint32_t sy = dst[i].syn, po = dst[i].port;
-            atomicAdd(&d.ev_cnt[2 * sy + po - 1], 1ull);
-            atomicAdd(&d.ev_sum[2 * sy + po - 1], (unsigned long long)(n0 + st));
-        }
-    }
-    __syncthreads();
-    STAGE_MARK(6);
-
     // the cells of this wavefront: a solver wavefront's share split by CV
     // count, a synapse wavefront's share split by synapse count
     uint32_t wc0 = 0, wc1 = 0, uc0 = 0, uc1 = 0;
@@ -404,8 +412,9 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
                                   ? sEv + off
                                   : d.ev + ((uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R)) * d.Q;
             for (uint32_t i = 0; i < cnt; ++i) {
-                const uint32_t sy = ev[i].syn;
-                const T dg = apply_event<T>(d, sy, ev[i].port, ev[i].w, sv, sc);
+                const Event e = off != 0xffffffffu ? ev[i] : ld_event(ev + i);
+                const uint32_t sy = e.syn;
+                const T dg = apply_event<T>(d, sy, e.port, e.w, sv, sc);
                 if (carry_sums && dg != T(0)) {
                     const uint32_t q = sy - s0, cv = sSynCv[q];
                     sGs[half * nv + cv] += (double)dg;
@@ -430,20 +439,71 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         }
     };
 
+    for (uint32_t ep = 0; ep < n_ep; ++ep) {
+    n0 = nbase + (uint64_t)ep * K;
+    const uint32_t nst = multi ? K : nsteps;
+    // external arrivals of this epoch for the workgroup's cells enter the
+    // rings (trains and Poisson sources grouped by target cell)
+    {
+        const uint64_t epoch_end = n0 + nst;
+        const uint32_t t0 = d.tr_cell_off[c0], t1 = d.tr_cell_off[c1];
+        for (uint32_t x = t0 + tid; x < t1; x += BS) inject_train(d, d.tr_by_cell[x], n0, epoch_end);
+        const uint32_t p0 = d.po_cell_off[c0], p1 = d.po_cell_off[c1];
+        for (uint32_t x = p0 + tid; x < p1; x += BS) inject_poisson(d, d.po_by_cell[x], n0, epoch_end);
+    }
+    if (tid == 0) sScan[0] = 0;
+    __syncthreads();
+    // events of the epoch: one lane per (cell, step) slot takes the slot's
+    // count, claims room in the LDS event buffer, copies the records there
+    // and sorts them into delivery order (a slot that does not fit is
+    // sorted in place in the ring); the delivery statistics are counted
+    // here, in parallel
+    const uint32_t nslot = ncb * nst;
+    for (uint32_t x = tid; x < nslot; x += BS) {
+        const uint32_t c = x / nst, st = x - c * nst;
+        const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
+        const uint32_t cnt = min(ld_coh(d.ev_n + ring), d.Q);
+        sEvN[c * K + st] = cnt;
+        if (!cnt) continue;
+        st_coh(d.ev_n + ring, 0u);
+        Event *ev = d.ev + ring * d.Q;
+        const uint32_t off = atomicAdd(&sScan[0], cnt);
+        if (off + cnt <= lay.ev_cap) {
+            Event *dst = sEv + off;
+            for (uint32_t i = 0; i < cnt; ++i) dst[i] = ld_event(ev + i);
+            sort_slot(dst, cnt);
+            sEvOff[c * K + st] = off;
+        } else {
+            sort_slot_coh(ev, cnt);
+            sEvOff[c * K + st] = 0xffffffffu;
+        }
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const Event e = off + cnt <= lay.ev_cap ? sEv[off + i] : ld_event(ev + i);
+            atomicAdd(&d.ev_cnt[2 * e.syn + e.port - 1], 1ull);
+            atomicAdd(&d.ev_sum[2 * e.syn + e.port - 1], (unsigned long long)(n0 + st));
+        }
+    }
+    __syncthreads();
+    STAGE_MARK(6);
+
     // the first step's events, and its conductance sums
-    if (synw) {
-        deliver(0, sG, 0);
-        if constexpr (!EXACT) {
-            wave_sync();
-            cv_sums(sG, 0);
+    {
+        const uint32_t h0 = (uint32_t)(n0 - nbase) & 1u;
+        if (synw) {
+            deliver(0, sG + h0 * ns, h0);
+            if constexpr (!EXACT) {
+                wave_sync();
+                cv_sums(sG + h0 * ns, h0);
+            }
         }
     }
     __syncthreads();
 
-    for (uint32_t st = 0; st < nsteps; ++st) {
+    for (uint32_t st = 0; st < nst; ++st) {
         const uint64_t n = n0 + st;
         const double tn = (double)n * d.dt;
-        const uint32_t cur = st & 1u, nxt = cur ^ 1u;
+        // halves of the double buffers alternate over the steps of the launch
+        const uint32_t cur = (uint32_t)(n - nbase) & 1u, nxt = cur ^ 1u;
         T *gc = sG + cur * ns, *gn = sG + nxt * ns;
         uint8_t *postc = sPost + cur * ncb, *postn = sPost + nxt * ncb;
         STAGE_MARK(5);
@@ -524,8 +584,30 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
                 T *x = j == 0 ? sM + k : (j == 1 ? sHH + k : sN + k);
                 *x = gate_next<T>(*x, (T)sV[sHHcv[k]], (T)d.dt, (int)j);
             }
-            for (uint32_t c = wc0 + lane; c < wc1; c += 64)
-                postn[c] = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]) ? 1 : 0;
+            for (uint32_t c = wc0 + lane; c < wc1; c += 64) {
+                bool fired;
+                if (!multi) {
+                    fired = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]);
+                } else {
+                    const double v0 = sVold[c], v1 = sV[sDet[c]];
+                    fired = crossed(d, v0, v1);
+                    if (fired) {
+                        const double ts = spike_time(d, n, v0, v1);
+                        const uint64_t pos = atomicAdd((unsigned long long *)&d.ctr->hist_n, 1ull);
+                        if (pos < d.hist_cap) {
+                            d.hist_gid[pos] = c0 + c;
+                            d.hist_step[pos] = n;
+                            d.hist_t[pos] = ts;
+                        } else {
+                            raise_flag(d, FLAG_OVERFLOW, c0 + c);
+                        }
+                        const uint32_t k = atomicAdd(sSpkN, 1u);
+                        sSpkC[k] = c;
+                        sSpkT[k] = ts;
+                    }
+                }
+                postn[c] = fired ? 1 : 0;
+            }
             STAGE_MARK(2);
         }
         if (synw) {
@@ -543,7 +625,7 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
                 if (lane == 0) sP[c] = prp_next(d, p, S);
             }
             STAGE_MARK(3);
-            if (st + 1 < nsteps) {
+            if (st + 1 < nst) {
                 if (carry_sums) {
                     for (uint32_t i = uva + lane; i < uvb; i += 64) {
                         sGs[nxt * nv + i] = sGs[cur * nv + i] * sDecCv[i];
@@ -561,10 +643,23 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         }
         __syncthreads();
     }
+    if (multi) {
+        // this epoch's spikes of the workgroup's cells become events in
+        // the target cells' rings (due in a later epoch), then every
+        // workgroup waits for all the others before the next epoch reads
+        // its rings
+        const uint32_t nsp = *sSpkN;
+        for (uint32_t k = wave; k < nsp; k += NW) expand_spike(d, c0 + sSpkC[k], sSpkT[k], lane, n0 + K);
+        const bool ok = grid_sync(d, gridDim.x, n0 + K, sScan + 2);
+        if (tid == 0) *sSpkN = 0;
+        if (!ok) break;
+    }
+    }
     STAGE_MARK(5);
     // ---- stage out
-    const T *gfin = sG + (nsteps & 1u) * ns;
-    const uint8_t *pfin = sPost + (nsteps & 1u) * ncb;
+    const uint32_t hfin = (uint32_t)((multi ? (uint64_t)n_ep * K : nsteps) & 1u);
+    const T *gfin = sG + hfin * ns;
+    const uint8_t *pfin = sPost + hfin * ncb;
     for (uint32_t i = tid; i < nv; i += BS) d.V[v0 + i] = sV[i];
     for (uint32_t s = tid; s < ns; s += BS) {
         ((T *)d.g)[s0 + s] = gfin[s];
@@ -582,30 +677,60 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         d.post[c0 + c] = pfin[c];
     }
     if (delivered) atomicAdd((unsigned long long *)&d.ctr->events, delivered);
+    if (multi && blockIdx.x == 0 && tid == 0) d.ctr->step = nbase + (uint64_t)n_ep * K;
     STAGE_MARK(7);
     STAGE_FLUSH();
 }
 
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, uint32_t n_blocks, size_t lds_bytes,
-                       uint32_t block_threads, uint32_t solver_waves, void *stream) {
+template <class T, uint32_t BS>
+static int launch_fused_t(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, const uint32_t *blk, uint32_t n_blocks,
+                          size_t lds_bytes, uint32_t solver_waves, hipStream_t s) {
+    if (n_epochs == 0) {
+        hipLaunchKernelGGL((k_epoch<T, BS>), dim3(n_blocks), dim3(BS), lds_bytes, s, d, blk, nsteps, 0u, solver_waves);
+        return (int)hipGetLastError();
+    }
+    // all workgroups must be resident for the grid barrier: a cooperative
+    // launch guarantees it or fails
+    DevNet dc = d;
+    const uint32_t *b = blk;
+    uint32_t a_ns = nsteps, a_ne = n_epochs, a_sw = solver_waves;
+    void *args[] = {&dc, &b, &a_ns, &a_ne, &a_sw};
+    return (int)hipLaunchCooperativeKernel((const void *)k_epoch<T, BS>, dim3(n_blocks), dim3(BS), args,
+                                           (unsigned)lds_bytes, s);
+}
+
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, const uint32_t *blk, uint32_t n_blocks,
+                       size_t lds_bytes, uint32_t block_threads, uint32_t solver_waves, void *stream) {
     hipStream_t s = (hipStream_t)stream;
-#define PA_LAUNCH_EPOCH(BS_)                                                                                    \
-    do {                                                                                                        \
-        if (d.mixed)                                                                                            \
-            hipLaunchKernelGGL((k_epoch<float, BS_>), dim3(n_blocks), dim3(BS_), lds_bytes, s, d, blk, nsteps,   \
-                               solver_waves);                                                                   \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_epoch<double, BS_>), dim3(n_blocks), dim3(BS_), lds_bytes, s, d, blk, nsteps,  \
-                               solver_waves);                                                                   \
-    } while (0)
     switch (block_threads) {
-    case 64: PA_LAUNCH_EPOCH(64); break;
-    case 128: PA_LAUNCH_EPOCH(128); break;
-    case 256: PA_LAUNCH_EPOCH(256); break;
+    case 64: return d.mixed ? launch_fused_t<float, 64>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s)
+                            : launch_fused_t<double, 64>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s);
+    case 128: return d.mixed ? launch_fused_t<float, 128>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s)
+                             : launch_fused_t<double, 128>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s);
+    case 256: return d.mixed ? launch_fused_t<float, 256>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s)
+                             : launch_fused_t<double, 256>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s);
     default: return (int)hipErrorInvalidValue;
     }
-#undef PA_LAUNCH_EPOCH
-    return (int)hipGetLastError();
+}
+
+template <class T, uint32_t BS>
+static uint32_t capacity_t(size_t lds_bytes) {
+    int dev = 0, coop = 0, cus = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_epoch<T, BS>, (int)BS, lds_bytes) != hipSuccess)
+        return 0;
+    return (uint32_t)(nb * cus);
+}
+
+uint32_t epoch_fused_capacity(bool mixed, uint32_t block_threads, size_t lds_bytes) {
+    switch (block_threads) {
+    case 64: return mixed ? capacity_t<float, 64>(lds_bytes) : capacity_t<double, 64>(lds_bytes);
+    case 128: return mixed ? capacity_t<float, 128>(lds_bytes) : capacity_t<double, 128>(lds_bytes);
+    case 256: return mixed ? capacity_t<float, 256>(lds_bytes) : capacity_t<double, 256>(lds_bytes);
+    default: return 0;
+    }
 }
 
 }  // namespace pa
@@ -640,6 +765,7 @@ struct BatchedPlan {
     uint32_t cells_per_block = 0;
     uint32_t threads = 256;
     uint32_t solver_waves = 1;
+    bool multi = false;         // whole epochs in one cooperative launch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t graph_epochs = 0;
@@ -697,9 +823,19 @@ int enqueue_epoch(const DevNet &d, const BatchedPlan &P, uint32_t nsteps, hipStr
                   hipEvent_t e0, hipEvent_t e1) {
     int r = 0;
     if (e0) (void)hipEventRecord(e0, st);
-    r |= launch_epoch_fused(d, nsteps, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, P.threads, P.solver_waves, st);
+    r |= launch_epoch_fused(d, nsteps, 0u, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, P.threads, P.solver_waves, st);
     if (e1) (void)hipEventRecord(e1, st);
     r |= launch_expand(d, nsteps, st);
+    return r;
+}
+
+int enqueue_epochs_multi(const DevNet &d, const BatchedPlan &P, uint32_t n_epochs, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1) {
+    int r = 0;
+    if (e0) (void)hipEventRecord(e0, st);
+    r |= launch_epoch_fused(d, d.K, n_epochs, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, P.threads, P.solver_waves,
+                            st);
+    if (e1) (void)hipEventRecord(e1, st);
     return r;
 }
 
@@ -748,17 +884,39 @@ pa_status batched_setup(pa_sim *s) {
         }
         if (cands.empty()) return pa_fail(s, PA_EINVAL, "no workgroup shape matches the configuration");
     }
-    double best_ms = INFINITY;
-    Cand best{0, 0, 0};
-    const bool tune = cands.size() > 1;
-    if (tune && pa_snapshot(s, 0) != PA_OK) return PA_EDEVICE;
+    // each shape is tried with a separate exchange kernel per epoch and, if
+    // all its workgroups fit on the device at once, resident over several
+    // epochs per launch
+    const uint32_t xmode = pa_cfg(s).exchange;
+    struct Trial { Cand c; bool multi; };
+    std::vector<Trial> trials;
+    std::vector<BatchedPlan> packed;
     for (const Cand &cd : cands) {
         BatchedPlan P;
         P.threads = cd.threads;
         P.solver_waves = cd.sw;
         if (!pack(o, cd.cpb, cd.threads, P.blk, P.lds)) continue;
+        const bool fits = epoch_fused_capacity(d.mixed != 0, cd.threads, P.lds) >= P.blk.size() - 1;
+        if (xmode != PA_EXCHANGE_RESIDENT) trials.push_back({cd, false});
+        if (xmode != PA_EXCHANGE_KERNEL && fits) trials.push_back({cd, true});
+    }
+    if (trials.empty())
+        return pa_fail(s, xmode == PA_EXCHANGE_RESIDENT ? PA_EINVAL : PA_EINVAL,
+                       xmode == PA_EXCHANGE_RESIDENT ? "the workgroups do not fit on the device at once"
+                                                     : "a cell does not fit the LDS of one workgroup");
+    double best_ms = INFINITY;
+    Trial best{{0, 0, 0}, false};
+    const bool tune = trials.size() > 1;
+    if (tune && pa_snapshot(s, 0) != PA_OK) return PA_EDEVICE;
+    for (const Trial &tr : trials) {
+        const Cand &cd = tr.c;
+        BatchedPlan P;
+        P.threads = cd.threads;
+        P.solver_waves = cd.sw;
+        P.multi = tr.multi;
+        pack(o, cd.cpb, cd.threads, P.blk, P.lds);
         if (!tune) {
-            best = cd;
+            best = tr;
             break;
         }
         if (upload_plan(s, P) != PA_OK) return PA_EDEVICE;
@@ -768,7 +926,20 @@ pa_status batched_setup(pa_sim *s) {
             return pa_fail(s, PA_EDEVICE, "event");
         int r = enqueue_epoch(d, P, d.K, st, nullptr, nullptr);
         r |= (int)hipEventRecord(a, st);
-        for (int e = 0; e < 4; ++e) r |= enqueue_epoch(d, P, d.K, st, nullptr, nullptr);
+        if (tr.multi) {
+            // a cooperative launch the device refuses (too many workgroups to
+            // be resident) only rules this trial out
+            if (enqueue_epochs_multi(d, P, 4, st, nullptr, nullptr) != 0) {
+                (void)hipGetLastError();
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                if (hipStreamSynchronize(st) != hipSuccess || pa_snapshot(s, 1) != PA_OK)
+                    return pa_fail(s, PA_EDEVICE, "autotune trial");
+                continue;
+            }
+        } else {
+            for (int e = 0; e < 4; ++e) r |= enqueue_epoch(d, P, d.K, st, nullptr, nullptr);
+        }
         r |= (int)hipEventRecord(b, st);
         if (r || hipEventSynchronize(b) != hipSuccess) return pa_fail(s, PA_EDEVICE, "autotune trial");
         float ms = 0.f;
@@ -776,19 +947,21 @@ pa_status batched_setup(pa_sim *s) {
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
         if (getenv("PA_AUTOTUNE_VERBOSE"))
-            fprintf(stderr, "[autotune] threads %u cells/block %u solver waves %u blocks %zu lds %zu: %.3f ms / 4 epochs\n",
-                    cd.threads, cd.cpb, cd.sw, P.blk.size() - 1, P.lds, ms);
+            fprintf(stderr,
+                    "[autotune] threads %u cells/block %u solver waves %u %s blocks %zu lds %zu: %.3f ms / 4 epochs\n",
+                    cd.threads, cd.cpb, cd.sw, tr.multi ? "resident" : "kernel-exchange", P.blk.size() - 1, P.lds, ms);
         if (ms < best_ms) {
             best_ms = ms;
-            best = cd;
+            best = tr;
         }
         if (pa_snapshot(s, 1) != PA_OK) return PA_EDEVICE;
     }
-    if (!best.cpb) return pa_fail(s, PA_EINVAL, "a cell does not fit the LDS of one workgroup");
-    plan->cells_per_block = best.cpb;
-    plan->threads = best.threads;
-    plan->solver_waves = best.sw;
-    pack(o, best.cpb, best.threads, plan->blk, plan->lds);
+    if (!best.c.cpb) return pa_fail(s, PA_EINVAL, "a cell does not fit the LDS of one workgroup");
+    plan->cells_per_block = best.c.cpb;
+    plan->threads = best.c.threads;
+    plan->solver_waves = best.c.sw;
+    plan->multi = best.multi;
+    pack(o, best.c.cpb, best.c.threads, plan->blk, plan->lds);
     if (upload_plan(s, *plan) != PA_OK) return PA_EDEVICE;
     // graph of G full epochs
     plan->graph_epochs = 8;
@@ -813,10 +986,25 @@ void batched_release(pa_sim *s) {
     plan = nullptr;
 }
 
-void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves) {
+void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves, uint32_t &exchange) {
     BatchedPlan *p = pa_plan(s);
     threads = p ? p->threads : 0;
     solver_waves = p ? (p->threads == 64 ? 1 : p->solver_waves) : 0;
+    exchange = p ? (p->multi ? PA_EXCHANGE_RESIDENT : PA_EXCHANGE_KERNEL) : 0;
+}
+
+// Epochs one resident launch may run (0 when the plan exchanges spikes with
+// a separate kernel); bounded so that a launch stays well under a second.
+uint32_t batched_multi_epochs(pa_sim *s) {
+    BatchedPlan *p = pa_plan(s);
+    return p && p->multi ? 256u : 0u;
+}
+
+pa_status run_multi_batched(pa_sim *s, uint32_t n_epochs, hipEvent_t e0, hipEvent_t e1) {
+    const BatchedPlan &P = *pa_plan(s);
+    if (enqueue_epochs_multi(pa_devnet(s), P, n_epochs, pa_stream(s), e0, e1))
+        return pa_fail(s, PA_EDEVICE, "resident epoch launch");
+    return PA_OK;
 }
 
 uint32_t batched_cells_per_block(pa_sim *s) {

@@ -24,7 +24,7 @@ struct Event {
 static_assert(sizeof(Event) == 32, "event record is 32 bytes");
 
 // Error flags raised on the device, read back after every chunk of steps.
-enum : uint32_t { FLAG_OVERFLOW = 1u, FLAG_LATE = 2u, FLAG_NONFINITE = 4u };
+enum : uint32_t { FLAG_OVERFLOW = 1u, FLAG_LATE = 2u, FLAG_NONFINITE = 4u, FLAG_BARRIER = 8u };
 
 struct Counters {
     uint64_t step;      // first step of the current epoch (advanced by the epoch close)
@@ -34,6 +34,8 @@ struct Counters {
     uint64_t events;    // events delivered
     uint32_t bad_cell;  // first cell that raised a flag
     uint32_t blocks_done;  // workgroups of the exchange kernel that finished
+    uint32_t bar_count;    // grid barrier of the multi-epoch kernel: arrivals
+    uint32_t bar_gen;      // and generation
 };
 
 struct Stc {
@@ -123,6 +125,7 @@ struct DevNet {
 
     // event rings
     uint32_t *ev_n;              // n_cells * R
+    uint64_t *blk_done;          // n_cells: per workgroup, the epoch its exchange finished (grid barrier)
     Event *ev;                   // n_cells * R * Q
 
     // spikes
@@ -151,9 +154,15 @@ int launch_step_plain(const DevNet &d, uint64_t n, void *stream, void *ev_begin,
 int launch_expand(const DevNet &d, uint32_t nsteps, void *stream);
 int launch_probe(const DevNet &d, uint64_t row, void *stream);
 // Fused epoch: workgroup b owns cells blk[b] .. blk[b+1]-1; the first
-// solver_waves wavefronts of a 256-lane workgroup share its cable solves.
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, const uint32_t *blk, uint32_t n_blocks, size_t lds_bytes,
-                       uint32_t block_threads, uint32_t solver_waves, void *stream);
+// solver_waves wavefronts of a multi-wavefront workgroup share its cable
+// solves.  n_epochs = 0: one epoch of nsteps steps (the spike exchange is a
+// separate kernel); n_epochs > 0: n_epochs whole epochs in one cooperative
+// launch, the workgroups exchanging spikes themselves between epochs.
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, const uint32_t *blk, uint32_t n_blocks,
+                       size_t lds_bytes, uint32_t block_threads, uint32_t solver_waves, void *stream);
+// Workgroups of the fused kernel that can be resident at once (0 if the
+// device does not support cooperative launches).
+uint32_t epoch_fused_capacity(bool mixed, uint32_t block_threads, size_t lds_bytes);
 int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream);
 
 }  // namespace pa

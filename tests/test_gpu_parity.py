@@ -175,6 +175,63 @@ def test_plain_and_batched_forms_are_bitwise_identical():
         np.testing.assert_array_equal(a, b)
 
 
+SHAPES = [
+    dict(exchange="kernel", cells_per_block=1, block_threads=64),
+    dict(exchange="kernel", cells_per_block=4, block_threads=256, solver_waves=2),
+    dict(exchange="resident", cells_per_block=4, block_threads=128, solver_waves=1),
+    dict(exchange="resident", cells_per_block=8, block_threads=256, solver_waves=3),
+]
+
+
+def test_workgroup_shapes_and_exchange_modes_are_bitwise_identical():
+    """The FP64 batched form gives the same bits whatever the packing, the
+    split of wavefront roles and the spike-exchange mode (separate kernel,
+    or resident workgroups behind a grid barrier), and the same as the
+    plain form."""
+    net = netgen.tiny(seed=8, n_cells=23, t_end=150.0)
+    ref = Simulation(net, mode="plain")
+    ref.advance_steps(700)
+    want = (ref.spikes(), [ref.read(k) for k in ("V", "h", "z", "g", "c", "p")], ref.event_stats())
+    for shape in SHAPES:
+        _say(f"shape {shape}")
+        s = Simulation(net, mode="batched", **shape)
+        st = s.stats()
+        assert st["exchange"] == (2 if shape["exchange"] == "resident" else 1)
+        assert st["block_threads"] == shape["block_threads"]
+        s.advance_steps(350)
+        s.advance_steps(350)
+        for a, b in zip(want[0], s.spikes()):
+            np.testing.assert_array_equal(a, b)
+        for a, k in zip(want[1], ("V", "h", "z", "g", "c", "p")):
+            np.testing.assert_array_equal(a, s.read(k), err_msg=k)
+        for a, b in zip(want[2], s.event_stats()):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_mixed_exchange_modes_are_bitwise_identical():
+    net = netgen.config2(t_end=100.0)
+    out = []
+    for x in ("kernel", "resident"):
+        _say(f"mixed config2 exchange={x}")
+        s = Simulation(net, mode="batched", precision="mixed", exchange=x, cells_per_block=2,
+                       block_threads=128, solver_waves=1)
+        s.advance_steps(280)
+        out.append((s.spikes(), s.read("V"), s.read("g"), s.read("c")))
+    for a, b in zip(out[0][0], out[1][0]):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(out[0][1:], out[1][1:]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_resident_exchange_matches_oracle_on_ei_network():
+    net = netgen.config2(t_end=200.0)
+    _say("config2 resident exchange 300 steps")
+    o, s = run_pair(net, 300, chunks=2, mode="batched", exchange="resident")
+    assert assert_raster_equal(o, s) > 100
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
 # ------------------------------------------------------------------ edges
 def test_edge_cases_empty_and_degenerate():
     """Cells without synapses, a network without connections or trains, a
