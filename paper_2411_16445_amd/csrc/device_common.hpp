@@ -74,6 +74,14 @@ __device__ inline double std_normal(uint64_t seed, uint64_t sid, uint64_t n) {
     return (lane & 1) ? r * sin(ang) : r * cos(ang);
 }
 
+// The early-phase noise increment sigma sqrt((Theta_p + Theta_d) dt / tau_h) N
+// of synapse s at step n; out of line, as it is needed only while calcium
+// is above a threshold.
+__device__ __attribute__((noinline)) double noise_increment(uint64_t seed, uint64_t sid, uint64_t n, double sigma,
+                                                           double th, double ah) {
+    return sigma * sqrt(th * ah) * std_normal(seed, sid, n);
+}
+
 constexpr uint64_t POIS_TAG = 0x706f6973736f6e21ull;
 
 // Inter-arrival time (ms) number j of Poisson source k at rate (Hz):
@@ -113,6 +121,27 @@ __device__ __forceinline__ void hh_rate_pair(T v, int j, T &a, T &b) {
     const T rel = (x1 == T(0)) ? T(1) : x1 / em1;
     a = h ? T(0.07) * e1 : (j == 0 ? rel : T(0.1) * rel);
     b = h ? T(1) / (e2 + T(1)) : (j == 0 ? T(4) : T(0.125)) * e2;
+}
+
+// Mixed form: the same rates in FP32 with the hardware exponential and
+// reciprocal (a few ulp), and expm1 by its Taylor series below |x| = 0.1,
+// where exp(x) - 1 would cancel.
+template <>
+__device__ __forceinline__ void hh_rate_pair<float>(float v, int j, float &a, float &b) {
+    const bool h = (j == 1);
+    const float c1 = j == 0 ? 40.0f : (h ? 65.0f : 55.0f);
+    const float d1 = h ? 20.0f : 10.0f;
+    const float c2 = h ? 35.0f : 65.0f;
+    const float d2 = j == 0 ? 18.0f : (h ? 10.0f : 80.0f);
+    const float x1 = -__fdividef(v + c1, d1);
+    const float x2 = -__fdividef(v + c2, d2);
+    const float e1 = __expf(x1), e2 = __expf(x2);
+    const float em1 = fabsf(x1) < 0.1f
+                          ? x1 * (1.0f + x1 * (0.5f + x1 * (1.0f / 6.0f + x1 * (1.0f / 24.0f + x1 * (1.0f / 120.0f)))))
+                          : e1 - 1.0f;
+    const float rel = (x1 == 0.0f) ? 1.0f : __fdividef(x1, em1);
+    a = h ? 0.07f * e1 : (j == 0 ? rel : 0.1f * rel);
+    b = h ? __fdividef(1.0f, e2 + 1.0f) : (j == 0 ? 4.0f : 0.125f) * e2;
 }
 
 template <class T>
@@ -155,6 +184,14 @@ __device__ __forceinline__ T gate_next(T x, T v, T dt, int j) {
     hh_rate_pair<T>(v, j, a, b);
     const T xinf = a / (a + b);
     return xinf + (x - xinf) * dexp(-dt * (a + b));
+}
+
+template <>
+__device__ __forceinline__ float gate_next<float>(float x, float v, float dt, int j) {
+    float a, b;
+    hh_rate_pair<float>(v, j, a, b);
+    const float xinf = __fdividef(a, a + b);
+    return xinf + (x - xinf) * __expf(-dt * (a + b));
 }
 
 // The three gates of HH slot k (the gates are independent of each other).
@@ -663,19 +700,22 @@ template <class T>
 __device__ inline double syn_update(const DevNet &d, uint32_t s, uint64_t n, double p, bool post,
                                     const SynView<T> &sv, const SynConst<T> &sc, T *gout) {
     const uint32_t j = s - sv.base, jc = s - sc.base;
-    gout[j] = sv.g[j] * sc.decay[jc];
-    if (sc.kind[jc] != 1) return 0.0;
-    const Stc &P = d.stc;
+    // every operand first, so that their loads overlap
+    const T g = sv.g[j], dec = sc.decay[jc];
+    const uint8_t kind = sc.kind[jc];
     T c = sv.c[j];
+    const double h = sv.h[j], z = sv.z[j];
+    gout[j] = g * dec;
+    if (kind != 1) return 0.0;
+    const Stc &P = d.stc;
     if (post) c = c + (T)P.c_post;
-    const double h = sv.h[j], z = sv.z[j], h0 = P.h0;
+    const double h0 = P.h0;
     const double thp = (c - (T)P.theta_p > T(0)) ? 1.0 : 0.0;
     const double thd = (c - (T)P.theta_d > T(0)) ? 1.0 : 0.0;
     const double ah = d.dt / P.tau_h;
     const double drift = 0.1 * (h0 - h) + P.gamma_p * (10.0 - h) * thp - P.gamma_d * h * thd;
     double hn = h + ah * drift;
-    if (thp + thd > 0.0)
-        hn += P.sigma_pl * sqrt((thp + thd) * ah) * std_normal(d.seed, d.syn_sid[s], n);
+    if (thp + thd > 0.0) hn += noise_increment(d.seed, d.syn_sid[s], n, P.sigma_pl, thp + thd, ah);
     const double tagp = ((h - h0) - P.theta_tag > 0.0) ? 1.0 : 0.0;
     const double tagd = ((h0 - h) - P.theta_tag > 0.0) ? 1.0 : 0.0;
     const double az = d.dt / P.tau_z;
