@@ -29,38 +29,42 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def _alg_bytes_per_launch(form: str, s: dict, steps_per_launch: float) -> float:
-    """Algorithmic HBM bytes of one launch of the dominant kernel.
+# Algorithmic HBM bytes per unit and step (streaming model: state read and
+# written once per step, invariants read once), FP64 / mixed.
+ALG_BYTES = {
+    "cv": (36.0, 36.0),        # V r/w 16, axial 8, C/dt (with g_pas folded) 8, branch-table share 4
+    "hh": (48.0, 24.0),        # m, h, n r/w
+    "stc": (68.0, 52.0),       # g, c, h, z r/w + CV index 4 (g, c FP32 in the mixed form)
+    "static": (20.0, 12.0),    # g r/w + CV index 4
+    "cell": (16.0, 16.0),      # p r/w
+}
 
-    plain: the synapse kernel, per step: every synapse reads and writes g and
-    reads its decay factor and kind (25 B FP64 / 13 B FP32 g); a plastic
-    synapse also reads and writes c, h, z and reads its cell index
-    (52 B FP64, 44 B with FP32 c).
-    batched: the fused epoch kernel, per step: per CV V r/w + axial + C/dt +
-    d0 + g_pas E (48 B); per HH CV 3 gates r/w (48 / 24 B); per synapse as
-    above plus its reversal potential and CV index (12 B); per cell p r/w
-    and the detector voltage (24 B).
-    """
-    mixed = form.endswith("mixed")
-    n_syn, n_stc, n_cv, n_cells = s["n_syn"], s["n_stc"], s["n_cv"], s["n_cells"]
-    syn = 25.0 if not mixed else 13.0
-    stc = 52.0 if not mixed else 44.0
+
+def _alg_bytes_per_launch(form: str, s: dict, steps_per_launch: float) -> float:
+    """Algorithmic bytes of one launch of the dominant kernel: the per-unit
+    figures of ALG_BYTES times the units one step touches, times the steps
+    one launch advances.  The plain form's dominant kernel is the
+    synapse-update kernel (one step, synapse units only)."""
+    m = 1 if form.endswith("mixed") else 0
+    n_stc, n_static = s["n_stc"], s["n_syn"] - s["n_stc"]
+    syn = n_stc * ALG_BYTES["stc"][m] + n_static * ALG_BYTES["static"][m]
     if form.startswith("plain"):
-        per_step = n_syn * syn + n_stc * stc
-    else:
-        gate = 48.0 if not mixed else 24.0
-        per_step = (n_cv * 48.0 + n_cells * gate + n_syn * (syn + 12.0) + n_stc * stc
-                    + n_cells * 24.0)
+        return syn * steps_per_launch
+    n_hh = s["n_hh"]
+    per_step = (s["n_cv"] * ALG_BYTES["cv"][m] + n_hh * ALG_BYTES["hh"][m] + syn
+                + s["n_cells"] * ALG_BYTES["cell"][m])
     return per_step * steps_per_launch
 
 
-def run_form(net, form, steps, warmup, time_kernel=True):
+def run_form(net, form, steps, warmup, time_kernel=True, plan=None):
     import torch
 
     from paper_2411_16445_amd import Simulation
     mode, prec = form.split("-")
-    sim = Simulation(net, mode=mode, precision={"fp64": "fp64", "mixed": "mixed"}[prec])
+    sim = Simulation(net, mode=mode, precision={"fp64": "fp64", "mixed": "mixed"}[prec],
+                     **(plan if mode == "batched" and plan else {}))
     st = sim.stats()
+    st["n_hh"] = sim.n_hh
     sim.advance_steps(warmup)
     sp0 = sim.stats()["spikes"]
     if time_kernel:
@@ -75,7 +79,9 @@ def run_form(net, form, steps, warmup, time_kernel=True):
                cv_steps_per_s=st["n_cv"] * steps / el,
                synapse_updates_per_s=st["n_syn"] * steps / el,
                stc_synapse_updates_per_s=st["n_stc"] * steps / el,
-               epoch_steps=st["epoch_steps"], cells_per_block=st2["cells_per_block"])
+               epoch_steps=st["epoch_steps"], cells_per_block=st2["cells_per_block"],
+               block_threads=st2["block_threads"], solver_waves=st2["solver_waves"],
+               exchange={1: "kernel", 2: "resident"}.get(st2["exchange"], "-"))
     if time_kernel:
         ms, launches, name = sim.kernel_time()
         avg_ms = ms / max(1, launches)
@@ -111,6 +117,12 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the plain FP64 reference run")
     ap.add_argument("--cpu-steps", type=int, default=1500)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plan", default="",
+                    help="fix the batched form's plan instead of autotuning it: "
+                         "CELLS_PER_BLOCK,BLOCK_THREADS,SOLVER_WAVES,EXCHANGE (kernel|resident)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the runs, copy this many MiB device to device (a plain copy kernel of known "
+                         "size that scales rocprofv3's FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -120,7 +132,11 @@ def main():
     t_end = (args.warmup + args.steps + 10) * 0.2
     net = netgen.config2(t_end=t_end)
     print(f"[bench] network {netgen.summary(net)}", file=sys.stderr, flush=True)
-    head = run_form(net, args.form, args.steps, args.warmup)
+    plan = None
+    if args.plan:
+        cpb, bt, sw, xm = args.plan.split(",")
+        plan = dict(cells_per_block=int(cpb), block_threads=int(bt), solver_waves=int(sw), exchange=xm)
+    head = run_form(net, args.form, args.steps, args.warmup, plan=plan)
     print(f"[bench] {args.form}: {head['ms_per_step']*1e3:.2f} us/step, {head['spikes']} spikes",
           file=sys.stderr, flush=True)
     ref = None
@@ -132,7 +148,17 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(net, args.cpu_steps)
         print(f"[bench] cpu oracle: {cpu['value']:.3e} CV-steps/s", file=sys.stderr, flush=True)
+    if args.copy_probe_mib:
+        import torch
+        x = torch.ones(args.copy_probe_mib * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
     k = head.get("kernel", {})
+    from paper_2411_16445_amd.profiling import traffic_for_bench
+    traffic, traffic_src = traffic_for_bench(os.path.join(ROOT, "profiles"), k.get("name") or "")
+    steps_per_launch = args.steps / max(1, k.get("launches") or 1)
     line = {
         "metric": "CV-steps/s + synapse-updates/s, mixed+batched vs plain FP64 at equal spikes",
         "value": head["cv_steps_per_s"],
@@ -150,13 +176,16 @@ def main():
                    "cvs": head["stats"]["n_cv"], "synapses": head["stats"]["n_syn"],
                    "stc_synapses": head["stats"]["n_stc"], "dt_ms": 0.2, "form": args.form,
                    "epoch_steps": head["epoch_steps"], "cells_per_block": head["cells_per_block"],
-                   "parallelism": "single-gpu"},
+                   "block_threads": head["block_threads"], "solver_waves": head["solver_waves"],
+                   "exchange": head["exchange"], "parallelism": "single-gpu"},
         "synapse_updates_per_s": head["synapse_updates_per_s"],
         "stc_synapse_updates_per_s": head["stc_synapse_updates_per_s"],
         "spikes": head["spikes"],
         "roofline": {
             "bound": "hbm", "achieved": k.get("achieved_gbs"), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": (k.get("achieved_gbs") or 0) / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": (k.get("achieved_gbs") or 0) / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic * steps_per_launch,
+            "traffic_source": traffic_src,
             "kernel": k.get("name"), "avg_us": k.get("avg_us"), "launches": k.get("launches"),
             "alg_bytes_per_launch": k.get("alg_bytes_per_launch"),
             "kernel_share_of_step_time": k.get("share_of_time"),

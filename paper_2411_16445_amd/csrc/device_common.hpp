@@ -77,7 +77,7 @@ __device__ inline double std_normal(uint64_t seed, uint64_t sid, uint64_t n) {
 // The early-phase noise increment sigma sqrt((Theta_p + Theta_d) dt / tau_h) N
 // of synapse s at step n; out of line, as it is needed only while calcium
 // is above a threshold.
-__device__ __attribute__((noinline)) double noise_increment(uint64_t seed, uint64_t sid, uint64_t n, double sigma,
+static __device__ __attribute__((noinline)) double noise_increment(uint64_t seed, uint64_t sid, uint64_t n, double sigma,
                                                            double th, double ah) {
     return sigma * sqrt(th * ah) * std_normal(seed, sid, n);
 }
@@ -192,17 +192,6 @@ __device__ __forceinline__ float gate_next<float>(float x, float v, float dt, in
     hh_rate_pair<float>(v, j, a, b);
     const float xinf = __fdividef(a, a + b);
     return xinf + (x - xinf) * __expf(-dt * (a + b));
-}
-
-// The three gates of HH slot k (the gates are independent of each other).
-template <class T>
-__device__ inline void gate_update(const DevNet &d, uint32_t k, double vnew, const GateView<T> &gv) {
-    const uint32_t j0 = k - gv.base;
-    const T v = (T)vnew;
-    const T dt = (T)d.dt;
-    gv.m[j0] = gate_next<T>(gv.m[j0], v, dt, 0);
-    gv.h[j0] = gate_next<T>(gv.h[j0], v, dt, 1);
-    gv.n[j0] = gate_next<T>(gv.n[j0], v, dt, 2);
 }
 
 // --------------------------------------------------------------- coherent access

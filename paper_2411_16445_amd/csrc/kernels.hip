@@ -112,17 +112,28 @@ __global__ void k_solve(DevNet d) {
 }
 
 // ----------------------------------------------------------------- gates, S
+// One wavefront per cell: the cell's HH gates at V^{n+1} (one lane per
+// gate) and its protein trigger sum S over the plastic synapses, lane l
+// taking the cell's synapses l, l+64, ... and a fixed lane-shift tree
+// adding the lanes (the order of the fused form).
 template <class T>
 __global__ void k_cellpre(DevNet d) {
-    uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t cell = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (cell >= d.n_cells) return;
-    const GateView<T> gv = global_gates<T>(d);
-    for (uint32_t k = d.hh_off[cell]; k < d.hh_off[cell + 1]; ++k) gate_update<T>(d, k, d.V[d.hh_cv[k]], gv);
+    const uint32_t k0 = d.hh_off[cell], nh = d.hh_off[cell + 1] - k0;
+    T *gates[3] = {(T *)d.gm, (T *)d.gh, (T *)d.gn};
+    for (uint32_t t = lane; t < 3 * nh; t += 64) {
+        const uint32_t k = k0 + t / 3, j = t % 3;
+        T *x = gates[j] + k;
+        *x = gate_next<T>(*x, (T)d.V[d.hh_cv[k]], (T)d.dt, (int)j);
+    }
     const double h0 = d.stc.h0;
     double S = 0.0;
-    for (uint32_t s = d.syn_off[cell]; s < d.syn_off[cell + 1]; ++s)
-        if (d.syn_kind[s] == 1) S += fabs(d.h[s] - h0);
-    d.S[cell] = S;
+    for (uint32_t s = d.syn_off[cell] + lane; s < d.syn_off[cell + 1]; s += 64)
+        S += d.syn_kind[s] == 1 ? fabs(d.h[s] - h0) : 0.0;
+    S = wave_sum(S);
+    if (lane == 0) d.S[cell] = S;
 }
 
 // ----------------------------------------------------------------- synapses
@@ -240,7 +251,7 @@ static int step_plain(const DevNet &d, uint64_t n, hipStream_t s, hipEvent_t e0,
     hipLaunchKernelGGL(k_deliver<T>, grid_for(d.n_cells, 256), b, 0, s, d, n);
     hipLaunchKernelGGL(k_current<T>, grid_for(d.n_cv, 256), b, 0, s, d, tn);
     hipLaunchKernelGGL(k_solve, grid_for(d.n_cells, 64), dim3(64), 0, s, d);
-    hipLaunchKernelGGL(k_cellpre<T>, grid_for(d.n_cells, 64), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_cellpre<T>, grid_for((uint64_t)d.n_cells * 64, 256), b, 0, s, d);
     if (e0) (void)hipEventRecord(e0, s);
     if (d.n_syn) hipLaunchKernelGGL(k_syn<T>, grid_for(d.n_syn, 256), b, 0, s, d, n);
     if (e1) (void)hipEventRecord(e1, s);

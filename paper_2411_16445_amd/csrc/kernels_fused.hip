@@ -62,6 +62,9 @@ struct FusedLayout {
     uint32_t total;
     __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
                                     uint32_t tsize, uint32_t ng) {
+        // the cyclic reduction's buffers only for mixed-form workgroups of
+        // unbranched cells (one branch segment per cell)
+        const uint32_t npcr = tsize == 4 && ng == nc ? nv : 0;
         uint32_t o = 0;
         auto take = [&](uint32_t bytes, uint32_t align) {
             o = (o + align - 1) / align * align;
@@ -77,7 +80,7 @@ struct FusedLayout {
         Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
         const uint32_t nm = tsize == 4 ? nv : 0;
         Gs = take(16 * nm, 8); GsE = take(16 * nm, 8);
-        Xa = take(16 * nm, 8); Xc = take(16 * nm, 8); Xr = take(16 * nm, 8); Xi = take(16 * nm, 8);
+        Xa = take(16 * npcr, 8); Xc = take(16 * npcr, 8); Xr = take(16 * npcr, 8); Xi = take(16 * npcr, 8);
         G = take(2 * tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
         M = take(tsize * nh, 8); HH = take(tsize * nh, 8); N = take(tsize * nh, 8);
         Par = take(4 * nv, 4); HHk = take(4 * nv, 4); CvSyn = take(4 * (nv + 1), 4);
@@ -206,33 +209,48 @@ __device__ __forceinline__ bool pcr_cells(const DevNet &d, uint32_t va, uint32_t
 }
 
 // Barrier across all workgroups of a cooperative launch (all resident).
-// Each workgroup publishes the token (the first step of the next epoch) in
-// its own word of blk_done; the first wavefront then reads every
-// workgroup's word until all hold the token.  Everything other workgroups
-// read after the barrier (event rings and counts) is written and read with
-// device-coherent accesses, so no cache write-back or invalidation is
-// needed; the publishing store is ordered after this workgroup's writes by
-// waiting for them to complete.  A wait that lasts about a second, or a
-// barrier failure raised elsewhere, makes the workgroup give up (returns
-// false) instead of hanging.
-__device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint64_t token, uint32_t *ok_word) {
+// Workgroup b counts itself into group counter b mod G (G = 32 counters on
+// separate cache lines, so about nblocks/G workgroups contend for each),
+// then its first wavefront reads the G counters until each holds its
+// group's size times the number of barriers passed so far (kept per
+// workgroup in blk_done).  Everything other workgroups read after the
+// barrier (event rings and counts) is written and read with device-coherent
+// accesses, so no cache write-back or invalidation is needed; the count is
+// ordered after this workgroup's writes by waiting for them to complete.
+// A wait that lasts about a second, or a barrier failure raised elsewhere,
+// makes the workgroup give up (returns false) instead of hanging.
+constexpr uint32_t BAR_GROUPS = 32, BAR_STRIDE = 32;  // counters 128 bytes apart
+
+__device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) {
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x < 64) {
         const uint32_t lane = threadIdx.x;
-        if (lane == 0) st_coh(d.blk_done + blockIdx.x, token);
+        const uint32_t G = min(BAR_GROUPS, nblocks);
+        // barriers this workgroup has passed with the present plan, this one
+        // included
+        const uint64_t k = ld_coh(d.blk_done + blockIdx.x) + 1;
+        wave_sync();
+        if (lane == 0) {
+            st_coh(d.blk_done + blockIdx.x, k);
+            __hip_atomic_fetch_add(d.bar_grp + (blockIdx.x % G) * BAR_STRIDE, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
         uint32_t ok = 1, spins = 0;
         for (;;) {
             bool mine = true;
-            for (uint32_t b = lane; b < nblocks; b += 64) mine = mine && ld_coh(d.blk_done + b) >= token;
+            if (lane < G) {
+                const uint32_t size = nblocks / G + (lane < nblocks % G ? 1u : 0u);
+                mine = (uint64_t)ld_coh(d.bar_grp + lane * BAR_STRIDE) >= k * size;
+            }
             if (__ballot(!mine) == 0) break;
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
             if ((++spins & 255u) == 0 && (ld_coh(&d.ctr->flags) & FLAG_BARRIER)) {
                 ok = 0;
                 break;
             }
-            if (spins == (1u << 22)) {
+            if (spins == (1u << 23)) {
                 if (lane == 0) raise_flag(d, FLAG_BARRIER, blockIdx.x);
                 ok = 0;
                 break;
@@ -650,7 +668,7 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         // its rings
         const uint32_t nsp = *sSpkN;
         for (uint32_t k = wave; k < nsp; k += NW) expand_spike(d, c0 + sSpkC[k], sSpkT[k], lane, n0 + K);
-        const bool ok = grid_sync(d, gridDim.x, n0 + K, sScan + 2);
+        const bool ok = grid_sync(d, gridDim.x, sScan + 2);
         if (tid == 0) *sSpkN = 0;
         if (!ok) break;
     }

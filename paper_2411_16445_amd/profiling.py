@@ -3,7 +3,8 @@
 Two uses:
 
 * ``python -m paper_2411_16445_amd.profiling counters FETCH_DIR WRITE_DIR
-  --kernel k_epoch --copy-mib 256 --command "..." > profiles/<name>.md``
+  --kernel k_epoch --copy-mib 256 --steps-per-dispatch N --command "..."
+  > profiles/<name>.md``
   turns two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
   ``bench.py --copy-probe-mib 256`` into the HBM traffic per launch of the
   kernel.  Both counters are in KiB per dispatch; each is scaled by what it
@@ -63,7 +64,7 @@ def _per_dispatch(rows, counter, pick):
     return list(out.values())
 
 
-def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command):
+def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_dispatch):
     copy_bytes = copy_mib * 1024 * 1024
     lines = []
     res = {}
@@ -100,7 +101,10 @@ def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command):
                      f"{r['bytes']:.0f} |")
     total = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
     lines.append("")
+    lines.append(f"Each dispatch advances {steps_per_dispatch} steps.")
+    lines.append("")
     lines.append(f"traffic_bytes_per_launch: {total:.0f}")
+    lines.append(f"traffic_bytes_per_step: {total / steps_per_dispatch:.1f}")
     lines.append(f"kernel: {kernel}")
     lines.append(f"source_sha256: {fp}")
     return "\n".join(lines) + "\n"
@@ -127,8 +131,8 @@ def trace_summary(stats_csv, command, title):
 
 
 def traffic_for_bench(profiles_dir, kernel):
-    """(bytes per launch, summary file) from the newest matching counters
-    summary whose source fingerprint equals the present sources, else
+    """(HBM bytes per step, summary file) from a counters summary of this
+    kernel whose source fingerprint equals the present sources, else
     (None, reason)."""
     if not os.path.isdir(profiles_dir):
         return None, "no profiles directory"
@@ -140,7 +144,7 @@ def traffic_for_bench(profiles_dir, kernel):
         with open(os.path.join(profiles_dir, fn)) as f:
             text = f.read()
         m_k = re.search(r"^kernel: (.+)$", text, re.M)
-        m_t = re.search(r"^traffic_bytes_per_launch: ([0-9.]+)$", text, re.M)
+        m_t = re.search(r"^traffic_bytes_per_step: ([0-9.]+)$", text, re.M)
         m_s = re.search(r"^source_sha256: ([0-9a-f]+)$", text, re.M)
         if not (m_k and m_t and m_s) or m_k.group(1).strip() not in kernel:
             continue
@@ -160,6 +164,7 @@ def main(argv=None):
     c.add_argument("write_dir")
     c.add_argument("--kernel", default="k_epoch")
     c.add_argument("--copy-mib", type=int, default=256)
+    c.add_argument("--steps-per-dispatch", type=int, required=True)
     c.add_argument("--command", action="append", default=[])
     t = sub.add_parser("trace")
     t.add_argument("stats_csv")
@@ -168,7 +173,8 @@ def main(argv=None):
     sub.add_parser("fingerprint")
     a = ap.parse_args(argv)
     if a.cmd == "counters":
-        sys.stdout.write(counters_summary(a.fetch_dir, a.write_dir, a.kernel, a.copy_mib, a.command))
+        sys.stdout.write(counters_summary(a.fetch_dir, a.write_dir, a.kernel, a.copy_mib, a.command,
+                                          a.steps_per_dispatch))
     elif a.cmd == "trace":
         sys.stdout.write(trace_summary(a.stats_csv, a.command, a.title))
     else:
