@@ -83,14 +83,19 @@ _LIVE: "weakref.WeakSet" = weakref.WeakSet()
 def _close_all():
     for sim in list(_LIVE):
         sim.close()
+
+
 _P = C.c_void_p
 
 
-def load_library(path: str = LIB_PATH):
-    """Loads libplasticarbor.so; raises ImportError if it is not built."""
+def load_library(path: str = None):
+    """Loads libplasticarbor.so (the in-tree build, or the file named by the
+    PA_LIBRARY environment variable); raises ImportError if it is not built."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("PA_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2411_16445_amd.build`")
     # PyTorch ships its own HIP runtime under the same soname; importing it

@@ -608,6 +608,9 @@ __device__ inline bool hines_solve(double *D, double *B, double *V, const int32_
     return ok;
 }
 
+// Nodes whose operands the segment sweeps load ahead of the dependent chain.
+constexpr uint32_t SEG_PRELOAD = 8;
+
 // Elimination of one unbranched segment [a, b] (every node after a has its
 // predecessor as parent and only child), from the bottom node b, whose
 // diagonal and right-hand side (after its children's contributions) are
@@ -617,23 +620,23 @@ template <bool EXACT>
 __device__ inline void seg_backward(double *D, double *B, const double *ax, uint32_t a, uint32_t b,
                                     double &dc, double &bc) {
     uint32_t i = b;
-    while (i >= a + 8) {
-        double U[8], Dp[8], Bp[8];
+    while (i >= a + SEG_PRELOAD) {
+        double U[SEG_PRELOAD], Dp[SEG_PRELOAD], Bp[SEG_PRELOAD];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
             U[j] = -ax[i - j];
             Dp[j] = D[i - j - 1];
             Bp[j] = B[i - j - 1];
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
             const double f = qdiv<EXACT>(U[j], dc);
             D[i - j] = dc;
             B[i - j] = bc;
             dc = Dp[j] - f * U[j];
             bc = Bp[j] - f * bc;
         }
-        i -= 8;
+        i -= SEG_PRELOAD;
     }
     for (; i > a; --i) {
         const double u = -ax[i];
@@ -654,21 +657,21 @@ __device__ inline bool seg_forward(const double *D, const double *B, double *V, 
     double vp = V[a];
     bool ok = isfinite(vp);
     uint32_t i = a + 1;
-    while (i + 8 <= b + 1) {
-        double U[8], Dl[8], Bl[8];
+    while (i + SEG_PRELOAD <= b + 1) {
+        double U[SEG_PRELOAD], Dl[SEG_PRELOAD], Bl[SEG_PRELOAD];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
             U[j] = -ax[i + j];
             Dl[j] = D[i + j];
             Bl[j] = B[i + j];
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
             vp = qdiv<EXACT>(Bl[j] - U[j] * vp, Dl[j]);
             V[i + j] = vp;
             ok = ok && isfinite(vp);
         }
-        i += 8;
+        i += SEG_PRELOAD;
     }
     for (; i <= b; ++i) {
         vp = qdiv<EXACT>(B[i] - (-ax[i]) * vp, D[i]);
@@ -686,34 +689,69 @@ __device__ inline bool seg_forward(const double *D, const double *B, double *V, 
 // decayed conductance goes to gout (sv.g itself, or the other half of a
 // double buffer).  Returns |h - h0| of step start (0 for plain synapses).
 template <class T>
-__device__ inline double syn_update(const DevNet &d, uint32_t s, uint64_t n, double p, bool post,
-                                    const SynView<T> &sv, const SynConst<T> &sc, T *gout) {
-    const uint32_t j = s - sv.base, jc = s - sc.base;
-    // every operand first, so that their loads overlap
-    const T g = sv.g[j], dec = sc.decay[jc];
-    const uint8_t kind = sc.kind[jc];
-    T c = sv.c[j];
-    const double h = sv.h[j], z = sv.z[j];
-    gout[j] = g * dec;
-    if (kind != 1) return 0.0;
+struct SynIn {
+    T g, dec, c;
+    double h, z;
+};
+
+template <class T>
+struct SynOut {
+    T g, c;
+    double h, z, absdh, th;
+};
+
+// The arithmetic of one synapse's update from its loaded operands (no
+// memory access, no branch, so that several synapses of one lane can be
+// interleaved); the caller adds the noise where out.th > 0 and stores the
+// plastic state only for tagging-and-capture synapses.
+template <class T>
+__device__ __forceinline__ SynOut<T> syn_compute(const DevNet &d, double p, bool post, const SynIn<T> &x) {
     const Stc &P = d.stc;
-    if (post) c = c + (T)P.c_post;
-    const double h0 = P.h0;
+    SynOut<T> o;
+    o.g = x.g * x.dec;
+    const T c = post ? x.c + (T)P.c_post : x.c;
+    const double h = x.h, z = x.z, h0 = P.h0;
     const double thp = (c - (T)P.theta_p > T(0)) ? 1.0 : 0.0;
     const double thd = (c - (T)P.theta_d > T(0)) ? 1.0 : 0.0;
     const double ah = d.dt / P.tau_h;
     const double drift = 0.1 * (h0 - h) + P.gamma_p * (10.0 - h) * thp - P.gamma_d * h * thd;
-    double hn = h + ah * drift;
-    if (thp + thd > 0.0) hn += noise_increment(d.seed, d.syn_sid[s], n, P.sigma_pl, thp + thd, ah);
+    o.h = h + ah * drift;
+    o.th = thp + thd;
     const double tagp = ((h - h0) - P.theta_tag > 0.0) ? 1.0 : 0.0;
     const double tagd = ((h0 - h) - P.theta_tag > 0.0) ? 1.0 : 0.0;
     const double az = d.dt / P.tau_z;
-    const double zn = z + az * p * P.f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
-    sv.h[j] = hn;
-    sv.z[j] = zn;
-    if constexpr (sizeof(T) == 8) sv.c[j] = c * (T)d.r_c;
-    else sv.c[j] = c * d.r_c_f;
-    return fabs(h - h0);
+    o.z = z + az * p * P.f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
+    if constexpr (sizeof(T) == 8) o.c = c * (T)d.r_c;
+    else o.c = c * d.r_c_f;
+    o.absdh = fabs(h - h0);
+    return o;
+}
+
+// Noise increment of Eq. 18 added to the new h where a threshold is crossed.
+template <class T>
+__device__ __forceinline__ void syn_noise(const DevNet &d, uint32_t s, uint64_t n, SynOut<T> &o) {
+    if (o.th > 0.0) o.h += noise_increment(d.seed, d.syn_sid[s], n, d.stc.sigma_pl, o.th, d.dt / d.stc.tau_h);
+}
+
+template <class T>
+__device__ __forceinline__ double syn_store(const SynView<T> &sv, uint32_t j, bool stc, const SynOut<T> &o, T *gout) {
+    gout[j] = o.g;
+    if (!stc) return 0.0;
+    sv.h[j] = o.h;
+    sv.z[j] = o.z;
+    sv.c[j] = o.c;
+    return o.absdh;
+}
+
+template <class T>
+__device__ inline double syn_update(const DevNet &d, uint32_t s, uint64_t n, double p, bool post,
+                                    const SynView<T> &sv, const SynConst<T> &sc, T *gout) {
+    const uint32_t j = s - sv.base, jc = s - sc.base;
+    const SynIn<T> x{sv.g[j], sc.decay[jc], sv.c[j], sv.h[j], sv.z[j]};
+    const bool stc = sc.kind[jc] == 1;
+    SynOut<T> o = syn_compute<T>(d, p, post, x);
+    if (stc) syn_noise<T>(d, s, n, o);
+    return syn_store<T>(sv, j, stc, o, gout);
 }
 
 // --------------------------------------------------------------- cells

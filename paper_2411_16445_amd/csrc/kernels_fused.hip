@@ -245,12 +245,16 @@ __device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) 
                 mine = (uint64_t)ld_coh(d.bar_grp + lane * BAR_STRIDE) >= k * size;
             }
             if (__ballot(!mine) == 0) break;
-            __builtin_amdgcn_s_sleep(1);
+            // back off so that spinning wavefronts leave the issue slots of
+            // their compute unit to workgroups still in the epoch
+            if (spins < 16) __builtin_amdgcn_s_sleep(1);
+            else if (spins < 64) __builtin_amdgcn_s_sleep(4);
+            else __builtin_amdgcn_s_sleep(16);
             if ((++spins & 255u) == 0 && (ld_coh(&d.ctr->flags) & FLAG_BARRIER)) {
                 ok = 0;
                 break;
             }
-            if (spins == (1u << 23)) {
+            if (spins == (1u << 21)) {
                 if (lane == 0) raise_flag(d, FLAG_BARRIER, blockIdx.x);
                 ok = 0;
                 break;
@@ -638,7 +642,20 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
                 const double p = sP[c];
                 const bool post = postc[c] != 0;
                 double S = 0.0;
-                for (uint32_t s = a + lane; s < e; s += 64) S += syn_update<T>(d, s0 + s, n, p, post, svc, sc, gn);
+                // two synapses per lane and pass, their arithmetic interleaved
+                for (uint32_t s = a + lane; s < e; s += 128) {
+                    const bool two = s + 64 < e;
+                    const uint32_t s2 = two ? s + 64 : s;
+                    const SynIn<T> x1{gc[s], sDec[s], sC[s], sH[s], sZ[s]};
+                    const SynIn<T> x2{gc[s2], sDec[s2], sC[s2], sH[s2], sZ[s2]};
+                    const bool k1 = sKind[s] == 1, k2 = sKind[s2] == 1;
+                    SynOut<T> o1 = syn_compute<T>(d, p, post, x1);
+                    SynOut<T> o2 = syn_compute<T>(d, p, post, x2);
+                    if (k1) syn_noise<T>(d, s0 + s, n, o1);
+                    if (two && k2) syn_noise<T>(d, s0 + s2, n, o2);
+                    S += syn_store<T>(svc, s, k1, o1, gn);
+                    if (two) S += syn_store<T>(svc, s2, k2, o2, gn);
+                }
                 S = wave_sum(S);
                 if (lane == 0) sP[c] = prp_next(d, p, S);
             }
@@ -886,8 +903,8 @@ pa_status batched_setup(pa_sim *s) {
         const pa_config &cf = pa_cfg(s);
         std::vector<Cand> all;
         for (uint32_t c : {1u, 2u, 4u}) all.push_back({64u, c, 1u});
-        for (uint32_t c : {2u, 4u, 8u}) all.push_back({128u, c, 1u});
-        for (uint32_t c : {4u, 8u, 16u, 32u})
+        for (uint32_t c : {1u, 2u, 4u, 8u}) all.push_back({128u, c, 1u});
+        for (uint32_t c : {2u, 4u, 8u, 16u, 32u})
             for (uint32_t w : {1u, 2u, 3u}) all.push_back({256u, c, w});
         for (Cand cd : all) {
             if (cf.block_threads && cd.threads != cf.block_threads) continue;
