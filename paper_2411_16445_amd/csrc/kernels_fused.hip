@@ -521,162 +521,184 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     }
     __syncthreads();
 
-    for (uint32_t st = 0; st < nst; ++st) {
+    // one step of each role (n = n0 + st); the roles run in separate loops
+    // so that each loop keeps only its own role's values live
+    auto solver_step = [&](uint32_t st) {
         const uint64_t n = n0 + st;
         const double tn = (double)n * d.dt;
-        // halves of the double buffers alternate over the steps of the launch
         const uint32_t cur = (uint32_t)(n - nbase) & 1u, nxt = cur ^ 1u;
-        T *gc = sG + cur * ns, *gn = sG + nxt * ns;
-        uint8_t *postc = sPost + cur * ncb, *postn = sPost + nxt * ncb;
-        STAGE_MARK(5);
-        if (solver) {
-            // currents at V^n and assembly of the cable system
-            const SynView<T> svc{gc, sC, sH, sZ, s0};
-            for (uint32_t i = wva + lane; i < wvb; i += 64) {
-                const double v = sV[i];
-                double I, G;
-                const int32_t hk = sHHk[i];
-                const double *P = hk >= 0 ? sHHp + 7 * (hk - (int32_t)k0) : nullptr;
-                if constexpr (EXACT)
-                    cv_current<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, svc, sc, sCvSyn[i], sCvSyn[i + 1],
-                                  sCvCl[i], sCvCl[i + 1], I, G);
-                else
-                    cv_current_sums<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, sGs[cur * nv + i],
-                                       sGsE[cur * nv + i], sCvCl[i], sCvCl[i + 1], I, G);
-                sD[i] = sD0[i] + G;
-                sB[i] = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
-            }
-            for (uint32_t c = wc0 + lane; c < wc1; c += 64) sVold[c] = sV[sDet[c]];
-            wave_sync();
-            STAGE_MARK(0);
-            // the cable solve of the share's cells
-            if (wva == wvb) {
-                // no cells of this share
-            } else if (use_pcr) {
-                // unbranched cells, mixed form: cyclic reduction on the lanes
-                double *xa = (double *)(L + lay.Xa), *xc = (double *)(L + lay.Xc);
-                double *xr = (double *)(L + lay.Xr), *xi = (double *)(L + lay.Xi);
-                const bool ok = wvb - wva <= 64
-                                    ? pcr_cells<1>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr, xi)
-                                    : pcr_cells<PCR_NPL>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr,
-                                                         xi);
-                if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + wc0);
-            } else {
-                // Hines elimination level-scheduled over branch segments,
-                // deepest level first; a branch point takes its children's
-                // contributions in descending child order, as in the
-                // sequential elimination
-                for (int lv = (int)wlev - 1; lv >= 0; --lv) {
-                    for (uint32_t g = wga + lane; g < wgb; g += 64) {
-                        if (sSegLvl[g] != (uint32_t)lv) continue;
-                        const uint32_t a = sSegA[g], b = sSegB[g];
-                        double dc = sD[b], bc = sB[b];
-                        for (uint32_t q = sKidOff[g]; q < sKidOff[g + 1]; ++q) {
-                            const uint32_t kd = sKids[q];
-                            dc -= sCu[kd];
-                            bc -= sCb[kd];
-                        }
-                        seg_backward<EXACT>(sD, sB, sAx, a, b, dc, bc);
-                        if (sPar[a] >= 0) {
-                            const double u = -sAx[a];
-                            const double f = qdiv<EXACT>(u, dc);
-                            sCu[g] = f * u;
-                            sCb[g] = f * bc;
-                        }
-                    }
-                    wave_sync();
-                }
-                for (uint32_t lv = 0; lv < wlev; ++lv) {
-                    for (uint32_t g = wga + lane; g < wgb; g += 64) {
-                        if (sSegLvl[g] != lv) continue;
-                        const uint32_t a = sSegA[g], b = sSegB[g];
-                        const int32_t p = sPar[a];
-                        sV[a] = (p < 0) ? qdiv<EXACT>(sB[a], sD[a]) : qdiv<EXACT>(sB[a] - (-sAx[a]) * sV[p], sD[a]);
-                        if (!seg_forward<EXACT>(sD, sB, sV, sAx, a, b)) raise_flag(d, FLAG_NONFINITE, c0 + sSegCell[g]);
-                    }
-                    wave_sync();
-                }
-            }
-            wave_sync();
-            STAGE_MARK(1);
-            // HH gates at V^{n+1}, one lane per gate (the three gates of a
-            // CV are independent), and threshold detection
-            for (uint32_t t = lane; t < 3 * (whb - wha); t += 64) {
-                const uint32_t k = wha + t / 3, j = t % 3;
-                T *x = j == 0 ? sM + k : (j == 1 ? sHH + k : sN + k);
-                *x = gate_next<T>(*x, (T)sV[sHHcv[k]], (T)d.dt, (int)j);
-            }
-            for (uint32_t c = wc0 + lane; c < wc1; c += 64) {
-                bool fired;
-                if (!multi) {
-                    fired = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]);
-                } else {
-                    const double v0 = sVold[c], v1 = sV[sDet[c]];
-                    fired = crossed(d, v0, v1);
-                    if (fired) {
-                        const double ts = spike_time(d, n, v0, v1);
-                        const uint64_t pos = atomicAdd((unsigned long long *)&d.ctr->hist_n, 1ull);
-                        if (pos < d.hist_cap) {
-                            d.hist_gid[pos] = c0 + c;
-                            d.hist_step[pos] = n;
-                            d.hist_t[pos] = ts;
-                        } else {
-                            raise_flag(d, FLAG_OVERFLOW, c0 + c);
-                        }
-                        const uint32_t k = atomicAdd(sSpkN, 1u);
-                        sSpkC[k] = c;
-                        sSpkT[k] = ts;
-                    }
-                }
-                postn[c] = fired ? 1 : 0;
-            }
-            STAGE_MARK(2);
+        T *gc = sG + cur * ns;
+        uint8_t *postn = sPost + nxt * ncb;
+        // currents at V^n and assembly of the cable system
+        const SynView<T> svc{gc, sC, sH, sZ, s0};
+        for (uint32_t i = wva + lane; i < wvb; i += 64) {
+            const double v = sV[i];
+            double I, G;
+            const int32_t hk = sHHk[i];
+            const double *P = hk >= 0 ? sHHp + 7 * (hk - (int32_t)k0) : nullptr;
+            if constexpr (EXACT)
+                cv_current<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, svc, sc, sCvSyn[i], sCvSyn[i + 1],
+                              sCvCl[i], sCvCl[i + 1], I, G);
+            else
+                cv_current_sums<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, sGs[cur * nv + i],
+                                   sGsE[cur * nv + i], sCvCl[i], sCvCl[i + 1], I, G);
+            sD[i] = sD0[i] + G;
+            sB[i] = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
         }
-        if (synw) {
-            // synapse updates of step n (from step-start values) with the
-            // cell's protein trigger sum: lane l sums the cell's synapses
-            // l, l+64, ..., then a fixed lane-shift tree; then p of the cell
-            const SynView<T> svc{gc, sC, sH, sZ, s0};
-            for (uint32_t c = uc0; c < uc1; ++c) {
-                const uint32_t a = sCs0[c], e = sCs0[c + 1];
-                const double p = sP[c];
-                const bool post = postc[c] != 0;
-                double S = 0.0;
-                // two synapses per lane and pass, their arithmetic interleaved
-                for (uint32_t s = a + lane; s < e; s += 128) {
-                    const bool two = s + 64 < e;
-                    const uint32_t s2 = two ? s + 64 : s;
-                    const SynIn<T> x1{gc[s], sDec[s], sC[s], sH[s], sZ[s]};
-                    const SynIn<T> x2{gc[s2], sDec[s2], sC[s2], sH[s2], sZ[s2]};
-                    const bool k1 = sKind[s] == 1, k2 = sKind[s2] == 1;
-                    SynOut<T> o1 = syn_compute<T>(d, p, post, x1);
-                    SynOut<T> o2 = syn_compute<T>(d, p, post, x2);
-                    if (k1) syn_noise<T>(d, s0 + s, n, o1);
-                    if (two && k2) syn_noise<T>(d, s0 + s2, n, o2);
-                    S += syn_store<T>(svc, s, k1, o1, gn);
-                    if (two) S += syn_store<T>(svc, s2, k2, o2, gn);
-                }
-                S = wave_sum(S);
-                if (lane == 0) sP[c] = prp_next(d, p, S);
-            }
-            STAGE_MARK(3);
-            if (st + 1 < nst) {
-                if (carry_sums) {
-                    for (uint32_t i = uva + lane; i < uvb; i += 64) {
-                        sGs[nxt * nv + i] = sGs[cur * nv + i] * sDecCv[i];
-                        sGsE[nxt * nv + i] = sGsE[cur * nv + i] * sDecCv[i];
+        for (uint32_t c = wc0 + lane; c < wc1; c += 64) sVold[c] = sV[sDet[c]];
+        wave_sync();
+        STAGE_MARK(0);
+        // the cable solve of the share's cells
+        if (wva == wvb) {
+            // no cells of this share
+        } else if (use_pcr) {
+            // unbranched cells, mixed form: cyclic reduction on the lanes
+            double *xa = (double *)(L + lay.Xa), *xc = (double *)(L + lay.Xc);
+            double *xr = (double *)(L + lay.Xr), *xi = (double *)(L + lay.Xi);
+            const bool ok = wvb - wva <= 64
+                                ? pcr_cells<1>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr, xi)
+                                : pcr_cells<PCR_NPL>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr,
+                                                     xi);
+            if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + wc0);
+        } else {
+            // Hines elimination level-scheduled over branch segments,
+            // deepest level first; a branch point takes its children's
+            // contributions in descending child order, as in the
+            // sequential elimination
+            for (int lv = (int)wlev - 1; lv >= 0; --lv) {
+                for (uint32_t g = wga + lane; g < wgb; g += 64) {
+                    if (sSegLvl[g] != (uint32_t)lv) continue;
+                    const uint32_t a = sSegA[g], b = sSegB[g];
+                    double dc = sD[b], bc = sB[b];
+                    for (uint32_t q = sKidOff[g]; q < sKidOff[g + 1]; ++q) {
+                        const uint32_t kd = sKids[q];
+                        dc -= sCu[kd];
+                        bc -= sCb[kd];
+                    }
+                    seg_backward<EXACT>(sD, sB, sAx, a, b, dc, bc);
+                    if (sPar[a] >= 0) {
+                        const double u = -sAx[a];
+                        const double f = qdiv<EXACT>(u, dc);
+                        sCu[g] = f * u;
+                        sCb[g] = f * bc;
                     }
                 }
                 wave_sync();
-                deliver(st + 1, gn, nxt);
-                if (!EXACT && !carry_sums) {
-                    wave_sync();
-                    cv_sums(gn, nxt);
+            }
+            for (uint32_t lv = 0; lv < wlev; ++lv) {
+                for (uint32_t g = wga + lane; g < wgb; g += 64) {
+                    if (sSegLvl[g] != lv) continue;
+                    const uint32_t a = sSegA[g], b = sSegB[g];
+                    const int32_t p = sPar[a];
+                    sV[a] = (p < 0) ? qdiv<EXACT>(sB[a], sD[a]) : qdiv<EXACT>(sB[a] - (-sAx[a]) * sV[p], sD[a]);
+                    if (!seg_forward<EXACT>(sD, sB, sV, sAx, a, b)) raise_flag(d, FLAG_NONFINITE, c0 + sSegCell[g]);
+                }
+                wave_sync();
+            }
+        }
+        wave_sync();
+        STAGE_MARK(1);
+        // HH gates at V^{n+1}, one lane per gate (the three gates of a
+        // CV are independent), and threshold detection
+        for (uint32_t t = lane; t < 3 * (whb - wha); t += 64) {
+            const uint32_t k = wha + t / 3, j = t % 3;
+            T *x = j == 0 ? sM + k : (j == 1 ? sHH + k : sN + k);
+            *x = gate_next<T>(*x, (T)sV[sHHcv[k]], (T)d.dt, (int)j);
+        }
+        for (uint32_t c = wc0 + lane; c < wc1; c += 64) {
+            bool fired;
+            if (!multi) {
+                fired = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]);
+            } else {
+                const double v0 = sVold[c], v1 = sV[sDet[c]];
+                fired = crossed(d, v0, v1);
+                if (fired) {
+                    const double ts = spike_time(d, n, v0, v1);
+                    const uint64_t pos = atomicAdd((unsigned long long *)&d.ctr->hist_n, 1ull);
+                    if (pos < d.hist_cap) {
+                        d.hist_gid[pos] = c0 + c;
+                        d.hist_step[pos] = n;
+                        d.hist_t[pos] = ts;
+                    } else {
+                        raise_flag(d, FLAG_OVERFLOW, c0 + c);
+                    }
+                    const uint32_t k = atomicAdd(sSpkN, 1u);
+                    sSpkC[k] = c;
+                    sSpkT[k] = ts;
                 }
             }
-            STAGE_MARK(4);
+            postn[c] = fired ? 1 : 0;
         }
-        __syncthreads();
+        STAGE_MARK(2);
+        };
+    auto synapse_step = [&](uint32_t st) {
+        const uint64_t n = n0 + st;
+        const uint32_t cur = (uint32_t)(n - nbase) & 1u, nxt = cur ^ 1u;
+        T *gc = sG + cur * ns, *gn = sG + nxt * ns;
+        uint8_t *postc = sPost + cur * ncb;
+        // synapse updates of step n (from step-start values) with the
+        // cell's protein trigger sum: lane l sums the cell's synapses
+        // l, l+64, ..., then a fixed lane-shift tree; then p of the cell
+        const SynView<T> svc{gc, sC, sH, sZ, s0};
+        for (uint32_t c = uc0; c < uc1; ++c) {
+            const uint32_t a = sCs0[c], e = sCs0[c + 1];
+            const double p = sP[c];
+            const bool post = postc[c] != 0;
+            double S = 0.0;
+            // two synapses per lane and pass, their arithmetic interleaved
+            for (uint32_t s = a + lane; s < e; s += 128) {
+                const bool two = s + 64 < e;
+                const uint32_t s2 = two ? s + 64 : s;
+                const SynIn<T> x1{gc[s], sDec[s], sC[s], sH[s], sZ[s]};
+                const SynIn<T> x2{gc[s2], sDec[s2], sC[s2], sH[s2], sZ[s2]};
+                const bool k1 = sKind[s] == 1, k2 = sKind[s2] == 1;
+                SynOut<T> o1 = syn_compute<T>(d, p, post, x1);
+                SynOut<T> o2 = syn_compute<T>(d, p, post, x2);
+                if (k1) syn_noise<T>(d, s0 + s, n, o1);
+                if (two && k2) syn_noise<T>(d, s0 + s2, n, o2);
+                S += syn_store<T>(svc, s, k1, o1, gn);
+                if (two) S += syn_store<T>(svc, s2, k2, o2, gn);
+            }
+            S = wave_sum(S);
+            if (lane == 0) sP[c] = prp_next(d, p, S);
+        }
+        STAGE_MARK(3);
+        if (st + 1 < nst) {
+            if (carry_sums) {
+                for (uint32_t i = uva + lane; i < uvb; i += 64) {
+                    sGs[nxt * nv + i] = sGs[cur * nv + i] * sDecCv[i];
+                    sGsE[nxt * nv + i] = sGsE[cur * nv + i] * sDecCv[i];
+                }
+            }
+            wave_sync();
+            deliver(st + 1, gn, nxt);
+            if (!EXACT && !carry_sums) {
+                wave_sync();
+                cv_sums(gn, nxt);
+            }
+        }
+        STAGE_MARK(4);
+    };
+    // halves of the double buffers alternate over the steps of the launch
+    if (NW == 1) {
+        for (uint32_t st = 0; st < nst; ++st) {
+            STAGE_MARK(5);
+            solver_step(st);
+            synapse_step(st);
+            __syncthreads();
+        }
+    } else if (solver) {
+        for (uint32_t st = 0; st < nst; ++st) {
+            STAGE_MARK(5);
+            solver_step(st);
+            __syncthreads();
+        }
+    } else {
+        for (uint32_t st = 0; st < nst; ++st) {
+            STAGE_MARK(5);
+            synapse_step(st);
+            __syncthreads();
+        }
     }
     if (multi) {
         // this epoch's spikes of the workgroup's cells become events in
