@@ -45,10 +45,8 @@ namespace pa {
 struct FusedLayout {
     // doubles
     uint32_t V, D, B, Ax, D0, Cdt, Gpe, DecCv, H, Z, Erev, P, Vold, Cu, Cb, HHp;
-    // mixed form: per-CV conductance sums (two halves) and the cyclic
-    // reduction's published lower, upper, right-hand side and inverse
-    // diagonal (two halves)
-    uint32_t Gs, GsE, Xa, Xc, Xr, Xi;
+    // mixed form: per-CV conductance sums (two halves)
+    uint32_t Gs, GsE;
     // T
     uint32_t G, C, Dec, M, HH, N;
     // 32-bit
@@ -62,9 +60,6 @@ struct FusedLayout {
     uint32_t total;
     __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
                                     uint32_t tsize, uint32_t ng) {
-        // the cyclic reduction's buffers only for mixed-form workgroups of
-        // unbranched cells (one branch segment per cell)
-        const uint32_t npcr = tsize == 4 && ng == nc ? nv : 0;
         uint32_t o = 0;
         auto take = [&](uint32_t bytes, uint32_t align) {
             o = (o + align - 1) / align * align;
@@ -80,7 +75,6 @@ struct FusedLayout {
         Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
         const uint32_t nm = tsize == 4 ? nv : 0;
         Gs = take(16 * nm, 8); GsE = take(16 * nm, 8);
-        Xa = take(16 * npcr, 8); Xc = take(16 * npcr, 8); Xr = take(16 * npcr, 8); Xi = take(16 * npcr, 8);
         G = take(2 * tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
         M = take(tsize * nh, 8); HH = take(tsize * nh, 8); N = take(tsize * nh, 8);
         Par = take(4 * nv, 4); HHk = take(4 * nv, 4); CvSyn = take(4 * (nv + 1), 4);
@@ -138,71 +132,133 @@ __device__ __forceinline__ void split_cells(const uint32_t *off, uint32_t nc, ui
     hi = part + 1 == parts ? nc : count_below(off, nc, (uint32_t)((uint64_t)tot * (part + 1) / parts), lane);
 }
 
-// FP64 parallel cyclic reduction of the tridiagonal systems of the
-// unbranched cells whose CVs are [va, vb) (at most 64 NPL), on the lanes of
-// one wavefront, lane l holding CVs va + l + 64 j.  Equal to the elimination
-// up to rounding.  In each of `levels` rounds every node publishes its
-// lower and upper coupling, right-hand side and inverse diagonal (two
-// alternating halves of xa, xc, xr, xi), then folds in its neighbours at
-// distance 2^k; a zero coupling marks the end of a cell, so neighbours
-// never cross cells.  Writes V = x.
-template <uint32_t NPL>
-__device__ __forceinline__ bool pcr_cells(const DevNet &d, uint32_t va, uint32_t vb, uint32_t nv, uint32_t levels,
-                                          uint32_t lane, const int32_t *par, const double *ax, const double *D,
-                                          const double *B, double *V, double *xa, double *xc, double *xr,
-                                          double *xi) {
-    double ra[NPL], rc[NPL], rd[NPL], rr[NPL];
+// One round of cyclic reduction across the lanes of a wavefront, lane l
+// holding row l (lower coupling ra, diagonal rd, upper coupling rc,
+// right-hand side rr) of a tridiagonal system of n rows: the row folds in
+// rows l - sft and l + sft, read from their lanes.  A zero coupling marks
+// the end of a cell, so rows never combine across cells.
+__device__ __forceinline__ void pcr_round(uint32_t lane, uint32_t n, uint32_t sft, double &ra, double &rd,
+                                          double &rc, double &rr) {
+    const bool act = lane < n;
+    const bool hm = act && ra != 0.0 && lane >= sft;
+    const bool hp = act && rc != 0.0 && lane + sft < n;
+    const double ri = qdiv<false>(1.0, rd);
+    const int lm = (int)(hm ? lane - sft : lane), lp = (int)(hp ? lane + sft : lane);
+    const double ima = __shfl(ri, lm), am = __shfl(ra, lm), cm = __shfl(rc, lm), rm = __shfl(rr, lm);
+    const double ipa = __shfl(ri, lp), ap = __shfl(ra, lp), cp = __shfl(rc, lp), rp = __shfl(rr, lp);
+    const double al = -ra * ima, ga = -rc * ipa;
+    const double d1 = hm ? rd + al * cm : rd;
+    const double r1 = hm ? rr + al * rm : rr;
+    rd = hp ? d1 + ga * ap : d1;
+    rr = hp ? r1 + ga * rp : r1;
+    ra = hm ? al * am : 0.0;
+    rc = hp ? ga * cp : 0.0;
+}
+
+// Mixed-form parallel cyclic reduction of the tridiagonal systems of the
+// unbranched cells whose CVs are [va, vb) (at most 64), CV va + l on lane
+// l, in `levels` rounds.  Equal to the elimination up to rounding.  Writes
+// V = x.
+__device__ __forceinline__ bool pcr_cells(uint32_t va, uint32_t vb, uint32_t levels, uint32_t lane,
+                                          const int32_t *par, const double *ax, const double *D, const double *B,
+                                          double *V) {
+    const uint32_t n = vb - va;
+    const bool act = lane < n;
+    const uint32_t i = act ? va + lane : va;
+    const bool up = act && lane + 1 < n && par[i + 1] == (int32_t)i;
+    double ra = act && par[i] >= 0 ? -ax[i] : 0.0;
+    double rc = up ? -ax[i + 1] : 0.0;
+    double rd = act ? D[i] : 1.0;
+    double rr = act ? B[i] : 0.0;
+    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, n, sft, ra, rd, rc, rr);
+    if (!act) return true;
+    const double v = qdiv<false>(rr, rd);
+    V[i] = v;
+    return isfinite(v);
+}
+
+// Mixed-form solve of the unbranched cells whose CVs are [va, vb) (at most
+// 64 M) on one wavefront by the partition method: the range is cut into
+// consecutive chunks of m = ceil(n / 64) rows, chunk l on lane l.  A lane
+// first eliminates its chunk's lower couplings (each row then couples to
+// the previous chunk's last CV instead of its predecessor), then its upper
+// couplings (each row other than the last is expressed through the
+// previous chunk's last CV and its own last CV).  The chunks' last CVs
+// then obey a tridiagonal system with one row per lane (a row also takes
+// in the next chunk's first row), solved by `levels` rounds of cyclic
+// reduction across the lanes; the remaining CVs follow independently.
+// Cell boundaries are zero couplings, so cells may share a chunk.  Equal to
+// the elimination up to rounding.  Writes V = x.
+template <uint32_t M>
+__device__ __forceinline__ bool part_cells(uint32_t va, uint32_t vb, uint32_t levels, uint32_t lane,
+                                           const int32_t *par, const double *ax, const double *D, const double *B,
+                                           double *V) {
+    const uint32_t n = vb - va;
+    const uint32_t m = (n + 63) >> 6;
+    const uint32_t nact = (n + m - 1) / m;
+    const uint32_t s = va + lane * m;
+    const uint32_t cnt = lane < nact ? min(m, vb - s) : 0u;
+    // row j of the chunk: A x_prev + (1 / Iv) x_j + Cc x_{j+1} = R
+    double A[M], R[M], Iv[M], Cc[M];
+    double ae = 0.0, re = 0.0, ce = 0.0, de = 1.0;  // the chunk's last row
 #pragma unroll
-    for (uint32_t j = 0; j < NPL; ++j) {
-        const uint32_t i = va + lane + 64 * j;
-        const bool act = i < vb;
-        const uint32_t ic = act ? i : va;
-        const bool up = act && i + 1 < vb && par[ic + (i + 1 < vb ? 1 : 0)] == (int32_t)i;
-        const double axi = ax[ic], axn = ax[i + 1 < vb ? i + 1 : ic];
-        ra[j] = act && par[ic] >= 0 ? -axi : 0.0;
-        rc[j] = up ? -axn : 0.0;
-        rd[j] = act ? D[ic] : 1.0;
-        rr[j] = act ? B[ic] : 0.0;
-    }
-    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) {
-        const uint32_t h = (k & 1u) * nv;
-#pragma unroll
-        for (uint32_t j = 0; j < NPL; ++j) {
-            const uint32_t i = va + lane + 64 * j;
-            if (i < vb) {
-                xa[h + i] = ra[j];
-                xc[h + i] = rc[j];
-                xr[h + i] = rr[j];
-                xi[h + i] = qdiv<false>(1.0, rd[j]);
+    for (uint32_t j = 0; j < M; ++j) {
+        if (j < cnt) {
+            const uint32_t i = s + j;
+            const double a = par[i] >= 0 ? -ax[i] : 0.0;
+            const double c = i + 1 < vb && par[i + 1] == (int32_t)i ? -ax[i + 1] : 0.0;
+            double aj = a, dj = D[i], rj = B[i];
+            if (j > 0) {
+                const double f = a * Iv[j - 1];
+                aj = -f * A[j - 1];
+                dj = dj - f * Cc[j - 1];
+                rj = rj - f * R[j - 1];
             }
-        }
-        wave_sync();
-#pragma unroll
-        for (uint32_t j = 0; j < NPL; ++j) {
-            const uint32_t i = va + lane + 64 * j;
-            const bool act = i < vb;
-            const bool hm = act && ra[j] != 0.0 && i >= va + sft;
-            const bool hp = act && rc[j] != 0.0 && i + sft < vb;
-            const uint32_t im = h + (hm ? i - sft : va), ip = h + (hp ? i + sft : va);
-            const double ima = xi[im], am = xa[im], cm = xc[im], rm = xr[im];
-            const double ipa = xi[ip], ap = xa[ip], cp = xc[ip], rp = xr[ip];
-            const double al = -ra[j] * ima, ga = -rc[j] * ipa;
-            const double d1 = hm ? rd[j] + al * cm : rd[j];
-            const double r1 = hm ? rr[j] + al * rm : rr[j];
-            rd[j] = hp ? d1 + ga * ap : d1;
-            rr[j] = hp ? r1 + ga * rp : r1;
-            ra[j] = hm ? al * am : 0.0;
-            rc[j] = hp ? ga * cp : 0.0;
+            A[j] = aj;
+            R[j] = rj;
+            Cc[j] = c;
+            Iv[j] = qdiv<false>(1.0, dj);
+            ae = aj;
+            re = rj;
+            ce = c;
+            de = dj;
         }
     }
-    bool ok = true;
+    // x_j = R - A x_prev - Cc x_last for the rows before the last; (rn, an,
+    // cn) ends as the chunk's first row in that form (x_last itself when the
+    // chunk has one row)
+    double rn = 0.0, an = 0.0, cn = -1.0;
 #pragma unroll
-    for (uint32_t j = 0; j < NPL; ++j) {
-        const uint32_t i = va + lane + 64 * j;
-        if (i < vb) {
-            const double v = qdiv<false>(rr[j], rd[j]);
-            V[i] = v;
+    for (int j = (int)M - 2; j >= 0; --j) {
+        if ((uint32_t)j + 1 < cnt) {
+            rn = (R[j] - Cc[j] * rn) * Iv[j];
+            an = (A[j] - Cc[j] * an) * Iv[j];
+            cn = -(Cc[j] * cn) * Iv[j];
+            R[j] = rn;
+            A[j] = an;
+            Cc[j] = cn;
+        }
+    }
+    // the last row with the next chunk's first row substituted
+    const double rn1 = __shfl_down(rn, 1), an1 = __shfl_down(an, 1), cn1 = __shfl_down(cn, 1);
+    const bool act = cnt > 0;
+    double ra = act ? ae : 0.0;
+    double rc = act ? -(ce * cn1) : 0.0;
+    double rd = act ? de - ce * an1 : 1.0;
+    double rr = act ? re - ce * rn1 : 0.0;
+    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, nact, sft, ra, rd, rc, rr);
+    const double xe = qdiv<false>(rr, rd);
+    const double xp0 = __shfl_up(xe, 1);
+    const double xp = lane > 0 ? xp0 : 0.0;
+    bool ok = !act || isfinite(xe);
+#pragma unroll
+    for (uint32_t j = 0; j < M; ++j) {
+        if (j + 1 < cnt) {
+            const double v = R[j] - A[j] * xp - Cc[j] * xe;
+            V[s + j] = v;
             ok = ok && isfinite(v);
+        } else if (j + 1 == cnt) {
+            V[s + j] = xe;
         }
     }
     return ok;
@@ -271,8 +327,13 @@ __device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) 
 // workgroup b.  Mutable state of those cells (V, gates, g, c, h, z, p, post
 // flag), their constants and the epoch's events live in LDS, so a step
 // touches global memory only for spikes, clamps and rare noise keys.
+#ifdef PA_MIN_WAVES_PER_EU
+#define PA_EPOCH_BOUNDS(BS_) __launch_bounds__(BS_, PA_MIN_WAVES_PER_EU)
+#else
+#define PA_EPOCH_BOUNDS(BS_) __launch_bounds__(BS_)
+#endif
 template <class T, uint32_t BS>
-__global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk, uint32_t nsteps,
+__global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk, uint32_t nsteps,
                                               uint32_t n_epochs, uint32_t solver_waves) {
     extern __shared__ double lds[];
     uint8_t *L = (uint8_t *)lds;
@@ -411,10 +472,14 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
     for (uint32_t c = wc0 + lane; c < wc1; c += 64) wlen = max(wlen, sCb0[c + 1] - sCb0[c]);
     wlev = wave_max(wlev);
     wlen = wave_max(wlen);
+    // partition solve of unbranched cells (mixed form): rows per lane, and
+    // reduction rounds for the most chunk ends one cell holds
+    constexpr uint32_t PART_M = 4;
+    const bool use_pcr = !EXACT && chains && wvb - wva <= 64 * PART_M;
+    const uint32_t wrows = max(1u, (wvb - wva + 63) >> 6);
+    const uint32_t wends = (wlen + wrows - 1) / wrows;
     uint32_t wpcr = 0;
-    while ((1u << wpcr) < wlen) ++wpcr;
-    constexpr uint32_t PCR_NPL = 4;  // CVs per lane held in registers
-    const bool use_pcr = !EXACT && chains && wvb - wva <= 64 * PCR_NPL;
+    while ((1u << wpcr) < wends) ++wpcr;
     unsigned long long delivered = 0;
 
     // mixed form with one decay factor per CV: the per-CV conductance sums
@@ -552,13 +617,9 @@ __global__ __launch_bounds__(BS) void k_epoch(DevNet d, const uint32_t *__restri
         if (wva == wvb) {
             // no cells of this share
         } else if (use_pcr) {
-            // unbranched cells, mixed form: cyclic reduction on the lanes
-            double *xa = (double *)(L + lay.Xa), *xc = (double *)(L + lay.Xc);
-            double *xr = (double *)(L + lay.Xr), *xi = (double *)(L + lay.Xi);
-            const bool ok = wvb - wva <= 64
-                                ? pcr_cells<1>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr, xi)
-                                : pcr_cells<PCR_NPL>(d, wva, wvb, nv, wpcr, lane, sPar, sAx, sD, sB, sV, xa, xc, xr,
-                                                     xi);
+            // unbranched cells, mixed form: partition method on the lanes
+            const bool ok = wvb - wva <= 64 ? pcr_cells(wva, wvb, wpcr, lane, sPar, sAx, sD, sB, sV)
+                                            : part_cells<PART_M>(wva, wvb, wpcr, lane, sPar, sAx, sD, sB, sV);
             if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + wc0);
         } else {
             // Hines elimination level-scheduled over branch segments,
