@@ -732,6 +732,11 @@ pa_status build(pa_sim *s) {
     d.cv_syn_off = upload(s, cv_syn_off, ok);
     d.cv_dec = upload(s, cv_dec, ok);
     d.cv_dec_uniform = dec_uniform ? 1u : 0u;
+    // the conductances start at zero, and so do their carried sums
+    if (d.mixed && dec_uniform) {
+        d.gsum = zeros<double>(s, ncv, ok);
+        d.gesum = zeros<double>(s, ncv, ok);
+    }
     d.cv_cl_off = upload(s, cv_cl_off, ok);
     d.V = upload(s, V, ok);
     d.I = zeros<double>(s, ncv, ok);
@@ -1148,6 +1153,9 @@ extern "C" pa_status pa_state_write(pa_sim *s, int32_t what, const void *in, uin
     }
     HIPCHECK(s, hipStreamSynchronize(s->stream), "sync");
     if (!buf.empty()) HIPCHECK(s, hipMemcpyAsync(v.p, buf.data(), buf.size(), hipMemcpyHostToDevice, s->stream), "state write");
+    // new conductances: their carried per-CV sums follow
+    if (what == PA_STATE_G && launch_carried_sums(s->d, s->stream) != 0)
+        return fail(s, PA_EDEVICE, "carried sums");
     HIPCHECK(s, hipStreamSynchronize(s->stream), "sync");
     return PA_OK;
 }
@@ -1220,6 +1228,7 @@ pa_status pa_snapshot(pa_sim *s, int restore) {
         {d.h, (size_t)d.n_syn * 8}, {d.z, (size_t)d.n_syn * 8}, {d.p, (size_t)d.n_cells * 8},
         {d.S, (size_t)d.n_cells * 8}, {d.vdet_old, (size_t)d.n_cells * 8}, {d.post, (size_t)d.n_cells},
         {d.ev_cnt, (size_t)d.n_syn * 16}, {d.ev_sum, (size_t)d.n_syn * 16},
+        {d.gsum, d.gsum ? (size_t)d.n_cv * 8 : 0}, {d.gesum, d.gesum ? (size_t)d.n_cv * 8 : 0},
         {d.ev_n, (size_t)d.n_cells * d.R * 4}, {d.blk_done, (size_t)d.n_cells * 8}, {d.bar_grp, 32 * 32 * 4},
         {d.tr_cur, (size_t)d.n_trains * 16},
         {d.pois_t, (size_t)d.n_pois * 8}, {d.pois_j, (size_t)d.n_pois * 8},

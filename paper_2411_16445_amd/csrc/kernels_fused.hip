@@ -37,6 +37,10 @@
 
 namespace pa {
 
+// Most rows per lane of the lanes' solve of unbranched cells (mixed form):
+// a solver share of up to 64 CHAIN_ROWS CVs.
+constexpr uint32_t CHAIN_ROWS = 4;
+
 // LDS layout of a workgroup owning nv CVs, ns synapses, nh HH CVs, nc cells
 // and ng branch segments for an epoch of at most K steps; gates,
 // conductance, calcium and decay factors take tsize bytes (4 selects the
@@ -58,8 +62,17 @@ struct FusedLayout {
     // 16-bit, 8-bit
     uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, Kind, Post, SegLvl;
     uint32_t total;
+    // lean: mixed-form workgroup of unbranched cells solved by the lanes
+    // with the rows assembled in registers (no D, B); carried: mixed form
+    // with carried per-CV sums, so the synapse wavefronts alone read the
+    // synapse conductances (one buffer), and the reversal potentials and
+    // per-CV synapse ranges stay in global memory
+    bool lean, carried;
     __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
-                                    uint32_t tsize, uint32_t ng) {
+                                    uint32_t tsize, uint32_t ng, bool carried_sums) {
+        lean = tsize == 4 && ng == nc && nv <= 64 * CHAIN_ROWS;
+        carried = tsize == 4 && carried_sums;
+        const uint32_t nvd = lean ? 0 : nv, nse = carried ? 0 : ns;
         uint32_t o = 0;
         auto take = [&](uint32_t bytes, uint32_t align) {
             o = (o + align - 1) / align * align;
@@ -67,17 +80,17 @@ struct FusedLayout {
             o += bytes;
             return r;
         };
-        V = take(8 * nv, 16); D = take(8 * nv, 8); B = take(8 * nv, 8); Ax = take(8 * nv, 8);
+        V = take(8 * nv, 16); D = take(8 * nvd, 8); B = take(8 * nvd, 8); Ax = take(8 * nv, 8);
         D0 = take(8 * nv, 8); Cdt = take(8 * nv, 8); Gpe = take(8 * nv, 8);
         DecCv = take(8 * (tsize == 4 ? nv : 0), 8);
-        H = take(8 * ns, 8); Z = take(8 * ns, 8); Erev = take(8 * ns, 8);
+        H = take(8 * ns, 8); Z = take(8 * ns, 8); Erev = take(8 * nse, 8);
         P = take(8 * nc, 8); Vold = take(8 * nc, 8);
         Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
         const uint32_t nm = tsize == 4 ? nv : 0;
         Gs = take(16 * nm, 8); GsE = take(16 * nm, 8);
-        G = take(2 * tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
+        G = take((carried ? 1 : 2) * tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
         M = take(tsize * nh, 8); HH = take(tsize * nh, 8); N = take(tsize * nh, 8);
-        Par = take(4 * nv, 4); HHk = take(4 * nv, 4); CvSyn = take(4 * (nv + 1), 4);
+        Par = take(4 * nv, 4); HHk = take(4 * nv, 4); CvSyn = take(carried ? 0 : 4 * (nv + 1), 4);
         CvCl = take(4 * (nv + 1), 4); Cb0 = take(4 * (nc + 1), 4); Cs0 = take(4 * (nc + 1), 4);
         Cg0 = take(4 * (nc + 1), 4); Ch0 = take(4 * (nc + 1), 4);
         Det = take(4 * nc, 4); HHcv = take(4 * nh, 4); EvN = take(4 * nc * K, 4);
@@ -157,19 +170,20 @@ __device__ __forceinline__ void pcr_round(uint32_t lane, uint32_t n, uint32_t sf
 
 // Mixed-form parallel cyclic reduction of the tridiagonal systems of the
 // unbranched cells whose CVs are [va, vb) (at most 64), CV va + l on lane
-// l, in `levels` rounds.  Equal to the elimination up to rounding.  Writes
-// V = x.
+// l, in `levels` rounds; row(i, d, b) assembles CV i's diagonal and
+// right-hand side.  Equal to the elimination up to rounding.  Writes V = x
+// (after every row has read V).
+template <class Row>
 __device__ __forceinline__ bool pcr_cells(uint32_t va, uint32_t vb, uint32_t levels, uint32_t lane,
-                                          const int32_t *par, const double *ax, const double *D, const double *B,
-                                          double *V) {
+                                          const int32_t *par, const double *ax, Row &&row, double *V) {
     const uint32_t n = vb - va;
     const bool act = lane < n;
     const uint32_t i = act ? va + lane : va;
     const bool up = act && lane + 1 < n && par[i + 1] == (int32_t)i;
     double ra = act && par[i] >= 0 ? -ax[i] : 0.0;
     double rc = up ? -ax[i + 1] : 0.0;
-    double rd = act ? D[i] : 1.0;
-    double rr = act ? B[i] : 0.0;
+    double rd = 1.0, rr = 0.0;
+    if (act) row(i, rd, rr);
     for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, n, sft, ra, rd, rc, rr);
     if (!act) return true;
     const double v = qdiv<false>(rr, rd);
@@ -188,11 +202,11 @@ __device__ __forceinline__ bool pcr_cells(uint32_t va, uint32_t vb, uint32_t lev
 // in the next chunk's first row), solved by `levels` rounds of cyclic
 // reduction across the lanes; the remaining CVs follow independently.
 // Cell boundaries are zero couplings, so cells may share a chunk.  Equal to
-// the elimination up to rounding.  Writes V = x.
-template <uint32_t M>
+// the elimination up to rounding.  Rows are assembled by row() as in
+// pcr_cells.  Writes V = x (after every row has read V).
+template <uint32_t M, class Row>
 __device__ __forceinline__ bool part_cells(uint32_t va, uint32_t vb, uint32_t levels, uint32_t lane,
-                                           const int32_t *par, const double *ax, const double *D, const double *B,
-                                           double *V) {
+                                           const int32_t *par, const double *ax, Row &&row, double *V) {
     const uint32_t n = vb - va;
     const uint32_t m = (n + 63) >> 6;
     const uint32_t nact = (n + m - 1) / m;
@@ -207,7 +221,8 @@ __device__ __forceinline__ bool part_cells(uint32_t va, uint32_t vb, uint32_t le
             const uint32_t i = s + j;
             const double a = par[i] >= 0 ? -ax[i] : 0.0;
             const double c = i + 1 < vb && par[i + 1] == (int32_t)i ? -ax[i + 1] : 0.0;
-            double aj = a, dj = D[i], rj = B[i];
+            double aj = a, dj, rj;
+            row(i, dj, rj);
             if (j > 0) {
                 const double f = a * Iv[j - 1];
                 aj = -f * A[j - 1];
@@ -352,7 +367,13 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     const uint32_t SW = NW == 1 ? 1u : min(max(solver_waves, 1u), NW - 1);
     const bool solver = wave < SW;
     const bool synw = NW == 1 || wave >= SW;
-    const FusedLayout lay(nv, ns, nhh, ncb, K, sizeof(T), ng);
+    // mixed form with one decay factor per CV: the per-CV conductance sums
+    // are carried from step to step (decayed, plus each event's increment)
+    // instead of being summed again
+    const bool carry_sums = !EXACT && d.cv_dec_uniform != 0;
+    const FusedLayout lay(nv, ns, nhh, ncb, K, sizeof(T), ng, carry_sums);
+    // offset of conductance half h (one buffer when the sums are carried)
+    auto gofs = [&](uint32_t h) { return lay.carried ? 0u : h * ns; };
     double *sV = (double *)(L + lay.V), *sD = (double *)(L + lay.D), *sB = (double *)(L + lay.B);
     double *sAx = (double *)(L + lay.Ax), *sD0 = (double *)(L + lay.D0), *sCdt = (double *)(L + lay.Cdt);
     double *sGpe = (double *)(L + lay.Gpe), *sH = (double *)(L + lay.H), *sZ = (double *)(L + lay.Z);
@@ -402,11 +423,15 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         const int32_t p = d.parent[g];
         sPar[i] = p < 0 ? -1 : p - (int32_t)v0;
         sHHk[i] = d.hh_of[g];
-        sCvSyn[i] = d.cv_syn_off[g];
+        if (!lay.carried) sCvSyn[i] = d.cv_syn_off[g];
         sCvCl[i] = d.cv_cl_off[g];
         if constexpr (!EXACT) sDecCv[i] = d.cv_dec[g];
+        if (lay.carried) {
+            sGs[i] = d.gsum[g];
+            sGsE[i] = d.gesum[g];
+        }
         if (i == nv - 1) {
-            sCvSyn[nv] = d.cv_syn_off[g + 1];
+            if (!lay.carried) sCvSyn[nv] = d.cv_syn_off[g + 1];
             sCvCl[nv] = d.cv_cl_off[g + 1];
         }
     }
@@ -416,7 +441,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         sC[s] = ((const T *)d.c)[q];
         sH[s] = d.h[q];
         sZ[s] = d.z[q];
-        sErev[s] = d.syn_erev[q];
+        if (!lay.carried) sErev[s] = d.syn_erev[q];
         if constexpr (EXACT) sDec[s] = (T)d.syn_decay[q];
         else sDec[s] = d.syn_decay_f[q];
         sKind[s] = d.syn_kind[q];
@@ -472,20 +497,14 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     for (uint32_t c = wc0 + lane; c < wc1; c += 64) wlen = max(wlen, sCb0[c + 1] - sCb0[c]);
     wlev = wave_max(wlev);
     wlen = wave_max(wlen);
-    // partition solve of unbranched cells (mixed form): rows per lane, and
+    // lanes' solve of unbranched cells (mixed form): rows per lane, and
     // reduction rounds for the most chunk ends one cell holds
-    constexpr uint32_t PART_M = 4;
-    const bool use_pcr = !EXACT && chains && wvb - wva <= 64 * PART_M;
     const uint32_t wrows = max(1u, (wvb - wva + 63) >> 6);
     const uint32_t wends = (wlen + wrows - 1) / wrows;
     uint32_t wpcr = 0;
     while ((1u << wpcr) < wends) ++wpcr;
     unsigned long long delivered = 0;
 
-    // mixed form with one decay factor per CV: the per-CV conductance sums
-    // are carried from step to step (decayed, plus each event's increment)
-    // instead of being summed again
-    const bool carry_sums = !EXACT && d.cv_dec_uniform != 0;
     // events of step index st (relative to n0) of the synapse share's cells
     // into conductance half gh (and, when carried, sum half `half`), in
     // delivery order
@@ -502,17 +521,21 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
                 const Event e = off != 0xffffffffu ? ev[i] : ld_event(ev + i);
                 const uint32_t sy = e.syn;
                 const T dg = apply_event<T>(d, sy, e.port, e.w, sv, sc);
-                if (carry_sums && dg != T(0)) {
-                    const uint32_t q = sy - s0, cv = sSynCv[q];
+                if (lay.carried && dg != T(0)) {
+                    // the reversal potential: in the record's time field
+                    // for an event staged in LDS, else from global memory
+                    const double E = off != 0xffffffffu ? e.t : d.syn_erev[sy];
+                    const uint32_t cv = sSynCv[sy - s0];
                     sGs[half * nv + cv] += (double)dg;
-                    sGsE[half * nv + cv] += (double)dg * sErev[q];
+                    sGsE[half * nv + cv] += (double)dg * E;
                 }
             }
             delivered += cnt;
         }
     };
-    // mixed form: summed conductance and conductance x reversal potential
-    // of every CV of the synapse share, from conductance half gh
+    // mixed form, sums not carried: summed conductance and conductance x
+    // reversal potential of every CV of the synapse share, from conductance
+    // half gh
     auto cv_sums = [&](const T *gh, uint32_t half) {
         for (uint32_t i = uva + lane; i < uvb; i += 64) {
             double gs = 0.0, ge = 0.0;
@@ -564,23 +587,28 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             sort_slot_coh(ev, cnt);
             sEvOff[c * K + st] = 0xffffffffu;
         }
+        const bool staged = off + cnt <= lay.ev_cap;
         for (uint32_t i = 0; i < cnt; ++i) {
-            const Event e = off + cnt <= lay.ev_cap ? sEv[off + i] : ld_event(ev + i);
+            const Event e = staged ? sEv[off + i] : ld_event(ev + i);
             atomicAdd(&d.ev_cnt[2 * e.syn + e.port - 1], 1ull);
             atomicAdd(&d.ev_sum[2 * e.syn + e.port - 1], (unsigned long long)(n0 + st));
+            // once sorted, a staged record's time field carries the target's
+            // reversal potential for the carried sums
+            if (lay.carried && staged) sEv[off + i].t = d.syn_erev[e.syn];
         }
     }
     __syncthreads();
     STAGE_MARK(6);
 
-    // the first step's events, and its conductance sums
+    // the first step's events, and its conductance sums (carried sums
+    // enter the epoch already decayed to this step)
     {
         const uint32_t h0 = (uint32_t)(n0 - nbase) & 1u;
         if (synw) {
-            deliver(0, sG + h0 * ns, h0);
-            if constexpr (!EXACT) {
+            deliver(0, sG + gofs(h0), h0);
+            if (!EXACT && !lay.carried) {
                 wave_sync();
-                cv_sums(sG + h0 * ns, h0);
+                cv_sums(sG + gofs(h0), h0);
             }
         }
     }
@@ -592,11 +620,11 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         const uint64_t n = n0 + st;
         const double tn = (double)n * d.dt;
         const uint32_t cur = (uint32_t)(n - nbase) & 1u, nxt = cur ^ 1u;
-        T *gc = sG + cur * ns;
+        T *gc = sG + gofs(cur);
         uint8_t *postn = sPost + nxt * ncb;
-        // currents at V^n and assembly of the cable system
+        // currents at V^n and the diagonal and right-hand side of CV i
         const SynView<T> svc{gc, sC, sH, sZ, s0};
-        for (uint32_t i = wva + lane; i < wvb; i += 64) {
+        auto row = [&](uint32_t i, double &Di, double &Bi) {
             const double v = sV[i];
             double I, G;
             const int32_t hk = sHHk[i];
@@ -607,19 +635,23 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             else
                 cv_current_sums<T>(d, hk, P, hk >= 0 ? P[6] : 0.0, v, tn, gv, sGs[cur * nv + i],
                                    sGsE[cur * nv + i], sCvCl[i], sCvCl[i + 1], I, G);
-            sD[i] = sD0[i] + G;
-            sB[i] = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
-        }
+            Di = sD0[i] + G;
+            Bi = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
+        };
         for (uint32_t c = wc0 + lane; c < wc1; c += 64) sVold[c] = sV[sDet[c]];
+        if (!lay.lean) {
+            for (uint32_t i = wva + lane; i < wvb; i += 64) row(i, sD[i], sB[i]);
+        }
         wave_sync();
         STAGE_MARK(0);
         // the cable solve of the share's cells
         if (wva == wvb) {
             // no cells of this share
-        } else if (use_pcr) {
-            // unbranched cells, mixed form: partition method on the lanes
-            const bool ok = wvb - wva <= 64 ? pcr_cells(wva, wvb, wpcr, lane, sPar, sAx, sD, sB, sV)
-                                            : part_cells<PART_M>(wva, wvb, wpcr, lane, sPar, sAx, sD, sB, sV);
+        } else if (lay.lean) {
+            // unbranched cells, mixed form: the lanes assemble the rows and
+            // solve by cyclic reduction or the partition method
+            const bool ok = wvb - wva <= 64 ? pcr_cells(wva, wvb, wpcr, lane, sPar, sAx, row, sV)
+                                            : part_cells<CHAIN_ROWS>(wva, wvb, wpcr, lane, sPar, sAx, row, sV);
             if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + wc0);
         } else {
             // Hines elimination level-scheduled over branch segments,
@@ -695,7 +727,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     auto synapse_step = [&](uint32_t st) {
         const uint64_t n = n0 + st;
         const uint32_t cur = (uint32_t)(n - nbase) & 1u, nxt = cur ^ 1u;
-        T *gc = sG + cur * ns, *gn = sG + nxt * ns;
+        T *gc = sG + gofs(cur), *gn = sG + gofs(nxt);
         uint8_t *postc = sPost + cur * ncb;
         // synapse updates of step n (from step-start values) with the
         // cell's protein trigger sum: lane l sums the cell's synapses
@@ -724,16 +756,18 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             if (lane == 0) sP[c] = prp_next(d, p, S);
         }
         STAGE_MARK(3);
-        if (st + 1 < nst) {
-            if (carry_sums) {
-                for (uint32_t i = uva + lane; i < uvb; i += 64) {
-                    sGs[nxt * nv + i] = sGs[cur * nv + i] * sDecCv[i];
-                    sGsE[nxt * nv + i] = sGsE[cur * nv + i] * sDecCv[i];
-                }
+        // carried sums decay to the next step also after an epoch's last
+        // step (the next epoch, or launch, starts from them)
+        if (lay.carried) {
+            for (uint32_t i = uva + lane; i < uvb; i += 64) {
+                sGs[nxt * nv + i] = sGs[cur * nv + i] * sDecCv[i];
+                sGsE[nxt * nv + i] = sGsE[cur * nv + i] * sDecCv[i];
             }
+        }
+        if (st + 1 < nst) {
             wave_sync();
             deliver(st + 1, gn, nxt);
-            if (!EXACT && !carry_sums) {
+            if (!EXACT && !lay.carried) {
                 wave_sync();
                 cv_sums(gn, nxt);
             }
@@ -776,9 +810,15 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     STAGE_MARK(5);
     // ---- stage out
     const uint32_t hfin = (uint32_t)((multi ? (uint64_t)n_ep * K : nsteps) & 1u);
-    const T *gfin = sG + hfin * ns;
+    const T *gfin = sG + gofs(hfin);
     const uint8_t *pfin = sPost + hfin * ncb;
-    for (uint32_t i = tid; i < nv; i += BS) d.V[v0 + i] = sV[i];
+    for (uint32_t i = tid; i < nv; i += BS) {
+        d.V[v0 + i] = sV[i];
+        if (lay.carried) {
+            d.gsum[v0 + i] = sGs[hfin * nv + i];
+            d.gesum[v0 + i] = sGsE[hfin * nv + i];
+        }
+    }
     for (uint32_t s = tid; s < ns; s += BS) {
         ((T *)d.g)[s0 + s] = gfin[s];
         ((T *)d.c)[s0 + s] = sC[s];
@@ -798,6 +838,27 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     if (multi && blockIdx.x == 0 && tid == 0) d.ctr->step = nbase + (uint64_t)n_ep * K;
     STAGE_MARK(7);
     STAGE_FLUSH();
+}
+
+// Carried per-CV sums from the conductances (mixed form), one lane per CV,
+// in synapse order.
+__global__ void k_carried_sums(DevNet d) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.n_cv) return;
+    const float *g = (const float *)d.g;
+    double gs = 0.0, ge = 0.0;
+    for (uint32_t q = d.cv_syn_off[i]; q < d.cv_syn_off[i + 1]; ++q) {
+        gs += (double)g[q];
+        ge += (double)g[q] * d.syn_erev[q];
+    }
+    d.gsum[i] = gs;
+    d.gesum[i] = ge;
+}
+
+int launch_carried_sums(const DevNet &d, void *stream) {
+    if (!d.gsum || d.n_cv == 0) return 0;
+    hipLaunchKernelGGL(k_carried_sums, dim3((d.n_cv + 255) / 256), dim3(256), 0, (hipStream_t)stream, d);
+    return (int)hipGetLastError();
 }
 
 template <class T, uint32_t BS>
@@ -898,6 +959,7 @@ constexpr size_t LDS_MAX = 160 * 1024;
 struct Offsets {
     std::vector<uint32_t> cv, syn, hh, seg;
     uint32_t tsize, K;
+    bool carried;  // mixed form with carried per-CV sums
 };
 
 // Packs consecutive cells, at most cpb per workgroup, within an LDS budget
@@ -907,7 +969,7 @@ bool pack(const Offsets &o, uint32_t cpb, uint32_t threads, std::vector<uint32_t
     const uint32_t nc = (uint32_t)o.cv.size() - 1;
     auto bytes = [&](uint32_t a, uint32_t e) {
         return (size_t)FusedLayout(o.cv[e] - o.cv[a], o.syn[e] - o.syn[a], o.hh[e] - o.hh[a], e - a, o.K,
-                                   o.tsize, o.seg[e] - o.seg[a]).total;
+                                   o.tsize, o.seg[e] - o.seg[a], o.carried).total;
     };
     blk.assign(1, 0);
     lds = 0;
@@ -971,6 +1033,7 @@ pa_status batched_setup(pa_sim *s) {
     o.hh.resize(d.n_cells + 1);
     o.tsize = d.mixed ? 4 : 8;
     o.K = d.K;
+    o.carried = d.mixed && d.cv_dec_uniform;
     o.seg.resize(d.n_cells + 1);
     if (hipMemcpy(o.seg.data(), d.seg_off, o.seg.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(o.cv.data(), d.cv_off, o.cv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||

@@ -78,6 +78,10 @@ struct DevNet {
     const uint32_t *cv_syn_off;  // n_cv + 1
     const double *cv_dec;        // per CV: the decay factor its synapses share (1 if none)
     uint32_t cv_dec_uniform;     // every CV's synapses share one decay factor
+    // batched mixed form with a shared decay factor per CV: summed synaptic
+    // conductance and conductance x reversal potential of each CV, decayed
+    // to the next step and still without its events (state, n_cv each)
+    double *gsum, *gesum;
     const uint32_t *cv_cl_off;   // n_cv + 1, into clamps sorted by (CV, id)
     double *V, *I, *G, *D, *b;
 
@@ -164,6 +168,9 @@ int launch_epoch_fused(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, cons
 // Workgroups of the fused kernel that can be resident at once (0 if the
 // device does not support cooperative launches).
 uint32_t epoch_fused_capacity(bool mixed, uint32_t block_threads, size_t lds_bytes);
+// Recomputes gsum and gesum from the synapse conductances (after they were
+// written from the host).
+int launch_carried_sums(const DevNet &d, void *stream);
 int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream);
 
 }  // namespace pa

@@ -223,6 +223,34 @@ def test_mixed_exchange_modes_are_bitwise_identical():
         np.testing.assert_array_equal(a, b)
 
 
+def test_mixed_written_conductances_reach_the_currents():
+    """Mixed form with one decay factor per CV carries the per-CV
+    conductance sums as state; conductances written from the host must
+    reach them, so the next steps agree with the oracle given the same
+    conductances (to the mixed form's rounding)."""
+    net = netgen._ei_network("small-ei", 20, 3, 100.0, n_e=16, n_i=4, p=0.3, w_ext=0.004, ext_rate=40.0)
+    rng = np.random.default_rng(5)
+    for x in ("kernel", "resident"):
+        _say(f"mixed small-ei conductance write exchange={x}")
+        o = oracle.Oracle(net)
+        s = Simulation(net, mode="batched", precision="mixed", exchange=x, cells_per_block=2,
+                       block_threads=128, solver_waves=1)
+        ref = oracle.Oracle(net)
+        for x_ in (o, s, ref):
+            x_.advance_steps(30) if x_ is s else x_.run(30)
+        g = rng.uniform(0.0, 0.01, o.n_syn)
+        o.write("g", g)
+        s.write("g", g)
+        for _ in range(3):
+            o.run(1)
+            ref.run(1)
+            s.advance_steps(1)
+            vo, vs = o.read("V"), s.read("V")
+            assert np.abs(vs - vo).max() < 1e-3, np.abs(vs - vo).max()
+        # the written conductances moved V
+        assert np.abs(o.read("V") - ref.read("V")).max() > 0.1
+
+
 def test_resident_exchange_matches_oracle_on_ei_network():
     net = netgen.config2(t_end=200.0)
     _say("config2 resident exchange 300 steps")
