@@ -60,7 +60,7 @@ struct FusedLayout {
     // events of the epoch, each slot's records sorted into delivery order
     uint32_t EvBuf, ev_cap;
     // 16-bit, 8-bit
-    uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, Kind, Post, SegLvl;
+    uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, SegOrd, LvlOff, Kind, Post, SegLvl;
     uint32_t total;
     // lean: mixed-form workgroup of unbranched cells solved by the lanes
     // with the rows assembled in registers (no D, B); carried: mixed form
@@ -101,6 +101,9 @@ struct FusedLayout {
         SynCv = take(2 * (tsize == 4 ? ns : 0), 2);
         SegA = take(2 * ng, 2); SegB = take(2 * ng, 2); SegCell = take(2 * ng, 2);
         KidOff = take(2 * (ng + 1), 2); Kids = take(2 * ng, 2);
+        // tree solve: each solver wavefront's segments ordered by level,
+        // and where each level starts
+        SegOrd = take(lean ? 0 : 2 * ng, 2); LvlOff = take(lean ? 0 : 2 * (ng + 4), 2);
         Kind = take(ns, 1); Post = take(2 * nc, 1); SegLvl = take(ng, 1);
         total = (o + 15) / 16 * 16;
     }
@@ -109,10 +112,10 @@ struct FusedLayout {
 #ifdef PA_STAGE_TIMING
 // Diagnostic build only: wall-clock ticks per stage, summed over the solver
 // wavefronts (entries 0-7) and the synapse wavefronts (8-15).
-__device__ unsigned long long pa_stage_ticks[16];
-#define STAGE_INIT() uint64_t st_prev_ = wall_clock64(); uint64_t st_acc_[8] = {0, 0, 0, 0, 0, 0, 0, 0}
+__device__ unsigned long long pa_stage_ticks[24];
+#define STAGE_INIT() uint64_t st_prev_ = wall_clock64(); uint64_t st_acc_[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}
 #define STAGE_MARK(k_) do { if (lane == 0) { const uint64_t t_ = wall_clock64(); st_acc_[k_] += t_ - st_prev_; st_prev_ = t_; } } while (0)
-#define STAGE_FLUSH() do { if (lane == 0) for (int k_ = 0; k_ < 8; ++k_) atomicAdd(&pa_stage_ticks[k_ + (solver ? 0 : 8)], (unsigned long long)st_acc_[k_]); } while (0)
+#define STAGE_FLUSH() do { if (lane == 0) for (int k_ = 0; k_ < 12; ++k_) atomicAdd(&pa_stage_ticks[k_ + (solver ? 0 : 12)], (unsigned long long)st_acc_[k_]); } while (0)
 #else
 #define STAGE_INIT() do {} while (0)
 #define STAGE_MARK(k_) do {} while (0)
@@ -396,6 +399,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     uint16_t *sSegA = (uint16_t *)(L + lay.SegA), *sSegB = (uint16_t *)(L + lay.SegB);
     uint16_t *sSegCell = (uint16_t *)(L + lay.SegCell), *sKidOff = (uint16_t *)(L + lay.KidOff);
     uint16_t *sKids = (uint16_t *)(L + lay.Kids);
+    uint16_t *sSegOrd = (uint16_t *)(L + lay.SegOrd), *sLvlOff = (uint16_t *)(L + lay.LvlOff);
     Event *sEv = (Event *)(L + lay.EvBuf);
     // blocks whose cells are all unbranched (one segment per cell)
     const bool chains = (ng == ncb);
@@ -497,6 +501,25 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     for (uint32_t c = wc0 + lane; c < wc1; c += 64) wlen = max(wlen, sCb0[c + 1] - sCb0[c]);
     wlev = wave_max(wlev);
     wlen = wave_max(wlen);
+    // tree solve: the share's segments in level order (cell order within
+    // a level), level lv at sSegOrd[lo .. hi) with lo, hi =
+    // sLvlOff[wga + wave + lv], sLvlOff[wga + wave + lv + 1]
+    if (solver && !lay.lean) {
+        uint32_t pos = wga;
+        const uint64_t below = (1ull << lane) - 1ull;
+        for (uint32_t lv = 0; lv < wlev; ++lv) {
+            if (lane == 0) sLvlOff[wga + wave + lv] = (uint16_t)pos;
+            for (uint32_t gb = wga; gb < wgb; gb += 64) {
+                const uint32_t g = gb + lane;
+                const bool m = g < wgb && sSegLvl[g] == lv;
+                const uint64_t bal = __ballot(m);
+                if (m) sSegOrd[pos + (uint32_t)__popcll(bal & below)] = (uint16_t)g;
+                pos += (uint32_t)__popcll(bal);
+            }
+        }
+        if (lane == 0) sLvlOff[wga + wave + wlev] = (uint16_t)pos;
+        wave_sync();
+    }
     // lanes' solve of unbranched cells (mixed form): rows per lane, and
     // reduction rounds for the most chunk ends one cell holds
     const uint32_t wrows = max(1u, (wvb - wva + 63) >> 6);
@@ -549,6 +572,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         }
     };
 
+    STAGE_MARK(6);
     for (uint32_t ep = 0; ep < n_ep; ++ep) {
     n0 = nbase + (uint64_t)ep * K;
     const uint32_t nst = multi ? K : nsteps;
@@ -563,6 +587,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     }
     if (tid == 0) sScan[0] = 0;
     __syncthreads();
+    STAGE_MARK(9);
     // events of the epoch: one lane per (cell, step) slot takes the slot's
     // count, claims room in the LDS event buffer, copies the records there
     // and sorts them into delivery order (a slot that does not fit is
@@ -598,7 +623,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         }
     }
     __syncthreads();
-    STAGE_MARK(6);
+    STAGE_MARK(10);
 
     // the first step's events, and its conductance sums (carried sums
     // enter the epoch already decayed to this step)
@@ -613,6 +638,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         }
     }
     __syncthreads();
+    STAGE_MARK(11);
 
     // one step of each role (n = n0 + st); the roles run in separate loops
     // so that each loop keeps only its own role's values live
@@ -658,9 +684,10 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             // deepest level first; a branch point takes its children's
             // contributions in descending child order, as in the
             // sequential elimination
+            const uint16_t *lo = sLvlOff + wga + wave;
             for (int lv = (int)wlev - 1; lv >= 0; --lv) {
-                for (uint32_t g = wga + lane; g < wgb; g += 64) {
-                    if (sSegLvl[g] != (uint32_t)lv) continue;
+                for (uint32_t q = lo[lv] + lane; q < lo[lv + 1]; q += 64) {
+                    const uint32_t g = sSegOrd[q];
                     const uint32_t a = sSegA[g], b = sSegB[g];
                     double dc = sD[b], bc = sB[b];
                     for (uint32_t q = sKidOff[g]; q < sKidOff[g + 1]; ++q) {
@@ -679,8 +706,8 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
                 wave_sync();
             }
             for (uint32_t lv = 0; lv < wlev; ++lv) {
-                for (uint32_t g = wga + lane; g < wgb; g += 64) {
-                    if (sSegLvl[g] != lv) continue;
+                for (uint32_t q = lo[lv] + lane; q < lo[lv + 1]; q += 64) {
+                    const uint32_t g = sSegOrd[q];
                     const uint32_t a = sSegA[g], b = sSegB[g];
                     const int32_t p = sPar[a];
                     sV[a] = (p < 0) ? qdiv<EXACT>(sB[a], sD[a]) : qdiv<EXACT>(sB[a] - (-sAx[a]) * sV[p], sD[a]);
@@ -803,6 +830,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         const uint32_t nsp = *sSpkN;
         for (uint32_t k = wave; k < nsp; k += NW) expand_spike(d, c0 + sSpkC[k], sSpkT[k], lane, n0 + K);
         const bool ok = grid_sync(d, gridDim.x, sScan + 2);
+        STAGE_MARK(8);
         if (tid == 0) *sSpkN = 0;
         if (!ok) break;
     }
@@ -916,10 +944,10 @@ uint32_t epoch_fused_capacity(bool mixed, uint32_t block_threads, size_t lds_byt
 
 #ifdef PA_STAGE_TIMING
 extern "C" int pa_debug_stage_ticks(unsigned long long *out, int reset) {
-    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(pa::pa_stage_ticks), 16 * sizeof(unsigned long long)) != hipSuccess)
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(pa::pa_stage_ticks), 24 * sizeof(unsigned long long)) != hipSuccess)
         return -1;
     if (reset) {
-        unsigned long long z[16] = {};
+        unsigned long long z[24] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(pa::pa_stage_ticks), z, sizeof z) != hipSuccess) return -1;
     }
     return 0;
