@@ -798,7 +798,7 @@ pa_status build(pa_sim *s) {
     d.cl_amp = upload(s, clamp, ok);
     d.ev_n = zeros<uint32_t>(s, (size_t)nc * d.R, ok);
     d.blk_done = zeros<uint64_t>(s, std::max<size_t>(1, nc), ok);
-    d.bar_grp = zeros<uint32_t>(s, 32 * 32, ok);
+    d.bar_grp = zeros<uint32_t>(s, 34 * 32, ok);  // 32 group counters, top counter, release word
     d.ev = (Event *)dev_alloc(s, (size_t)nc * d.R * d.Q * sizeof(Event));
     if (!d.ev) ok = false;
     d.ep_gid = zeros<uint32_t>(s, (size_t)nc * K, ok);
@@ -1229,7 +1229,7 @@ pa_status pa_snapshot(pa_sim *s, int restore) {
         {d.S, (size_t)d.n_cells * 8}, {d.vdet_old, (size_t)d.n_cells * 8}, {d.post, (size_t)d.n_cells},
         {d.ev_cnt, (size_t)d.n_syn * 16}, {d.ev_sum, (size_t)d.n_syn * 16},
         {d.gsum, d.gsum ? (size_t)d.n_cv * 8 : 0}, {d.gesum, d.gesum ? (size_t)d.n_cv * 8 : 0},
-        {d.ev_n, (size_t)d.n_cells * d.R * 4}, {d.blk_done, (size_t)d.n_cells * 8}, {d.bar_grp, 32 * 32 * 4},
+        {d.ev_n, (size_t)d.n_cells * d.R * 4}, {d.blk_done, (size_t)d.n_cells * 8}, {d.bar_grp, 34 * 32 * 4},
         {d.tr_cur, (size_t)d.n_trains * 16},
         {d.pois_t, (size_t)d.n_pois * 8}, {d.pois_j, (size_t)d.n_pois * 8},
         {d.ctr, sizeof(Counters)}};

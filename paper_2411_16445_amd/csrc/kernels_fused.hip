@@ -60,7 +60,7 @@ struct FusedLayout {
     // events of the epoch, each slot's records sorted into delivery order
     uint32_t EvBuf, ev_cap;
     // 16-bit, 8-bit
-    uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, SegOrd, LvlOff, Kind, Post, SegLvl;
+    uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, Kind, Post, SegLvl;
     uint32_t total;
     // lean: mixed-form workgroup of unbranched cells solved by the lanes
     // with the rows assembled in registers (no D, B); carried: mixed form
@@ -101,9 +101,6 @@ struct FusedLayout {
         SynCv = take(2 * (tsize == 4 ? ns : 0), 2);
         SegA = take(2 * ng, 2); SegB = take(2 * ng, 2); SegCell = take(2 * ng, 2);
         KidOff = take(2 * (ng + 1), 2); Kids = take(2 * ng, 2);
-        // tree solve: each solver wavefront's segments ordered by level,
-        // and where each level starts
-        SegOrd = take(lean ? 0 : 2 * ng, 2); LvlOff = take(lean ? 0 : 2 * (ng + 4), 2);
         Kind = take(ns, 1); Post = take(2 * nc, 1); SegLvl = take(ng, 1);
         total = (o + 15) / 16 * 16;
     }
@@ -284,16 +281,20 @@ __device__ __forceinline__ bool part_cells(uint32_t va, uint32_t vb, uint32_t le
 
 // Barrier across all workgroups of a cooperative launch (all resident).
 // Workgroup b counts itself into group counter b mod G (G = 32 counters on
-// separate cache lines, so about nblocks/G workgroups contend for each),
-// then its first wavefront reads the G counters until each holds its
-// group's size times the number of barriers passed so far (kept per
-// workgroup in blk_done).  Everything other workgroups read after the
-// barrier (event rings and counts) is written and read with device-coherent
-// accesses, so no cache write-back or invalidation is needed; the count is
-// ordered after this workgroup's writes by waiting for them to complete.
-// A wait that lasts about a second, or a barrier failure raised elsewhere,
-// makes the workgroup give up (returns false) instead of hanging.
+// separate cache lines, so about nblocks/G workgroups contend for each);
+// the workgroup that completes its group counts the group into a top
+// counter, and the one that completes the top counter publishes the
+// barrier's number in a release word, which the first wavefront of every
+// workgroup polls (k-th barrier of the present plan: group counter at k
+// times the group's size, top counter at k G; each workgroup keeps k in
+// blk_done).  Everything other workgroups read after the barrier (event
+// rings and counts) is written and read with device-coherent accesses, so
+// no cache write-back or invalidation is needed; the count is ordered after
+// this workgroup's writes by waiting for them to complete.  A wait that
+// lasts about a second, or a barrier failure raised elsewhere, makes the
+// workgroup give up (returns false) instead of hanging.
 constexpr uint32_t BAR_GROUPS = 32, BAR_STRIDE = 32;  // counters 128 bytes apart
+constexpr uint32_t BAR_TOP = BAR_GROUPS * BAR_STRIDE, BAR_RELEASE = BAR_TOP + BAR_STRIDE;
 
 __device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) {
     __builtin_amdgcn_s_waitcnt(0);
@@ -308,21 +309,22 @@ __device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) 
         wave_sync();
         if (lane == 0) {
             st_coh(d.blk_done + blockIdx.x, k);
-            __hip_atomic_fetch_add(d.bar_grp + (blockIdx.x % G) * BAR_STRIDE, 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t g = blockIdx.x % G;
+            const uint32_t size = nblocks / G + (g < nblocks % G ? 1u : 0u);
+            const uint32_t before = __hip_atomic_fetch_add(d.bar_grp + g * BAR_STRIDE, 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint64_t)before + 1 == k * size) {
+                const uint32_t tb = __hip_atomic_fetch_add(d.bar_grp + BAR_TOP, 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint64_t)tb + 1 == k * G) st_coh(d.bar_grp + BAR_RELEASE, (uint32_t)k);
+            }
         }
         uint32_t ok = 1, spins = 0;
-        for (;;) {
-            bool mine = true;
-            if (lane < G) {
-                const uint32_t size = nblocks / G + (lane < nblocks % G ? 1u : 0u);
-                mine = (uint64_t)ld_coh(d.bar_grp + lane * BAR_STRIDE) >= k * size;
-            }
-            if (__ballot(!mine) == 0) break;
+        while ((uint64_t)ld_coh(d.bar_grp + BAR_RELEASE) < k) {
             // back off so that spinning wavefronts leave the issue slots of
             // their compute unit to workgroups still in the epoch
-            if (spins < 16) __builtin_amdgcn_s_sleep(1);
-            else if (spins < 64) __builtin_amdgcn_s_sleep(4);
+            if (spins < 256) __builtin_amdgcn_s_sleep(1);
+            else if (spins < 1024) __builtin_amdgcn_s_sleep(4);
             else __builtin_amdgcn_s_sleep(16);
             if ((++spins & 255u) == 0 && (ld_coh(&d.ctr->flags) & FLAG_BARRIER)) {
                 ok = 0;
@@ -399,7 +401,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     uint16_t *sSegA = (uint16_t *)(L + lay.SegA), *sSegB = (uint16_t *)(L + lay.SegB);
     uint16_t *sSegCell = (uint16_t *)(L + lay.SegCell), *sKidOff = (uint16_t *)(L + lay.KidOff);
     uint16_t *sKids = (uint16_t *)(L + lay.Kids);
-    uint16_t *sSegOrd = (uint16_t *)(L + lay.SegOrd), *sLvlOff = (uint16_t *)(L + lay.LvlOff);
     Event *sEv = (Event *)(L + lay.EvBuf);
     // blocks whose cells are all unbranched (one segment per cell)
     const bool chains = (ng == ncb);
@@ -501,25 +502,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     for (uint32_t c = wc0 + lane; c < wc1; c += 64) wlen = max(wlen, sCb0[c + 1] - sCb0[c]);
     wlev = wave_max(wlev);
     wlen = wave_max(wlen);
-    // tree solve: the share's segments in level order (cell order within
-    // a level), level lv at sSegOrd[lo .. hi) with lo, hi =
-    // sLvlOff[wga + wave + lv], sLvlOff[wga + wave + lv + 1]
-    if (solver && !lay.lean) {
-        uint32_t pos = wga;
-        const uint64_t below = (1ull << lane) - 1ull;
-        for (uint32_t lv = 0; lv < wlev; ++lv) {
-            if (lane == 0) sLvlOff[wga + wave + lv] = (uint16_t)pos;
-            for (uint32_t gb = wga; gb < wgb; gb += 64) {
-                const uint32_t g = gb + lane;
-                const bool m = g < wgb && sSegLvl[g] == lv;
-                const uint64_t bal = __ballot(m);
-                if (m) sSegOrd[pos + (uint32_t)__popcll(bal & below)] = (uint16_t)g;
-                pos += (uint32_t)__popcll(bal);
-            }
-        }
-        if (lane == 0) sLvlOff[wga + wave + wlev] = (uint16_t)pos;
-        wave_sync();
-    }
     // lanes' solve of unbranched cells (mixed form): rows per lane, and
     // reduction rounds for the most chunk ends one cell holds
     const uint32_t wrows = max(1u, (wvb - wva + 63) >> 6);
@@ -684,10 +666,9 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             // deepest level first; a branch point takes its children's
             // contributions in descending child order, as in the
             // sequential elimination
-            const uint16_t *lo = sLvlOff + wga + wave;
             for (int lv = (int)wlev - 1; lv >= 0; --lv) {
-                for (uint32_t q = lo[lv] + lane; q < lo[lv + 1]; q += 64) {
-                    const uint32_t g = sSegOrd[q];
+                for (uint32_t g = wga + lane; g < wgb; g += 64) {
+                    if (sSegLvl[g] != (uint32_t)lv) continue;
                     const uint32_t a = sSegA[g], b = sSegB[g];
                     double dc = sD[b], bc = sB[b];
                     for (uint32_t q = sKidOff[g]; q < sKidOff[g + 1]; ++q) {
@@ -706,8 +687,8 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
                 wave_sync();
             }
             for (uint32_t lv = 0; lv < wlev; ++lv) {
-                for (uint32_t q = lo[lv] + lane; q < lo[lv + 1]; q += 64) {
-                    const uint32_t g = sSegOrd[q];
+                for (uint32_t g = wga + lane; g < wgb; g += 64) {
+                    if (sSegLvl[g] != lv) continue;
                     const uint32_t a = sSegA[g], b = sSegB[g];
                     const int32_t p = sPar[a];
                     sV[a] = (p < 0) ? qdiv<EXACT>(sB[a], sD[a]) : qdiv<EXACT>(sB[a] - (-sAx[a]) * sV[p], sD[a]);

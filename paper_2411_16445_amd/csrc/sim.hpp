@@ -130,7 +130,7 @@ struct DevNet {
     // event rings
     uint32_t *ev_n;              // n_cells * R
     uint64_t *blk_done;          // n_cells: per workgroup, grid barriers passed (multi-epoch kernel)
-    uint32_t *bar_grp;           // 32 grid-barrier group counters, 128 bytes apart
+    uint32_t *bar_grp;           // grid barrier: 32 group counters, top counter, release word (128 bytes apart)
     Event *ev;                   // n_cells * R * Q
 
     // spikes
