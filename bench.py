@@ -107,6 +107,11 @@ def cpu_baseline(net, n_steps):
                        f"single-threaded plain FP64 C oracle, {el:.1f} s")
 
 
+# workloads: name in the JSON line, network builder
+WORKLOADS = {"ei2000x21": ("ei-ball-and-stick-2000x21cv", "config2"),
+             "ei2000x101": ("ei-ball-and-stick-2000x101cv", "config4")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +125,8 @@ def main():
     ap.add_argument("--plan", default="",
                     help="fix the batched form's plan instead of autotuning it: "
                          "CELLS_PER_BLOCK,BLOCK_THREADS,SOLVER_WAVES,EXCHANGE (kernel|resident)")
+    ap.add_argument("--workload", default="ei2000x21", choices=sorted(WORKLOADS),
+                    help="ei2000x21: the headline network; ei2000x101: the same network with 100-CV dendrites")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the runs, copy this many MiB device to device (a plain copy kernel of known "
                          "size that scales rocprofv3's FETCH_SIZE / WRITE_SIZE)")
@@ -130,7 +137,8 @@ def main():
         sys.exit(2)
     import netgen
     t_end = (args.warmup + args.steps + 10) * 0.2
-    net = netgen.config2(t_end=t_end)
+    wname, make = WORKLOADS[args.workload]
+    net = getattr(netgen, make)(t_end=t_end)
     print(f"[bench] network {netgen.summary(net)}", file=sys.stderr, flush=True)
     plan = None
     if args.plan:
@@ -157,7 +165,7 @@ def main():
         torch.cuda.synchronize()
     k = head.get("kernel", {})
     from paper_2411_16445_amd.profiling import traffic_for_bench
-    traffic, traffic_src = traffic_for_bench(os.path.join(ROOT, "profiles"), k.get("name") or "")
+    traffic, traffic_src = traffic_for_bench(os.path.join(ROOT, "profiles"), k.get("name") or "", args.workload)
     steps_per_launch = args.steps / max(1, k.get("launches") or 1)
     line = {
         "metric": "CV-steps/s + synapse-updates/s, mixed+batched vs plain FP64 at equal spikes",
@@ -172,7 +180,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32" if args.form.endswith("mixed") else "f64",
         "data": "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network)",
-        "config": {"workload": "ei-ball-and-stick-2000x21cv", "cells": head["stats"]["n_cells"],
+        "config": {"workload": wname, "cells": head["stats"]["n_cells"],
                    "cvs": head["stats"]["n_cv"], "synapses": head["stats"]["n_syn"],
                    "stc_synapses": head["stats"]["n_stc"], "dt_ms": 0.2, "form": args.form,
                    "epoch_steps": head["epoch_steps"], "cells_per_block": head["cells_per_block"],

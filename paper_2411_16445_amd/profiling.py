@@ -3,8 +3,8 @@
 Two uses:
 
 * ``python -m paper_2411_16445_amd.profiling counters FETCH_DIR WRITE_DIR
-  --kernel k_epoch --copy-mib 256 --steps-per-dispatch N --command "..."
-  > profiles/<name>.md``
+  --kernel k_epoch --copy-mib 256 --steps-per-dispatch N --workload W
+  --command "..." > profiles/<name>.md``
   turns two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
   ``bench.py --copy-probe-mib 256`` into the HBM traffic per launch of the
   kernel.  Both counters are in KiB per dispatch; each is scaled by what it
@@ -64,7 +64,7 @@ def _per_dispatch(rows, counter, pick):
     return list(out.values())
 
 
-def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_dispatch):
+def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_dispatch, workload):
     copy_bytes = copy_mib * 1024 * 1024
     lines = []
     res = {}
@@ -106,6 +106,7 @@ def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_
     lines.append(f"traffic_bytes_per_launch: {total:.0f}")
     lines.append(f"traffic_bytes_per_step: {total / steps_per_dispatch:.1f}")
     lines.append(f"kernel: {kernel}")
+    lines.append(f"workload: {workload}")
     lines.append(f"source_sha256: {fp}")
     return "\n".join(lines) + "\n"
 
@@ -130,10 +131,10 @@ def trace_summary(stats_csv, command, title):
     return "\n".join(lines) + "\n"
 
 
-def traffic_for_bench(profiles_dir, kernel):
+def traffic_for_bench(profiles_dir, kernel, workload):
     """(HBM bytes per step, summary file) from a counters summary of this
-    kernel whose source fingerprint equals the present sources, else
-    (None, reason)."""
+    kernel and workload whose source fingerprint equals the present
+    sources, else (None, reason)."""
     if not os.path.isdir(profiles_dir):
         return None, "no profiles directory"
     fp = source_fingerprint()
@@ -146,7 +147,10 @@ def traffic_for_bench(profiles_dir, kernel):
         m_k = re.search(r"^kernel: (.+)$", text, re.M)
         m_t = re.search(r"^traffic_bytes_per_step: ([0-9.]+)$", text, re.M)
         m_s = re.search(r"^source_sha256: ([0-9a-f]+)$", text, re.M)
-        if not (m_k and m_t and m_s) or m_k.group(1).strip() not in kernel:
+        m_w = re.search(r"^workload: (.+)$", text, re.M)
+        if not (m_k and m_t and m_s and m_w) or m_k.group(1).strip() not in kernel:
+            continue
+        if m_w.group(1).strip() != workload:
             continue
         if m_s.group(1) != fp:
             stale = fn
@@ -165,6 +169,7 @@ def main(argv=None):
     c.add_argument("--kernel", default="k_epoch")
     c.add_argument("--copy-mib", type=int, default=256)
     c.add_argument("--steps-per-dispatch", type=int, required=True)
+    c.add_argument("--workload", required=True)
     c.add_argument("--command", action="append", default=[])
     t = sub.add_parser("trace")
     t.add_argument("stats_csv")
@@ -174,7 +179,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "counters":
         sys.stdout.write(counters_summary(a.fetch_dir, a.write_dir, a.kernel, a.copy_mib, a.command,
-                                          a.steps_per_dispatch))
+                                          a.steps_per_dispatch, a.workload))
     elif a.cmd == "trace":
         sys.stdout.write(trace_summary(a.stats_csv, a.command, a.title))
     else:

@@ -223,6 +223,46 @@ def test_mixed_exchange_modes_are_bitwise_identical():
         np.testing.assert_array_equal(a, b)
 
 
+def _passive_chains(lengths):
+    """Unbranched passive cells of the given CV counts (2 um CVs, 1 um
+    diameter, a 20 um first CV), each driven by current clamps on its first
+    and last CV, no synapses: the mixed form then computes every current in
+    FP64 and differs from the FP64 oracle only by how it solves the cable
+    systems."""
+    b = netgen._Builder()
+    for c, n in enumerate(lengths):
+        b.add_cell([-1] + list(range(n - 1)), [20.0] + [2.0] * (n - 1), [20.0] + [1.0] * (n - 1),
+                   [netgen.MECH_PAS] * n)
+        b.add_clamp(c, 0, 0.4 + 0.2 * (c % 3), 4.0, 0.05 + 0.02 * c)
+        b.add_clamp(c, n - 1, 1.0, 3.0, -0.01 * (1 + c % 4))
+    return b.finish("passive-chains", 0.2, 20.0, 17, netgen.STC_TABLE5)
+
+
+@pytest.mark.parametrize("shape", [
+    dict(cells_per_block=1, block_threads=64),
+    dict(cells_per_block=2, block_threads=128, solver_waves=1),
+    dict(cells_per_block=3, block_threads=256, solver_waves=2),
+    dict(cells_per_block=4, block_threads=256, solver_waves=3),
+])
+def test_mixed_chain_solve_matches_oracle(shape):
+    """The mixed form's lane solves of unbranched cells (cyclic reduction up
+    to 64 CVs a wavefront, the partition method with 2, 3 or 4 CVs a lane
+    above, cells sharing a lane's chunk, ragged last chunks; elimination for
+    workgroups over 256 CVs) against the FP64 oracle on passive chains: the
+    voltages agree to the FP64 bar."""
+    lengths = [101, 130, 1, 2, 65, 64, 37, 255, 3, 90, 129, 5]
+    net = _passive_chains(lengths)
+    _say(f"mixed passive chains {shape}")
+    o = oracle.Oracle(net)
+    s = Simulation(net, mode="batched", precision="mixed", exchange="kernel", **shape)
+    for _ in range(4):
+        o.run(10)
+        s.advance_steps(10)
+        vo, vs = o.read("V"), s.read("V")
+        assert np.all(np.abs(vs - vo) <= 1e-9 * np.maximum(np.abs(vo), 1.0)), np.abs(vs - vo).max()
+    assert np.abs(o.read("V") - o.read("V")[0]).max() > 0.1  # the clamps moved V
+
+
 def test_mixed_written_conductances_reach_the_currents():
     """Mixed form with one decay factor per CV carries the per-CV
     conductance sums as state; conductances written from the host must
