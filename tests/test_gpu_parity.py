@@ -62,6 +62,18 @@ def test_ei_network_full_size_short_horizon(mode):
 
 
 @pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_long_dendrite_network_full_size_short_horizon(mode):
+    """The E/I network with 100-CV dendrites (2000 x 101 CVs), 40 ms, FP64:
+    long unbranched cells through the elimination at full size."""
+    net = netgen.config4(t_end=100.0)
+    _say(f"config4 full size 200 steps mode={mode}")
+    o, s = run_pair(net, 200, chunks=2, mode=mode)
+    assert assert_raster_equal(o, s) > 100
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
 def test_uneven_trees_full_size_short_horizon(mode):
     """4096 random trees of 10-300 CVs, 100 plastic sites each, 30 ms."""
     net = netgen.config3(t_end=60.0)
