@@ -600,3 +600,170 @@ def test_poisson_source_is_a_poisson_process():
     assert abs(int(cnt[0, 0]) - lam) < 5 * math.sqrt(lam)
     # calcium events trail the conductance events by t_c,delay (94 steps)
     assert int(cnt[0, 0]) - int(cnt[0, 1]) <= 8
+
+
+# ------------------------------------------------------------------ Eq. 16 at the conductance port
+@pytest.mark.parametrize("h_init,z_init", [(STC["h0"], 1.0), (STC["h0"] + 1.7, 0.0), (STC["h0"] - 0.9, -0.35),
+                                           (2.5, 0.6)])
+def test_conductance_port_scales_with_total_weight(h_init, z_init):
+    """Eq. 16: the total weight of a plastic synapse is w = h + h0 z, h0 its
+    baseline; a conductance-port event adds the connection weight times
+    w / h0 (reading R10).  So z = 1 at h = h0 doubles the increment of a
+    plain synapse, and z = 0 scales it by h / h0."""
+    stc = dict(STC)
+    stc["sigma_pl"] = 0.0
+    b = netgen._Builder()
+    b.add_cell([-1], [20.0], [20.0], [netgen.MECH_PAS])
+    s_stc = b.add_syn(0, 0, netgen.KIND_STC, 5.0, 0.0)
+    s_exp = b.add_syn(0, 0, netgen.KIND_EXPSYN, 5.0, 0.0)
+    w = 0.0037
+    b.add_train(s_stc, netgen.PORT_G, w, [0.05])   # delivered at step 0
+    b.add_train(s_exp, netgen.PORT_G, w, [0.05])
+    o = oracle.Oracle(_net(b, stc=stc))
+    o.write("h", [h_init, 0.0])
+    o.write("z", [z_init, 0.0])
+    o.run(1)
+    r = math.exp(-0.2 / 5.0)
+    g = o.read("g")
+    total = h_init + STC["h0"] * z_init
+    assert abs(g[0] - w * r * total / STC["h0"]) <= 1e-15 * w
+    assert abs(g[1] - w * r) <= 1e-15 * w
+    if h_init == STC["h0"] and z_init == 1.0:
+        assert abs(g[0] - 2.0 * g[1]) <= 1e-15 * w
+
+
+# ------------------------------------------------------------------ synaptic conductance in the cable step
+@pytest.mark.parametrize("g_syn,e_syn", [(0.002, 0.0), (0.02, -80.0), (0.2, 0.0)])
+def test_passive_cv_under_constant_synaptic_conductance(g_syn, e_syn):
+    """A passive isopotential CV with a synaptic conductance held constant
+    (decay time constant so long that the per-step factor is exactly 1):
+    the ohmic current g (V - E) of Sec. 2.4 enters the backward-Euler step
+    of Eq. 4 implicitly, so V_n relaxes geometrically toward
+    V_inf = (g_pas E_pas + g E) / (g_pas + g) with ratio 1 / (1 + dt/tau_eff),
+    tau_eff = C / (g_pas + g).  An explicit (unlinearised) synaptic term, a
+    wrong sign or a wrong reversal potential breaks the closed form."""
+    cm, gpas_dens, epas, v0, dt = 1.0, 1e-4, -65.0, -70.0, 0.1
+    L, d = 30.0, 7.0
+    b = netgen._Builder()
+    b.add_cell([-1], [L], [d], [netgen.MECH_PAS], params=_cell_params(v_init=v0, g_pas=gpas_dens, e_pas=epas))
+    s = b.add_syn(0, 0, netgen.KIND_EXPSYN, 1e300, e_syn)
+    b.add_train(s, netgen.PORT_G, g_syn, [0.0])
+    o = oracle.Oracle(_net(b, dt=dt))
+    area = math.pi * d * L                      # um^2
+    C = 1e-5 * cm * area                        # nF
+    gpas = 1e-2 * gpas_dens * area              # uS
+    v_inf = (gpas * epas + g_syn * e_syn) / (gpas + g_syn)
+    q = 1.0 / (1.0 + dt * (gpas + g_syn) / C)
+    vs = []
+    for _ in range(120):
+        o.run(1)
+        vs.append(o.read("V")[0])
+    n = np.arange(1, 121)
+    expect = v_inf + (v0 - v_inf) * q ** n
+    np.testing.assert_allclose(vs, expect, rtol=1e-12, atol=1e-12)
+    assert o.read("g")[0] == g_syn
+
+
+# ------------------------------------------------------------------ detection and crossing time
+def _passive_clamped(v0, epas, theta, amp, t0=0.0, dur=1e9, dt=0.2, L=20.0, d=20.0):
+    b = netgen._Builder()
+    b.add_cell([-1], [L], [d], [netgen.MECH_PAS], params=_cell_params(v_init=v0, e_pas=epas))
+    if amp != 0.0:
+        b.add_clamp(0, 0, t0, dur, amp)
+    net = b.finish("pin", dt, 100.0, 11, STC, theta=theta)
+    return oracle.Oracle(net)
+
+
+def test_detector_crossing_step_and_time_on_closed_form_trajectory():
+    """A passive CV charged by a steady clamp current I0 follows
+    V_n = V_inf + (V_0 - V_inf) / (1 + dt/tau)^n, V_inf = E + I0 / g_pas
+    (backward Euler, Eq. 4).  The detector fires in the one step with
+    V_n < theta <= V_{n+1}, at the linear interpolation
+    t* = t_n + dt (theta - V_n) / (V_{n+1} - V_n) (reading R19), and never
+    again while V stays above theta."""
+    dt, L, d, cm, gpas_dens, epas, v0, I0, theta = 0.2, 20.0, 20.0, 1.0, 1e-4, -65.0, -65.0, 0.05, -30.0
+    o = _passive_clamped(v0, epas, theta, I0, dt=dt, L=L, d=d)
+    area = math.pi * d * L
+    C, gpas = 1e-5 * cm * area, 1e-2 * gpas_dens * area
+    v_inf = epas + I0 / gpas
+    q = 1.0 / (1.0 + dt * gpas / C)
+    n = np.arange(0, 400)
+    v = v_inf + (v0 - v_inf) * q ** n
+    k = int(np.nonzero((v[:-1] < theta) & (v[1:] >= theta))[0][0])
+    o.run(399)
+    gid, step, ts = o.spikes()
+    assert gid.size == 1 and int(step[0]) == k
+    t_expect = k * dt + dt * (theta - v[k]) / (v[k + 1] - v[k])
+    assert abs(ts[0] - t_expect) <= 1e-12 * t_expect
+    # the continuous crossing time of the same membrane, to first order in dt
+    tau = C / gpas
+    t_cont = tau * math.log((v0 - v_inf) / (theta - v_inf))
+    assert abs(ts[0] - t_cont) < 0.5 * dt + (dt / tau) * t_cont
+
+
+def test_detector_threshold_boundaries():
+    """The crossing condition is V_n < theta <= V_{n+1}: a voltage that
+    starts exactly at theta and rises is not a crossing, and a step that
+    lands exactly on theta is one (at t* = t_{n+1})."""
+    # starts at theta = 0 and rises toward E = +10 mV: no spike
+    o = _passive_clamped(0.0, 10.0, 0.0, 0.0)
+    o.run(200)
+    assert o.read("V")[0] > 5.0 and o.spikes()[0].size == 0
+    # from -10 mV, one clamp step whose charge lands V exactly on theta = 0:
+    # b = (C/dt) V_0 + g_pas E_pas + I0 = 0 with E_pas = 0 and I0 = 10 C/dt
+    dt, L, d = 0.2, 20.0, 20.0
+    cdt = (1e-5 * 1.0 * (math.pi * d * L)) / dt
+    o = _passive_clamped(-10.0, 0.0, 0.0, 10.0 * cdt, t0=0.0, dur=0.5 * dt, dt=dt, L=L, d=d)
+    o.run(1)
+    assert o.read("V")[0] == 0.0
+    o.run(50)
+    gid, step, ts = o.spikes()
+    assert gid.size == 1 and int(step[0]) == 0 and ts[0] == dt
+
+
+# ------------------------------------------------------------------ HH rates away from rest, resting root
+def _hh1952(v):
+    """Rate constants (1/ms) in the notation of Hodgkin and Huxley (1952):
+    V is the displacement from rest with depolarisation negative, so
+    V = -(v - E_rest) for a membrane potential v resting at -65 mV."""
+    V = -(v + 65.0)
+    am = 0.1 * (V + 25.0) / (math.exp((V + 25.0) / 10.0) - 1.0)
+    bm = 4.0 * math.exp(V / 18.0)
+    ah = 0.07 * math.exp(V / 20.0)
+    bh = 1.0 / (math.exp((V + 30.0) / 10.0) + 1.0)
+    an = 0.01 * (V + 10.0) / (math.exp((V + 10.0) / 10.0) - 1.0)
+    bn = 0.125 * math.exp(V / 80.0)
+    return np.array([am, bm, ah, bh, an, bn])
+
+
+def test_hh_rates_match_the_1952_formulation_across_voltages():
+    """The oracle's rates (written in the modern sign convention with
+    exprelr) equal the original paper's expressions over the whole
+    physiological range, not only at rest where several exponentials are 1."""
+    vs = [v for v in np.linspace(-110.0, 50.0, 97) if min(abs(v + 40.0), abs(v + 55.0)) > 0.5]
+    for v in vs:
+        np.testing.assert_allclose(oracle.hh_rates(v), _hh1952(v), rtol=2e-13, atol=0)
+
+
+def test_hh_soma_rests_at_the_root_of_the_steady_state_current():
+    """A lone HH CV settles where the membrane current with gates at their
+    steady states vanishes (the resting potential of the model, about
+    -64.974 mV with these parameters, reading R6).  The discrete step's
+    fixed point is that root exactly, so the long-run voltage agrees to
+    1e-6 mV with a root found here from the 1952 rate expressions."""
+    from scipy.optimize import brentq
+    P = netgen.DEFAULT_CELL
+    gna, gk, gl, ena, ek, el = P[5], P[6], P[7], P[8], P[9], P[10]
+
+    def i_ss(v):
+        am, bm, ah, bh, an, bn = _hh1952(v)
+        m, h, n = am / (am + bm), ah / (ah + bh), an / (an + bn)
+        return gna * m ** 3 * h * (v - ena) + gk * n ** 4 * (v - ek) + gl * (v - el)
+
+    root = brentq(i_ss, -70.0, -60.0, xtol=1e-13)
+    assert abs(root - (-64.974)) < 5e-4
+    b = netgen._Builder()
+    b.add_cell([-1], [20.0], [20.0], [netgen.MECH_HH])
+    o = oracle.Oracle(_net(b, dt=0.2))
+    o.run(20000)  # 4 s
+    assert abs(o.read("V")[0] - root) < 1e-6
