@@ -1,19 +1,21 @@
 """Throughput of the per-step update of a plastic network of multi-compartment
 neurons on one MI355X.
 
-Workload: 2000 ball-and-stick cells (HH soma + 20 passive dendrite CVs,
-42,000 CVs), 1600 excitatory / 400 inhibitory, Bernoulli(0.1) connectivity
-with 3 ms delays, ~255k plastic (calcium + tagging-and-capture) E->E
-synapses and ~146k static ones, 25 x 5 Hz Poisson inputs per cell, dt = 0.2 ms,
-seeded synthetic data (no dataset).  A bench "step" is one time step of the
-whole network (delivery, currents, cable solve, mechanisms, plasticity,
-detection, and its share of the spike exchange).
+Workload (default): 2000 ball-and-stick cells with 100-CV dendrites (HH soma
++ 100 passive dendrite CVs, 202,000 CVs), 1600 excitatory / 400 inhibitory,
+Bernoulli(0.1) connectivity with 3 ms delays, ~255k plastic (calcium +
+tagging-and-capture) E->E synapses and ~146k static ones, 25 x 5 Hz Poisson
+inputs per cell, dt = 0.2 ms, seeded synthetic data (no dataset), in the
+batched form with mixed precision.  A bench "step" is one time step of the
+whole network (event gathering and delivery, currents, cable solve,
+mechanisms, plasticity, detection).  Before the warmup the network runs
+--settle steps (untimed) from rest into its firing regime.
 
-    python bench.py [--steps 50000] [--warmup 500] [--form batched-mixed]
+    python bench.py [--steps 5000] [--warmup 500] [--form batched-mixed]
 
 Prints one JSON line.  value = CV-steps/s of the headline form over the
-timed steps; the plain FP64 form runs the same steps for the comparison at
-equal spikes.
+timed steps; the plain FP64 form and the batched FP64 form run the same
+steps for the comparison at equal spikes.
 """
 from __future__ import annotations
 
@@ -56,7 +58,7 @@ def _alg_bytes_per_launch(form: str, s: dict, steps_per_launch: float) -> float:
     return per_step * steps_per_launch
 
 
-def run_form(net, form, steps, warmup, time_kernel=True, plan=None):
+def run_form(net, form, steps, warmup, settle=0, time_kernel=True, plan=None):
     import torch
 
     from paper_2411_16445_amd import Simulation
@@ -65,6 +67,8 @@ def run_form(net, form, steps, warmup, time_kernel=True, plan=None):
                      **(plan if mode == "batched" and plan else {}))
     st = sim.stats()
     st["n_hh"] = sim.n_hh
+    if settle:
+        sim.advance_steps(settle)
     sim.advance_steps(warmup)
     sp0 = sim.stats()["spikes"]
     if time_kernel:
@@ -83,14 +87,19 @@ def run_form(net, form, steps, warmup, time_kernel=True, plan=None):
                block_threads=st2["block_threads"], solver_waves=st2["solver_waves"],
                exchange={1: "kernel", 2: "resident"}.get(st2["exchange"], "-"))
     if time_kernel:
+        # launches of the dominant kernel may cover unequal step counts (a
+        # resident launch runs up to 256 epochs): the achieved rate is the
+        # algorithmic bytes of all timed steps over the summed launch times
         ms, launches, name = sim.kernel_time()
         avg_ms = ms / max(1, launches)
         spl = steps / max(1, launches)
         alg = _alg_bytes_per_launch(form, st, spl)
-        achieved = alg / (avg_ms * 1e-3) / 1e9
+        alg_step = _alg_bytes_per_launch(form, st, 1.0)
+        achieved = alg_step * steps / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         out["kernel"] = dict(name=name, launches=launches, avg_us=avg_ms * 1e3,
-                             alg_bytes_per_launch=alg, achieved_gbs=achieved,
-                             share_of_time=ms / (el * 1e3))
+                             us_per_step=ms * 1e3 / steps, steps_per_launch=spl,
+                             alg_bytes_per_launch=alg, alg_bytes_per_step=alg_step,
+                             achieved_gbs=achieved, share_of_time=ms / (el * 1e3))
     out["stats"] = st
     sim.close()
     return out
@@ -102,9 +111,10 @@ def cpu_baseline(net, n_steps):
     t0 = time.perf_counter()
     o.run(n_steps)
     el = time.perf_counter() - t0
+    spikes = int(o.spikes()[0].size)
     return dict(value=o.n_cv * n_steps / el, unit="CV-steps/s", cores=1, kind="oracle",
-                sample=f"first {n_steps} steps ({n_steps * net['dt']:.0f} ms) of the same network, "
-                       f"single-threaded plain FP64 C oracle, {el:.1f} s")
+                sample=f"first {n_steps} steps ({n_steps * net['dt']:.0f} ms, {spikes} spikes) of the same "
+                       f"network with its inputs, single-threaded plain FP64 C oracle, {el:.1f} s")
 
 
 # workloads: name in the JSON line, network builder
@@ -115,18 +125,20 @@ WORKLOADS = {"ei2000x21": ("ei-ball-and-stick-2000x21cv", "config2"),
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50000)
+    ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--settle", type=int, default=1000,
+                    help="untimed steps from rest into the firing regime before the warmup")
     ap.add_argument("--form", default=os.environ.get("PA_BENCH_FORM", "batched-mixed"),
                     choices=["plain-fp64", "plain-mixed", "batched-fp64", "batched-mixed"])
-    ap.add_argument("--no-compare", action="store_true", help="skip the plain FP64 reference run")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain and batched FP64 runs")
     ap.add_argument("--cpu-steps", type=int, default=1500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plan", default="",
                     help="fix the batched form's plan instead of autotuning it: "
                          "CELLS_PER_BLOCK,BLOCK_THREADS,SOLVER_WAVES,EXCHANGE (kernel|resident)")
-    ap.add_argument("--workload", default="ei2000x21", choices=sorted(WORKLOADS),
-                    help="ei2000x21: the headline network; ei2000x101: the same network with 100-CV dendrites")
+    ap.add_argument("--workload", default="ei2000x101", choices=sorted(WORKLOADS),
+                    help="ei2000x101: the headline network (100-CV dendrites); ei2000x21: 20-CV dendrites")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the runs, copy this many MiB device to device (a plain copy kernel of known "
                          "size that scales rocprofv3's FETCH_SIZE / WRITE_SIZE)")
@@ -136,7 +148,9 @@ def main():
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
     import netgen
-    t_end = (args.warmup + args.steps + 10) * 0.2
+    # inputs over everything that runs: settle, warmup, timed steps and the
+    # oracle's sample
+    t_end = (max(args.settle + args.warmup + args.steps, args.cpu_steps) + 100) * 0.2
     wname, make = WORKLOADS[args.workload]
     net = getattr(netgen, make)(t_end=t_end)
     print(f"[bench] network {netgen.summary(net)}", file=sys.stderr, flush=True)
@@ -144,13 +158,17 @@ def main():
     if args.plan:
         cpb, bt, sw, xm = args.plan.split(",")
         plan = dict(cells_per_block=int(cpb), block_threads=int(bt), solver_waves=int(sw), exchange=xm)
-    head = run_form(net, args.form, args.steps, args.warmup, plan=plan)
+    head = run_form(net, args.form, args.steps, args.warmup, args.settle, plan=plan)
     print(f"[bench] {args.form}: {head['ms_per_step']*1e3:.2f} us/step, {head['spikes']} spikes",
           file=sys.stderr, flush=True)
-    ref = None
+    ref = bfp = None
     if not args.no_compare and args.form != "plain-fp64":
-        ref = run_form(net, "plain-fp64", args.steps, args.warmup)
+        ref = run_form(net, "plain-fp64", args.steps, args.warmup, args.settle)
         print(f"[bench] plain-fp64: {ref['ms_per_step']*1e3:.2f} us/step, {ref['spikes']} spikes",
+              file=sys.stderr, flush=True)
+    if not args.no_compare and args.form == "batched-mixed":
+        bfp = run_form(net, "batched-fp64", args.steps, args.warmup, args.settle)
+        print(f"[bench] batched-fp64: {bfp['ms_per_step']*1e3:.2f} us/step, {bfp['spikes']} spikes",
               file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
@@ -166,7 +184,6 @@ def main():
     k = head.get("kernel", {})
     from paper_2411_16445_amd.profiling import traffic_for_bench
     traffic, traffic_src = traffic_for_bench(os.path.join(ROOT, "profiles"), k.get("name") or "", args.workload)
-    steps_per_launch = args.steps / max(1, k.get("launches") or 1)
     line = {
         "metric": "CV-steps/s + synapse-updates/s, mixed+batched vs plain FP64 at equal spikes",
         "value": head["cv_steps_per_s"],
@@ -179,23 +196,26 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32" if args.form.endswith("mixed") else "f64",
-        "data": "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network)",
+        "data": "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network; "
+                f"{args.settle} untimed settling steps from rest)",
         "config": {"workload": wname, "cells": head["stats"]["n_cells"],
                    "cvs": head["stats"]["n_cv"], "synapses": head["stats"]["n_syn"],
                    "stc_synapses": head["stats"]["n_stc"], "dt_ms": 0.2, "form": args.form,
                    "epoch_steps": head["epoch_steps"], "cells_per_block": head["cells_per_block"],
                    "block_threads": head["block_threads"], "solver_waves": head["solver_waves"],
-                   "exchange": head["exchange"], "parallelism": "single-gpu"},
+                   "exchange": head["exchange"], "settle_steps": args.settle, "parallelism": "single-gpu"},
         "synapse_updates_per_s": head["synapse_updates_per_s"],
         "stc_synapse_updates_per_s": head["stc_synapse_updates_per_s"],
         "spikes": head["spikes"],
         "roofline": {
             "bound": "hbm", "achieved": k.get("achieved_gbs"), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": (k.get("achieved_gbs") or 0) / HBM_PEAK_GBS,
-            "traffic": None if traffic is None else traffic * steps_per_launch,
+            "traffic": None if traffic is None else traffic * (k.get("steps_per_launch") or 1),
             "traffic_source": traffic_src,
             "kernel": k.get("name"), "avg_us": k.get("avg_us"), "launches": k.get("launches"),
+            "us_per_step": k.get("us_per_step"), "steps_per_launch": k.get("steps_per_launch"),
             "alg_bytes_per_launch": k.get("alg_bytes_per_launch"),
+            "alg_bytes_per_step": k.get("alg_bytes_per_step"),
             "kernel_share_of_step_time": k.get("share_of_time"),
         },
         "cpu_baseline": cpu,
@@ -206,7 +226,10 @@ def main():
         line["speedup_vs_plain_fp64"] = ref["seconds"] / head["seconds"]
         if head["spikes"] and ref["spikes"]:
             line["speedup_per_spike"] = (ref["seconds"] / ref["spikes"]) / (head["seconds"] / head["spikes"])
-        line["equal_spikes"] = head["spikes"] == ref["spikes"]
+            line["equal_spikes"] = head["spikes"] == ref["spikes"]
+    if bfp is not None:
+        line["batched_fp64"] = {"cv_steps_per_s": bfp["cv_steps_per_s"], "ms_per_step": bfp["ms_per_step"],
+                                "spikes": bfp["spikes"]}
     print(json.dumps(line), flush=True)
 
 

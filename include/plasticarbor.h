@@ -21,11 +21,18 @@
  *
  * Units everywhere: ms, mV, um, nA, uS (conductance), nF, umol/l.
  *
+ * Section numbers refer to the paper: Sec. 2.1 (post-synaptic spike hook),
+ * 2.2 (one connection addressing a synapse through two streams), 2.3
+ * (stochastic differential equations), 2.4 (cable equation, Eq. 4, and
+ * ohmic membrane currents), 3.5 (synaptic tagging and capture, Eqs. 16-21,
+ * Table 5), 3.6-3.8 (networks, benchmarks).
+ *
  * Conventions
  *   - Every call returns a pa_status; no C++ exception crosses the ABI.
  *     On failure pa_last_error(sim) holds a message.
  *   - Input arrays are read during the call and copied; the caller keeps
- *     ownership.  Output arrays are caller-owned host buffers.
+ *     ownership.  Output arrays are caller-owned host buffers, except for
+ *     pa_state_read_device, which writes a caller-owned device buffer.
  *   - The library owns all device memory; it allocates it at pa_finalize
  *     through the allocator set with pa_set_allocator (default hipMalloc).
  *   - State machine: BUILD --pa_finalize--> READY.  Adding cells, synapses,
@@ -55,7 +62,8 @@ typedef int32_t pa_status;
 #define PA_ENOMEM (-3)     /* allocation failed */
 #define PA_EDEVICE (-4)    /* HIP runtime error */
 #define PA_ERANGE (-5)     /* time off the dt grid, backwards, or an event in the past */
-#define PA_EOVERFLOW (-6)  /* an event slot overflowed: raise slot_capacity */
+#define PA_EOVERFLOW (-6)  /* Poisson arrivals beyond their epoch queue, or the spike
+                              history of one advance overflowed */
 #define PA_ENUMERIC (-7)   /* a membrane voltage became non-finite */
 
 /* precision of the run */
@@ -82,8 +90,7 @@ typedef struct {
     uint64_t seed;           /* key of the early-phase noise */
     int32_t precision;       /* PA_FP64 or PA_MIXED */
     int32_t mode;            /* PA_PLAIN or PA_BATCHED */
-    uint32_t probe_stride;   /* steps between probe samples, >= 1 */
-    uint32_t slot_capacity;  /* events per (cell, step) slot; 0 = automatic */
+    uint32_t flags;          /* reserved, 0 */
     uint32_t cells_per_block;/* batched form: cells per workgroup; 0 = autotune */
     uint16_t block_threads;  /* batched form: 64, 128 or 256 lanes per workgroup;
                                 0 = autotune */
@@ -94,13 +101,13 @@ typedef struct {
                                 PA_EXCHANGE_RESIDENT */
 } pa_config;
 
-/* Batched form, spike exchange between epochs.  KERNEL: one launch per epoch
- * of the fused step kernel, then a separate exchange kernel (state staged
- * in and out of LDS every epoch).  RESIDENT: many epochs per cooperative
- * launch with every workgroup resident; the state stays in LDS and the
- * workgroups exchange spikes themselves behind a grid barrier (needs all
- * workgroups to fit on the device at once).  AUTO: the faster of the two in
- * trial epochs where RESIDENT fits. */
+/* Batched form, spike exchange between epochs.  KERNEL: one launch of the
+ * fused step kernel per epoch (state staged in and out of LDS every epoch;
+ * spikes reach the other cells at the launch boundary).  RESIDENT: many
+ * epochs per cooperative launch with every workgroup resident; the state
+ * stays in LDS and the workgroups wait for each other behind a grid
+ * barrier between epochs (needs all workgroups to fit on the device at
+ * once).  AUTO: the faster of the two in trial epochs where RESIDENT fits. */
 #define PA_EXCHANGE_AUTO 0
 #define PA_EXCHANGE_KERNEL 1
 #define PA_EXCHANGE_RESIDENT 2
@@ -133,8 +140,8 @@ typedef struct {
     uint64_t n_cells, n_cv, n_syn, n_stc, n_conn, n_trains, n_probes, n_poisson;
     uint64_t steps, spikes, events;
     uint32_t epoch_steps;    /* K: steps between spike exchanges */
-    uint32_t ring_slots;     /* R: per-cell event slots */
-    uint32_t slot_capacity;  /* Q */
+    uint32_t spike_ring;     /* spikes each cell keeps for its targets */
+    uint64_t queue_events;   /* room of the per-epoch event queues, all cells */
     uint32_t cells_per_block;
     double advance_ms;       /* wall time inside pa_advance* so far */
     uint64_t device_bytes;   /* device memory held */
@@ -143,9 +150,11 @@ typedef struct {
     uint32_t exchange;       /* batched form: PA_EXCHANGE_KERNEL or PA_EXCHANGE_RESIDENT chosen */
 } pa_stats;
 
-/* Creates a simulation in the BUILD state.  cfg and stc are copied.
+/* Creates a simulation in the BUILD state: a network advanced by the
+ * implicit step of the cable equation (Eq. 4, Sec. 2.4) with fixed dt,
+ * plasticity constants of Table 5 (Sec. 3.5).  cfg and stc are copied.
  * Errors: PA_EINVAL (NULL pointer, dt <= 0, unknown precision/mode,
- * probe_stride 0, non-finite or non-positive time constants). */
+ * flags != 0, non-finite or non-positive time constants). */
 pa_status pa_sim_create(const pa_config *cfg, const pa_stc_params *stc, pa_sim **out);
 
 /* Releases everything; NULL-safe. */
@@ -162,7 +171,9 @@ pa_status pa_set_stream(pa_sim *sim, void *hip_stream);
 pa_status pa_set_allocator(pa_sim *sim, void *(*alloc)(size_t bytes, void *ctx),
                            void (*release)(void *ptr, void *ctx), void *ctx);
 
-/* Adds n cells; cell k owns CVs cv_off[k] .. cv_off[k+1]-1 of the arrays
+/* Adds n cells (Sec. 2.4: cable equation Eq. 4 on a tree of cylindrical
+ * control volumes; Sec. 3.8: Hodgkin-Huxley soma, passive dendrites).
+ * Cell k owns CVs cv_off[k] .. cv_off[k+1]-1 of the arrays
  * (cv_off[0] = 0).  parent holds local CV indices: parent[first] = -1 and
  * 0 <= parent[i] < i (the ordering the Hines elimination relies on).
  * Each CV is a cylinder of the given length and diameter (um) carrying
@@ -174,14 +185,18 @@ pa_status pa_cells_add(pa_sim *sim, uint32_t n, const int64_t *cv_off, const int
                        const int32_t *detector_cv, const pa_cell_params *params,
                        uint32_t *first_gid);
 
-/* Adds n synapses: synapse k sits on local CV cv[k] of cell gid[k], kind
+/* Adds n synapses (conductance-based exponential synapses, Sec. 3.8; with
+ * PA_SYN_STC the calcium-based early phase and tagging-and-capture late
+ * phase of Eqs. 16-21, Sec. 3.5): synapse k sits on local CV cv[k] of cell gid[k], kind
  * PA_SYN_EXP or PA_SYN_STC, decay time constant tau_ms[k] > 0, reversal
  * erev_mV[k].  Synapse ids are dense in call order.  Errors: PA_EINVAL. */
 pa_status pa_synapses_add(pa_sim *sim, uint32_t n, const uint32_t *gid, const uint32_t *cv,
                           const uint8_t *kind, const double *tau_ms, const double *erev_mV,
                           uint32_t *first_sid);
 
-/* Adds n connections: a spike of cell src_gid[k] at t* reaches synapse
+/* Adds n connections (delayed spike delivery; the calcium port is the
+ * second stream of one connection into the same synapse, Sec. 2.2, delayed
+ * by t_c,delay, Eq. 19): a spike of cell src_gid[k] at t* reaches synapse
  * dst_sid[k] through the ports in ports[k] (PA_PORT_G and/or PA_PORT_CA;
  * the calcium port needs a PA_SYN_STC target) at t* + delay_ms[k] (plus
  * t_cd for the calcium port), with weight weight_uS[k] on the conductance
@@ -190,7 +205,9 @@ pa_status pa_synapses_add(pa_sim *sim, uint32_t n, const uint32_t *gid, const ui
 pa_status pa_connect(pa_sim *sim, uint64_t n, const uint32_t *src_gid, const uint32_t *dst_sid,
                      const uint8_t *ports, const double *weight_uS, const double *delay_ms);
 
-/* Adds n explicit presynaptic spike trains: train k delivers arrivals at
+/* Adds n explicit presynaptic spike trains (external input, e.g. the
+ * Poisson stimulation of Sec. 3.1 and 3.5 given as arrival times): train k
+ * delivers arrivals at
  * times_ms[time_off[k] .. time_off[k+1]-1] (non-decreasing, >= 0) to
  * synapse dst_sid[k] through ports[k] with weight weight_uS[k]; the
  * calcium port adds t_cd.  Trains act as sources with ids n_cells + k.
@@ -198,7 +215,9 @@ pa_status pa_connect(pa_sim *sim, uint64_t n, const uint32_t *src_gid, const uin
 pa_status pa_trains_add(pa_sim *sim, uint32_t n, const uint32_t *dst_sid, const uint8_t *ports,
                         const double *weight_uS, const int64_t *time_off, const double *times_ms);
 
-/* Adds n Poisson sources: source k delivers arrivals of a homogeneous
+/* Adds n Poisson sources (external Poisson input, Sec. 3.1 and 3.5, drawn
+ * on the device from the counter-based generator of Sec. 2.3): source k
+ * delivers arrivals of a homogeneous
  * Poisson process of rate_hz[k] to synapse dst_sid[k] through ports[k] with
  * weight weight_uS[k] (the calcium port adds t_cd).  Arrival j of source k
  * follows the previous one (or t = 0) after -ln(u) / rate, u the first
@@ -209,8 +228,9 @@ pa_status pa_trains_add(pa_sim *sim, uint32_t n, const uint32_t *dst_sid, const 
 pa_status pa_poisson_add(pa_sim *sim, uint32_t n, const uint32_t *dst_sid, const uint8_t *ports,
                          const double *weight_uS, const double *rate_hz);
 
-/* Adds n current clamps injecting amp_nA[k] into local CV cv[k] of cell
- * gid[k] during t0 <= t_n < t0 + dur.  Errors: PA_EINVAL. */
+/* Adds n current clamps (the injected current of the cable equation,
+ * Eq. 4) injecting amp_nA[k] into local CV cv[k] of cell gid[k] during
+ * t0 <= t_n < t0 + dur.  Errors: PA_EINVAL. */
 pa_status pa_clamps_add(pa_sim *sim, uint32_t n, const uint32_t *gid, const uint32_t *cv,
                         const double *t0_ms, const double *dur_ms, const double *amp_nA);
 
@@ -221,22 +241,29 @@ pa_status pa_clamps_add(pa_sim *sim, uint32_t n, const uint32_t *gid, const uint
 #define PA_PROBE_Z 4   /* index: synapse id (PA_SYN_STC) */
 #define PA_PROBE_P 5   /* index: cell id */
 
-/* Adds n probes, sampled after every probe_stride-th completed step.
- * Errors: PA_EINVAL. */
+/* Adds n probes (the recorded traces of the paper's figures): probe k
+ * samples quantity what[k] of element index[k] after every
+ * stride_steps[k]-th completed step (stride >= 1).  Probe ids are dense in
+ * call order; the first is written to *first_probe.  Errors: PA_EINVAL. */
 pa_status pa_probes_add(pa_sim *sim, uint32_t n, const int32_t *what, const uint64_t *index,
-                        uint32_t *first_probe);
+                        const uint32_t *stride_steps, uint32_t *first_probe);
 
 /* Validates, orders synapses by (cell, CV, id), builds the cable
- * invariants, the connection table by source and the event rings,
- * allocates and uploads device memory, and initialises the state
- * (V = v_init, gates at steady state, g = c = z = p = 0, h = h0).
- * Errors: PA_EINVAL, PA_ESTATE, PA_ENOMEM, PA_EDEVICE. */
+ * invariants (Eq. 4), the table of incoming connections by target cell,
+ * the spike rings and the per-epoch event queues, allocates and uploads
+ * device memory, initialises the state (V = v_init, gates at steady state,
+ * g = c = z = p = 0, h = h0) and, in the batched form, picks and captures
+ * the launch plan.  Errors: PA_EINVAL, PA_ESTATE, PA_ENOMEM, PA_EDEVICE. */
 pa_status pa_finalize(pa_sim *sim);
 
 /* Advances to t_until_ms, which must lie on the dt grid (within 1e-9
- * relative) and not before the present time.  Errors: PA_ESTATE,
- * PA_ERANGE, PA_EOVERFLOW, PA_ENUMERIC, PA_EDEVICE; after any of the last
- * three the simulation refuses further advances. */
+ * relative) and not before the present time: per step, event delivery and
+ * the post-synaptic hook (Sec. 2.1, Eq. 16, Eq. 19), membrane currents
+ * (Sec. 2.4), the implicit cable step (Eq. 4), HH gates and synaptic decay
+ * (Sec. 3.8), plasticity (Eqs. 17-21 with the noise of Sec. 2.3) and
+ * threshold detection (Sec. 2.1).  Errors: PA_ESTATE, PA_ERANGE,
+ * PA_EOVERFLOW, PA_ENUMERIC, PA_EDEVICE; after any of the last three the
+ * simulation refuses further advances. */
 pa_status pa_advance(pa_sim *sim, double t_until_ms);
 
 /* Advances by n_steps steps.  Errors as pa_advance. */
@@ -245,16 +272,18 @@ pa_status pa_advance_steps(pa_sim *sim, uint64_t n_steps);
 /* Number of spikes recorded so far. */
 pa_status pa_spikes_count(const pa_sim *sim, uint64_t *n);
 
-/* Copies up to cap spikes (gid, step of the crossing, interpolated time)
- * in (step, gid) order; *n receives the number copied. */
+/* Copies up to cap spikes (gid, step of the crossing, interpolated time;
+ * the threshold detector of Sec. 2.1) in (time, gid) order; *n receives
+ * the number copied.  Any of the three arrays may be NULL. */
 pa_status pa_spikes_read(const pa_sim *sim, uint32_t *gid, uint64_t *step, double *t_ms,
                          uint64_t cap, uint64_t *n);
 
-/* Number of probe samples (rows) recorded so far. */
-pa_status pa_probe_count(const pa_sim *sim, uint64_t *n_samples);
+/* Number of samples probe_id has recorded so far.  Errors: PA_EINVAL. */
+pa_status pa_probe_count(const pa_sim *sim, uint32_t probe_id, uint64_t *n_samples);
 
-/* Copies up to cap doubles of the samples, row-major (sample, probe). */
-pa_status pa_probe_read(const pa_sim *sim, double *out, uint64_t cap, uint64_t *n);
+/* Copies up to cap samples of probe probe_id, oldest first.  Errors:
+ * PA_EINVAL. */
+pa_status pa_probe_read(const pa_sim *sim, uint32_t probe_id, double *out, uint64_t cap, uint64_t *n);
 
 #define PA_STATE_V 0        /* n_cv doubles, CV order of pa_cells_add */
 #define PA_STATE_M 1        /* one double per HH CV, in CV order */
@@ -271,6 +300,14 @@ pa_status pa_probe_read(const pa_sim *sim, double *out, uint64_t cap, uint64_t *
 /* Copies a state array to a host buffer of n elements (count must match).
  * FP32 state of the mixed form is widened.  READY state only. */
 pa_status pa_state_read(pa_sim *sim, int32_t what, void *out, uint64_t n);
+
+/* The same into a caller-owned device buffer `dev_out` (e.g. a framework
+ * tensor's storage) of n elements: doubles for codes 0-8 (FP32 state of
+ * the mixed form widened), uint64 pairs for 9-10, in the same order as
+ * pa_state_read.  Enqueued on the simulation's stream; the call returns
+ * after the copy has completed.  Errors: PA_EINVAL, PA_ESTATE, PA_ENOMEM
+ * (element counts above 2^32), PA_EDEVICE. */
+pa_status pa_state_read_device(pa_sim *sim, int32_t what, void *dev_out, uint64_t n);
 
 /* Overwrites a state array (codes 0-8) from a host buffer; for setting up
  * test states.  READY state only. */

@@ -311,8 +311,14 @@ def config1(seed=1, t_end=10000.0, w_syn=0.05, rate_hz=20.0, sigma_on=True):
 
 def _ei_network(name, n_dend, seed, t_end, n_e=1600, n_i=400, p=0.1, delay=3.0,
                 w_ee=0.0003, w_ei=0.0005, w_ie=0.02, w_ii=0.01, w_ext=0.0005,
-                n_ext=25, ext_rate=5.0, explicit_trains=True, max_train_t=None):
-    rng_m, rng_c, rng_p, rng_t = _streams(seed, 4)
+                n_ext=25, ext_rate=5.0, explicit_trains=True, max_train_t=None,
+                stim_n=0, stim_rate=0.0, stim_t0=0.0, stim_dur=0.0, stim_amp=0.0):
+    """E/I network of ball-and-stick cells.  A learning stimulus (the shape
+    of the assembly-forming protocol of Sec. 3.5): the first stim_n
+    excitatory cells receive, on their external synapse, an extra Poisson
+    train of stim_rate Hz during [stim_t0, stim_t0 + stim_dur), and a
+    somatic current step of stim_amp nA over the same interval."""
+    rng_m, rng_c, rng_p, rng_t, rng_s = _streams(seed, 5)
     n = n_e + n_i
     b = _Builder()
     morph = ball_and_stick(n_dend, 200.0, 1.0, 20.0)
@@ -345,7 +351,14 @@ def _ei_network(name, n_dend, seed, t_end, n_e=1600, n_i=400, p=0.1, delay=3.0,
     if explicit_trains:
         t_tr = t_end if max_train_t is None else min(t_end, max_train_t)
         for c in range(n):
-            b.add_train(ext_syn[c], PORT_G, w_ext, _merge_trains(rng_t, n_ext, ext_rate, t_tr))
+            times = _merge_trains(rng_t, n_ext, ext_rate, t_tr)
+            if c < stim_n:
+                extra = stim_t0 + poisson_times(rng_s, stim_rate, min(stim_dur, t_tr - stim_t0))
+                times = np.concatenate([times, extra])
+            b.add_train(ext_syn[c], PORT_G, w_ext, times)
+    if stim_amp:
+        for c in range(stim_n):
+            b.add_clamp(c, 0, stim_t0, stim_dur, stim_amp)
     stc = dict(STC_TABLE5)
     stc.update(CA_INVIVO)
     net = b.finish(name, 0.2, t_end, seed, stc)
@@ -484,6 +497,39 @@ def tiny(seed=7, n_cells=13, t_end=200.0, n_min=2, n_max=24, p=0.35, n_static=3,
     stc = dict(STC_TABLE5)
     stc.update(CA_INVIVO)
     return b.finish("tiny", dt, t_end, seed, stc)
+
+
+def burst_network(seed=11, n_cells=160, t_end=60.0, n_dend=5, w=0.0004, delay=3.0):
+    """All-to-all network whose cells all fire in one step: identical ball-
+    and-stick cells, every ordered pair connected through both ports onto a
+    plastic synapse of its own on a random dendrite CV, plus a second
+    connection from the next cell onto the same synapse (two streams from one
+    source into one synapse, equal delivery times); one suprathreshold clamp
+    pulse on every soma at 2 ms.  Each cell then receives n_cells - 1 + 1
+    conductance events with equal delivery times from different sources in a
+    single step, and as many calcium events t_c,delay later."""
+    rng_p, = _streams(seed, 1)
+    b = _Builder()
+    morph = ball_and_stick(n_dend, 100.0, 1.0, 20.0)
+    for _ in range(n_cells):
+        b.add_cell(*morph)
+    src, dst = [], []
+    for tgt in range(n_cells):
+        for s_ in range(n_cells):
+            if s_ == tgt:
+                continue
+            sid = b.add_syn(tgt, int(rng_p.integers(1, n_dend + 1)), KIND_STC, 5.0, 0.0)
+            src.append(s_)
+            dst.append(sid)
+            if s_ == (tgt + 1) % n_cells:
+                src.append(s_)
+                dst.append(sid)
+    b.add_conns(src, dst, PORT_G | PORT_CA, w, delay)
+    for c in range(n_cells):
+        b.add_clamp(c, 0, 2.0, 1.0, 2.0)
+    stc = dict(STC_TABLE5)
+    stc.update(CA_INVIVO)
+    return b.finish("burst", 0.2, t_end, seed, stc)
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

@@ -20,20 +20,25 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# the same source with OpenMP over the independent per-CV, per-cell and
+# per-synapse loops: only for timing the oracle on several host cores
+LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 # -O2 without value-changing optimisations: no contraction into FMA, no
 # fast-math; the library's results are those of the C source read literally.
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-Wall", "-Wextra"]
+          "-Wall", "-Wextra", "-Wno-unknown-pragmas"]
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so next to it; returns the path."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC_PATH, "-lm"])
-        os.replace(tmp, LIB_PATH)
+    """Compile oracle.c into liboracle.so (and the OpenMP timing build
+    liboracle_omp.so) next to it; returns the path of the first."""
+    for path, extra in ((LIB_PATH, []), (LIB_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, SRC_PATH, "-lm"])
+            os.replace(tmp, path)
     return LIB_PATH
 
 
@@ -60,15 +65,15 @@ class _Net(C.Structure):
          ("n_pois", _I64), ("pois_dst", _P), ("pois_ports", _P), ("pois_w", _P), ("pois_rate", _P)]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def _load(threaded: bool = False):
+    path = LIB_OMP_PATH if threaded else LIB_PATH
+    if path not in _libs:
+        if not os.path.exists(path):
             build(force=False)
-        lib = C.CDLL(LIB_PATH)
+        lib = C.CDLL(path)
         lib.orc_create.restype = _P
         lib.orc_create.argtypes = [C.POINTER(_Net), C.c_char_p, C.c_int]
         lib.orc_run.restype = C.c_int
@@ -92,8 +97,8 @@ def _load():
         lib.orc_hh_rates.argtypes = [_D, _P]
         lib.orc_poisson_isi.restype = _D
         lib.orc_poisson_isi.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, _D]
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return _libs[path]
 
 
 _READ = {"V": 0, "m": 1, "hh": 2, "n": 3, "g": 4, "c": 5, "h": 6, "z": 7, "p": 8}
@@ -116,10 +121,11 @@ class OracleError(RuntimeError):
 
 
 class Oracle:
-    """One oracle simulation of a netgen network dictionary."""
+    """One oracle simulation of a netgen network dictionary.  threaded=True
+    uses the OpenMP build (same results; for timing on several cores)."""
 
-    def __init__(self, net: dict):
-        lib = _load()
+    def __init__(self, net: dict, threaded: bool = False):
+        lib = _load(threaded)
         self._keep = {k: np.ascontiguousarray(net.get(k, np.zeros(0, t)), dtype=t) for k, t in _ARRAYS.items()}
         st = net["stc"]
         s = _Net()
@@ -164,13 +170,15 @@ class Oracle:
             raise OracleError(self._lib.orc_error(self._h).decode())
 
     def spikes(self):
-        """(gid, step, t*) arrays in (step, gid) order."""
+        """The raster, (gid, step, t*) arrays in (t*, gid) order."""
         n = self._lib.orc_spike_count(self._h)
         gid = np.zeros(n, np.int64)
         step = np.zeros(n, np.int64)
         t = np.zeros(n, np.float64)
         if n:
             self._lib.orc_spikes(self._h, gid.ctypes.data, step.ctypes.data, t.ctypes.data)
+            o = np.lexsort((gid, t))
+            gid, step, t = gid[o], step[o], t[o]
         return gid, step, t
 
     def _size(self, what):

@@ -35,6 +35,10 @@
  *  inter-arrival times come from a counter-based generator.
  *
  * The event queue is a single binary min-heap; there are no epochs.
+ * Built with -fopenmp (the timing variant only), the loops over CVs, cells
+ * and synapses whose iterations are independent run on several threads;
+ * every value is computed by the same expressions in the same order, so
+ * both builds give the same bits.
  * Functions whose result no test pins against an independent fact are
  * marked "parity unpinned" below.
  */
@@ -438,6 +442,7 @@ static int record_spike(orc *o, int64_t gid, int64_t step, double t) {
  * order, then the clamps active at time tn. */
 static void currents(orc *o, double tn) {
     const orc_net *N = &o->net;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < o->n_cv; i++) {
         double I = 0.0, G = 0.0, v = o->V[i];
         if (o->hh_of[i] >= 0) {
@@ -503,6 +508,7 @@ static int orc_step(orc *o) {
         o->ev_count[2 * s + e.port - 1] += 1;
         o->ev_stepsum[2 * s + e.port - 1] += (uint64_t)n;
     }
+#pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N->n_syn; s++)
         if (N->syn_kind[s] == 1 && o->post[N->syn_cell[s]]) o->c[s] += N->c_post;
     memset(o->post, 0, (size_t)nc);
@@ -512,6 +518,7 @@ static int orc_step(orc *o) {
 
     /* 3. assembly and 4. Hines solve, cell by cell */
     for (int64_t i = 0; i < ncv; i++) o->Vold[i] = o->V[i];
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t cell = 0; cell < nc; cell++) {
         int64_t b0 = N->cv_off[cell], b1 = N->cv_off[cell + 1];
         for (int64_t i = b0; i < b1; i++) {
@@ -534,6 +541,7 @@ static int orc_step(orc *o) {
     }
 
     /* 5. gates at V^{n+1}; synaptic conductance decay */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < ncv; i++) {
         if (o->hh_of[i] < 0) continue;
         int64_t k = o->hh_of[i];
@@ -546,9 +554,11 @@ static int orc_step(orc *o) {
             *x[j] = xinf + (*x[j] - xinf) * exp(-dt * (a + bb));
         }
     }
+#pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N->n_syn; s++) o->g[s] *= o->decay[s];
 
     /* 6. plasticity: S from step-start h; h, z from step-start h, z, p, c */
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t cell = 0; cell < nc; cell++) {
         double S = 0.0;
         for (int64_t i = N->cv_off[cell]; i < N->cv_off[cell + 1]; i++)
@@ -559,6 +569,7 @@ static int orc_step(orc *o) {
         o->S[cell] = S;
     }
     const double ah = dt / N->tau_h, az = dt / N->tau_z;
+#pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N->n_syn; s++) {
         if (N->syn_kind[s] != 1) continue;
         double c = o->c[s], h = o->h[s], z = o->z[s], p = o->p[N->syn_cell[s]];
@@ -576,6 +587,7 @@ static int orc_step(orc *o) {
         o->c[s] = c * o->r_c;
     }
     const double ap = dt / N->tau_p;
+#pragma omp parallel for schedule(static)
     for (int64_t cell = 0; cell < nc; cell++) {
         double trig = (o->S[cell] - N->theta_pro > 0.0) ? 1.0 : 0.0;
         o->p[cell] = o->p[cell] + ap * (-o->p[cell] + N->p_max * trig);

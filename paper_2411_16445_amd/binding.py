@@ -34,15 +34,16 @@ EXPORTS = [
     "pa_sim_create", "pa_sim_destroy", "pa_set_stream", "pa_set_allocator", "pa_cells_add",
     "pa_synapses_add", "pa_connect", "pa_trains_add", "pa_poisson_add", "pa_clamps_add", "pa_probes_add",
     "pa_finalize", "pa_advance", "pa_advance_steps", "pa_spikes_count", "pa_spikes_read",
-    "pa_probe_count", "pa_probe_read", "pa_state_read", "pa_state_write", "pa_stats_get",
+    "pa_probe_count", "pa_probe_read", "pa_state_read", "pa_state_read_device", "pa_state_write",
+    "pa_stats_get",
     "pa_kernel_timing", "pa_kernel_time", "pa_last_error", "pa_status_str",
 ]
 
 
 class pa_config(C.Structure):
     _fields_ = [("dt_ms", C.c_double), ("threshold_mV", C.c_double), ("seed", C.c_uint64),
-                ("precision", C.c_int32), ("mode", C.c_int32), ("probe_stride", C.c_uint32),
-                ("slot_capacity", C.c_uint32), ("cells_per_block", C.c_uint32),
+                ("precision", C.c_int32), ("mode", C.c_int32), ("flags", C.c_uint32),
+                ("cells_per_block", C.c_uint32),
                 ("block_threads", C.c_uint16), ("solver_waves", C.c_uint16), ("exchange", C.c_uint32)]
 
 
@@ -64,7 +65,7 @@ class pa_stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("n_cells", "n_cv", "n_syn", "n_stc", "n_conn",
                                           "n_trains", "n_probes", "n_poisson", "steps", "spikes",
                                           "events")] + \
-        [("epoch_steps", C.c_uint32), ("ring_slots", C.c_uint32), ("slot_capacity", C.c_uint32),
+        [("epoch_steps", C.c_uint32), ("spike_ring", C.c_uint32), ("queue_events", C.c_uint64),
          ("cells_per_block", C.c_uint32), ("advance_ms", C.c_double), ("device_bytes", C.c_uint64),
          ("block_threads", C.c_uint32), ("solver_waves", C.c_uint32), ("exchange", C.c_uint32)]
 
@@ -118,15 +119,16 @@ def load_library(path: str = None):
         "pa_trains_add": (st, [_P, C.c_uint32, _P, _P, _P, _P, _P]),
         "pa_poisson_add": (st, [_P, C.c_uint32, _P, _P, _P, _P]),
         "pa_clamps_add": (st, [_P, C.c_uint32, _P, _P, _P, _P, _P]),
-        "pa_probes_add": (st, [_P, C.c_uint32, _P, _P, C.POINTER(C.c_uint32)]),
+        "pa_probes_add": (st, [_P, C.c_uint32, _P, _P, _P, C.POINTER(C.c_uint32)]),
         "pa_finalize": (st, [_P]),
         "pa_advance": (st, [_P, C.c_double]),
         "pa_advance_steps": (st, [_P, C.c_uint64]),
         "pa_spikes_count": (st, [_P, C.POINTER(C.c_uint64)]),
         "pa_spikes_read": (st, [_P, _P, _P, _P, C.c_uint64, C.POINTER(C.c_uint64)]),
-        "pa_probe_count": (st, [_P, C.POINTER(C.c_uint64)]),
-        "pa_probe_read": (st, [_P, _P, C.c_uint64, C.POINTER(C.c_uint64)]),
+        "pa_probe_count": (st, [_P, C.c_uint32, C.POINTER(C.c_uint64)]),
+        "pa_probe_read": (st, [_P, C.c_uint32, _P, C.c_uint64, C.POINTER(C.c_uint64)]),
         "pa_state_read": (st, [_P, C.c_int32, _P, C.c_uint64]),
+        "pa_state_read_device": (st, [_P, C.c_int32, _P, C.c_uint64]),
         "pa_state_write": (st, [_P, C.c_int32, _P, C.c_uint64]),
         "pa_stats_get": (st, [_P, C.POINTER(pa_stats)]),
         "pa_kernel_timing": (st, [_P, C.c_int32]),
@@ -164,11 +166,13 @@ class Simulation:
     """A network built through the C ABI from a network dictionary.
 
     precision: "fp64" | "mixed"; mode: "plain" | "batched".
-    probes: list of (quantity, index) with quantity in V, g, c, h, z, p.
+    probes: list of (quantity, index) or (quantity, index, stride_steps) with
+    quantity in V, g, c, h, z, p; probe_stride is the stride of those
+    without one.
     """
 
     def __init__(self, net: dict, precision="fp64", mode="plain", probes=(), probe_stride=1,
-                 slot_capacity=0, cells_per_block=0, block_threads=0, solver_waves=0, exchange="auto",
+                 cells_per_block=0, block_threads=0, solver_waves=0, exchange="auto",
                  use_torch=True):
         lib = load_library()
         self._lib = lib
@@ -178,8 +182,7 @@ class Simulation:
         cfg.seed = int(net["seed"]) & (2**64 - 1)
         cfg.precision = {"fp64": PA_FP64, "mixed": PA_MIXED}[precision]
         cfg.mode = {"plain": PA_PLAIN, "batched": PA_BATCHED}[mode]
-        cfg.probe_stride = int(probe_stride)
-        cfg.slot_capacity = int(slot_capacity)
+        cfg.flags = 0
         cfg.cells_per_block = int(cells_per_block)
         cfg.block_threads = int(block_threads)
         cfg.solver_waves = int(solver_waves)
@@ -197,9 +200,10 @@ class Simulation:
             self._attach_torch()
         self._add_network(net)
         if probes:
-            what = np.array([PA_PROBE[q] for q, _ in probes], np.int32)
-            idx = np.array([int(i) for _, i in probes], np.uint64)
-            self._check(lib.pa_probes_add(h, len(what), _ptr(what), _ptr(idx), None))
+            what = np.array([PA_PROBE[p[0]] for p in probes], np.int32)
+            idx = np.array([int(p[1]) for p in probes], np.uint64)
+            stride = np.array([int(p[2]) if len(p) > 2 else int(probe_stride) for p in probes], np.uint32)
+            self._check(lib.pa_probes_add(h, len(what), _ptr(what), _ptr(idx), _ptr(stride), None))
         self.n_probes = len(probes)
         self._check(lib.pa_finalize(h))
         s = self.stats()
@@ -305,7 +309,7 @@ class Simulation:
         self._check(self._lib.pa_advance_steps(self._h, int(n)))
 
     def spikes(self):
-        """(gid, step, t*) arrays in (step, gid) order."""
+        """The raster, (gid, step, t*) arrays in (t*, gid) order."""
         n = C.c_uint64()
         self._check(self._lib.pa_spikes_count(self._h, C.byref(n)))
         m = n.value
@@ -316,14 +320,19 @@ class Simulation:
         self._check(self._lib.pa_spikes_read(self._h, _ptr(gid), _ptr(step), _ptr(t), m, C.byref(got)))
         return gid.astype(np.int64), step.astype(np.int64), t
 
-    def probes(self):
-        """Probe samples, shape (samples, probes)."""
+    def probe(self, k: int) -> np.ndarray:
+        """Samples of probe k, oldest first."""
         n = C.c_uint64()
-        self._check(self._lib.pa_probe_count(self._h, C.byref(n)))
-        out = np.zeros(n.value * self.n_probes, np.float64)
+        self._check(self._lib.pa_probe_count(self._h, int(k), C.byref(n)))
+        out = np.zeros(n.value, np.float64)
         got = C.c_uint64()
-        self._check(self._lib.pa_probe_read(self._h, _ptr(out), out.size, C.byref(got)))
-        return out.reshape(n.value, self.n_probes)
+        self._check(self._lib.pa_probe_read(self._h, int(k), _ptr(out), out.size, C.byref(got)))
+        return out[:got.value]
+
+    def probes(self):
+        """Samples of probes with equal strides, shape (samples, probes)."""
+        cols = [self.probe(k) for k in range(self.n_probes)]
+        return np.stack(cols, axis=1) if cols else np.zeros((0, 0))
 
     def _size(self, what):
         return {"V": self.n_cv, "m": self.n_hh, "hh": self.n_hh, "n": self.n_hh,
@@ -336,6 +345,12 @@ class Simulation:
             out = np.zeros(self._size(what), np.float64)
         self._check(self._lib.pa_state_read(self._h, PA_STATE[what], _ptr(out) or C.c_void_p(1), out.size))
         return out
+
+    def read_into(self, what: str, tensor) -> None:
+        """State array `what` into a device tensor (float64, or int64 pairs
+        for the event statistics) of the right size, without a host copy."""
+        self._check(self._lib.pa_state_read_device(self._h, PA_STATE[what], C.c_void_p(tensor.data_ptr()),
+                                                   int(tensor.numel())))
 
     def write(self, what: str, values):
         a = np.ascontiguousarray(values, np.float64)

@@ -23,6 +23,7 @@ namespace {
 
 constexpr double PI = 3.14159265358979323846;
 constexpr uint64_t HIST_CAP = 1ull << 24;   // spikes held on the device per chunk
+constexpr uint64_t SP_STAGE = 1ull << 16;   // spikes copied to the host per transfer
 
 struct Alloc {
     void *p;
@@ -74,6 +75,7 @@ struct pa_sim {
     std::vector<double> cl_t0, cl_dur, cl_amp;
     std::vector<int32_t> pr_what;
     std::vector<uint64_t> pr_index;
+    std::vector<uint32_t> pr_stride;
 
     // derived
     std::vector<uint32_t> syn_perm;   // sorted position -> synapse id
@@ -87,8 +89,14 @@ struct pa_sim {
     std::vector<uint64_t> sp_step;
     std::vector<double> sp_t;
     bool spikes_sorted = true;
-    std::vector<double> probe_rows;
-    uint64_t n_probe_rows = 0;
+    std::vector<std::vector<double>> probe_samples;  // per probe
+    std::vector<uint64_t> pr_off_host;                // region of each probe in the device buffer
+    uint64_t pr_buf_len = 0;
+    uint64_t drained_to = 0;      // steps whose probe samples the host holds
+    Counters *ctr_host = nullptr; // pinned: copy of the device counters, then a zero word
+    double *pr_host = nullptr;    // pinned staging of the probe buffer
+    uint8_t *sp_host = nullptr;   // pinned staging of spikes: SP_STAGE x (gid, step, t)
+    uint64_t queue_events = 0;    // capacity of the per-epoch queues
     double advance_ms = 0.0;
     BatchedPlan *plan = nullptr;        // batched form
     void *snap = nullptr;               // device copy of the mutable state (autotuning)
@@ -178,7 +186,7 @@ const char *pa_status_str(pa_status st) {
     case PA_ENOMEM: return "out of memory";
     case PA_EDEVICE: return "device error";
     case PA_ERANGE: return "time or event out of range";
-    case PA_EOVERFLOW: return "event slot overflow";
+    case PA_EOVERFLOW: return "event queue or spike history overflow";
     case PA_ENUMERIC: return "non-finite membrane voltage";
     default: return "unknown status";
     }
@@ -192,7 +200,7 @@ pa_status pa_sim_create(const pa_config *cfg, const pa_stc_params *stc, pa_sim *
     if (!finite_pos(cfg->dt_ms) || !std::isfinite(cfg->threshold_mV)) return PA_EINVAL;
     if (cfg->precision != PA_FP64 && cfg->precision != PA_MIXED) return PA_EINVAL;
     if (cfg->mode != PA_PLAIN && cfg->mode != PA_BATCHED) return PA_EINVAL;
-    if (cfg->probe_stride == 0) return PA_EINVAL;
+    if (cfg->flags != 0) return PA_EINVAL;
     if (cfg->block_threads != 0 && cfg->block_threads != 64 && cfg->block_threads != 128 &&
         cfg->block_threads != 256)
         return PA_EINVAL;
@@ -221,6 +229,9 @@ void pa_sim_destroy(pa_sim *s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     batched_release(s);
+    if (s->ctr_host) (void)hipHostFree(s->ctr_host);
+    if (s->pr_host) (void)hipHostFree(s->pr_host);
+    if (s->sp_host) (void)hipHostFree(s->sp_host);
     for (hipEvent_t e : s->tev) (void)hipEventDestroy(e);
     for (auto &a : s->allocs) {
         if (s->free_fn) s->free_fn(a.p, s->alloc_ctx);
@@ -417,12 +428,14 @@ pa_status pa_clamps_add(pa_sim *s, uint32_t n, const uint32_t *gid, const uint32
     return PA_OK;
 }
 
-pa_status pa_probes_add(pa_sim *s, uint32_t n, const int32_t *what, const uint64_t *index, uint32_t *first) {
+pa_status pa_probes_add(pa_sim *s, uint32_t n, const int32_t *what, const uint64_t *index,
+                        const uint32_t *stride_steps, uint32_t *first) {
     if (!s) return PA_EINVAL;
     if (s->state != 0) return fail(s, PA_ESTATE, "probes cannot be added after pa_finalize");
-    if (n && (!what || !index)) return fail(s, PA_EINVAL, "null array");
+    if (n && (!what || !index || !stride_steps)) return fail(s, PA_EINVAL, "null array");
     for (uint32_t k = 0; k < n; ++k) {
         const uint64_t i = index[k];
+        if (stride_steps[k] == 0) return fail(s, PA_EINVAL, "probe %u: stride must be >= 1", k);
         switch (what[k]) {
         case PA_PROBE_V:
             if (i >= (uint64_t)s->cv_off.back()) return fail(s, PA_EINVAL, "probe %u: CV out of range", k);
@@ -442,6 +455,7 @@ pa_status pa_probes_add(pa_sim *s, uint32_t n, const int32_t *what, const uint64
     if (first) *first = (uint32_t)s->pr_what.size();
     s->pr_what.insert(s->pr_what.end(), what, what + n);
     s->pr_index.insert(s->pr_index.end(), index, index + n);
+    s->pr_stride.insert(s->pr_stride.end(), stride_steps, stride_steps + n);
     return PA_OK;
 }
 
@@ -481,11 +495,23 @@ pa_status build(pa_sim *s) {
     else {
         double q = dmin / dt;
         long k = (long)std::ceil(q - 1e-9) - 1;
-        K = (uint32_t)std::max<long>(1, std::min<long>(k, 4096));
+        K = (uint32_t)std::max<long>(1, std::min<long>(k, 256));
     }
     const double tcd = P.t_cd;
     d.K = K;
-    d.R = K + (uint32_t)std::ceil((dmax + tcd) / dt) + 2;
+    // Spike rings.  An epoch's gather looks back in_lag steps from its first
+    // step (the longest delay, calcium port included, plus a margin for the
+    // crossing time and rounding), while the ring's own cell may already be
+    // writing spikes of the running epoch; a cell crosses the threshold at
+    // most every second step (V^n < theta <= V^{n+1} needs V back below
+    // theta), so that many steps hold at most half as many spikes.
+    const uint32_t lag_max = (uint32_t)std::ceil((dmax + tcd) / dt) + 3;
+    {
+        const uint32_t need = (lag_max + K + 1) / 2 + 2;
+        uint32_t H = 1;
+        while (H < need) H <<= 1;
+        d.H = H;
+    }
 
     // ---- synapse order (cell, CV, id) == (global CV, id)
     std::vector<uint32_t> &perm = s->syn_perm;
@@ -593,54 +619,76 @@ pa_status build(pa_sim *s) {
     }
     for (uint32_t i = 0; i < ncv; ++i) cv_cl_off[i + 1] += cv_cl_off[i];
 
-    // ---- connections by source, in connection id order
+    // ---- incoming connections by target cell, in connection id order
     const uint64_t ncon = s->conn_src.size();
-    std::vector<uint64_t> out_off(nc + 1, 0);
-    for (uint64_t k = 0; k < ncon; ++k) out_off[s->conn_src[k] + 1]++;
-    for (uint32_t c = 0; c < nc; ++c) out_off[c + 1] += out_off[c];
-    std::vector<uint32_t> out_syn(ncon), out_cell(ncon), out_cid(ncon);
-    std::vector<uint8_t> out_ports(ncon);
-    std::vector<double> out_w(ncon), out_d(ncon);
+    std::vector<uint64_t> in_off(nc + 1, 0);
+    for (uint64_t k = 0; k < ncon; ++k) in_off[s->syn_cell[s->conn_dst[k]] + 1]++;
+    for (uint32_t c = 0; c < nc; ++c) in_off[c + 1] += in_off[c];
+    std::vector<uint32_t> in_src(ncon), in_syn(ncon), in_cid(ncon), in_lag(ncon);
+    std::vector<uint8_t> in_ports(ncon);
+    std::vector<double> in_w(ncon), in_d(ncon);
+    // room of each cell's queue for one epoch: the events of an epoch's
+    // steps come from source spikes within K + 2 steps, at most K / 2 + 2 of
+    // them per source
+    std::vector<uint64_t> qcap(nc, 0);
+    const uint64_t spk_per_window = K / 2 + 2;
     {
-        std::vector<uint64_t> fill(out_off.begin(), out_off.end() - 1);
+        std::vector<uint64_t> fill(in_off.begin(), in_off.end() - 1);
         for (uint64_t k = 0; k < ncon; ++k) {
-            const uint64_t q = fill[s->conn_src[k]]++;
-            out_syn[q] = s->syn_rank[s->conn_dst[k]];
-            out_cell[q] = s->syn_cell[s->conn_dst[k]];
-            out_cid[q] = (uint32_t)k;
-            out_ports[q] = s->conn_ports[k];
-            out_w[q] = s->conn_w[k];
-            out_d[q] = s->conn_d[k];
+            const uint32_t tc = s->syn_cell[s->conn_dst[k]];
+            const uint64_t q = fill[tc]++;
+            in_src[q] = s->conn_src[k];
+            in_syn[q] = s->syn_rank[s->conn_dst[k]];
+            in_cid[q] = (uint32_t)k;
+            in_ports[q] = s->conn_ports[k];
+            in_w[q] = s->conn_w[k];
+            in_d[q] = s->conn_d[k];
+            const double dq = s->conn_d[k] + ((s->conn_ports[k] & PA_PORT_CA) ? tcd : 0.0);
+            in_lag[q] = (uint32_t)std::ceil(dq / dt) + 3;
+            qcap[tc] += spk_per_window * (uint64_t)(((s->conn_ports[k] & 1) ? 1 : 0) + ((s->conn_ports[k] & 2) ? 1 : 0));
         }
     }
-    // in-degree in events per step bounds the slot capacity
-    uint32_t Q = s->cfg.slot_capacity;
-    if (Q == 0) {
-        std::vector<uint32_t> indeg(nc, 0);
-        for (uint64_t k = 0; k < ncon; ++k)
-            indeg[s->syn_cell[s->conn_dst[k]]] += (s->conn_ports[k] & 1) + ((s->conn_ports[k] >> 1) & 1);
-        uint32_t mx = 0;
-        for (uint32_t c = 0; c < nc; ++c) mx = std::max(mx, indeg[c]);
-        Q = std::min<uint32_t>(64, std::max<uint32_t>(16, mx / 2 + 8));
-    }
-    d.Q = Q;
 
-    // ---- trains
+    // ---- trains: their arrivals in any K consecutive steps, per port, add
+    // to the target cell's queue room
     const uint32_t ntr = d.n_trains;
     std::vector<uint32_t> tr_syn(ntr), tr_cell(ntr);
     for (uint32_t k = 0; k < ntr; ++k) {
         tr_syn[k] = s->syn_rank[s->tr_dst[k]];
         tr_cell[k] = s->syn_cell[s->tr_dst[k]];
+        for (uint32_t p = 1; p <= 2; ++p) {
+            if (!(s->tr_ports[k] & p)) continue;
+            uint64_t best = 0, a = s->tr_off[k];
+            for (uint64_t j = s->tr_off[k]; j < s->tr_off[k + 1]; ++j) {
+                const double tj = p == 2 ? s->tr_t[j] + tcd : s->tr_t[j];
+                const double sj = std::floor(tj / dt);
+                for (;;) {
+                    const double ta = p == 2 ? s->tr_t[a] + tcd : s->tr_t[a];
+                    if (std::floor(ta / dt) + K <= sj) ++a;
+                    else break;
+                }
+                best = std::max<uint64_t>(best, j - a + 1);
+            }
+            qcap[tr_cell[k]] += best;
+        }
     }
 
-    // ---- Poisson sources
+    // ---- Poisson sources: room for far more arrivals per epoch than their
+    // rate makes likely (mean + 12 standard deviations + 16); a source that
+    // exceeds its cell's room fails the advance with PA_EOVERFLOW
     const uint32_t npo = (uint32_t)s->po_dst.size();
     d.n_pois = npo;
     std::vector<uint32_t> po_syn(npo), po_cell(npo);
     for (uint32_t k = 0; k < npo; ++k) {
         po_syn[k] = s->syn_rank[s->po_dst[k]];
         po_cell[k] = s->syn_cell[s->po_dst[k]];
+        const double m = s->po_rate[k] * 1e-3 * K * dt;
+        const uint64_t cap = (uint64_t)std::ceil(m + 12.0 * std::sqrt(m) + 16.0);
+        qcap[po_cell[k]] += cap * (uint64_t)(((s->po_ports[k] & 1) ? 1 : 0) + ((s->po_ports[k] & 2) ? 1 : 0));
     }
+    std::vector<uint64_t> q_off(nc + 1, 0);
+    for (uint32_t c = 0; c < nc; ++c) q_off[c + 1] = q_off[c] + qcap[c];
+    s->queue_events = q_off[nc];
 
     // ---- trains and Poisson sources grouped by target cell
     std::vector<uint32_t> tr_cell_off(nc + 1, 0), tr_by_cell(ntr), po_cell_off(nc + 1, 0), po_by_cell(npo);
@@ -763,13 +811,17 @@ pa_status build(pa_sim *s) {
     d.z = zeros<double>(s, ns, ok);
     d.ev_cnt = zeros<unsigned long long>(s, 2 * (size_t)ns, ok);
     d.ev_sum = zeros<unsigned long long>(s, 2 * (size_t)ns, ok);
-    d.out_off = upload(s, out_off, ok);
-    d.out_syn = upload(s, out_syn, ok);
-    d.out_cell = upload(s, out_cell, ok);
-    d.out_cid = upload(s, out_cid, ok);
-    d.out_ports = upload(s, out_ports, ok);
-    d.out_w = upload(s, out_w, ok);
-    d.out_d = upload(s, out_d, ok);
+    d.in_off = upload(s, in_off, ok);
+    d.in_src = upload(s, in_src, ok);
+    d.in_syn = upload(s, in_syn, ok);
+    d.in_cid = upload(s, in_cid, ok);
+    d.in_lag = upload(s, in_lag, ok);
+    d.in_ports = upload(s, in_ports, ok);
+    d.in_w = upload(s, in_w, ok);
+    d.in_d = upload(s, in_d, ok);
+    d.spk = zeros<SpikeRec>(s, (size_t)nc * d.H, ok);
+    d.spk_n = zeros<uint32_t>(s, nc, ok);
+    d.spk_last = zeros<uint32_t>(s, nc, ok);
     d.tr_syn = upload(s, tr_syn, ok);
     d.tr_cell = upload(s, tr_cell, ok);
     d.tr_ports = upload(s, s->tr_ports, ok);
@@ -791,19 +843,22 @@ pa_status build(pa_sim *s) {
     d.pois_ports = upload(s, s->po_ports, ok);
     d.pois_w = upload(s, s->po_w, ok);
     d.pois_rate = upload(s, s->po_rate, ok);
-    d.pois_t = zeros<double>(s, npo, ok);
-    d.pois_j = zeros<uint64_t>(s, npo, ok);
+    d.pois_t = zeros<double>(s, 2 * (size_t)npo, ok);
+    d.pois_j = zeros<uint64_t>(s, 2 * (size_t)npo, ok);
     d.cl_t0 = upload(s, clt0, ok);
     d.cl_dur = upload(s, cldur, ok);
     d.cl_amp = upload(s, clamp, ok);
-    d.ev_n = zeros<uint32_t>(s, (size_t)nc * d.R, ok);
+    d.q_off = upload(s, q_off, ok);
+    if (ok) {
+        d.q_ev = (Event *)dev_alloc(s, std::max<uint64_t>(1, q_off[nc]) * sizeof(Event));
+        if (!d.q_ev) ok = false;
+    }
+    if (s->cfg.mode == PA_PLAIN) {
+        d.ev_n = zeros<uint32_t>(s, (size_t)nc * K, ok);
+        d.ev_off = zeros<uint32_t>(s, (size_t)nc * K, ok);
+    }
     d.blk_done = zeros<uint64_t>(s, std::max<size_t>(1, nc), ok);
     d.bar_grp = zeros<uint32_t>(s, 34 * 32, ok);  // 32 group counters, top counter, release word
-    d.ev = (Event *)dev_alloc(s, (size_t)nc * d.R * d.Q * sizeof(Event));
-    if (!d.ev) ok = false;
-    d.ep_gid = zeros<uint32_t>(s, (size_t)nc * K, ok);
-    d.ep_step = zeros<uint32_t>(s, (size_t)nc * K, ok);
-    d.ep_t = zeros<double>(s, (size_t)nc * K, ok);
     d.hist_cap = HIST_CAP;
     d.hist_gid = zeros<uint32_t>(s, HIST_CAP, ok);
     d.hist_step = zeros<uint64_t>(s, HIST_CAP, ok);
@@ -811,13 +866,28 @@ pa_status build(pa_sim *s) {
     d.ctr = zeros<Counters>(s, 1, ok);
     d.pr_what = upload(s, s->pr_what, ok);
     d.pr_idx = upload(s, pr_idx, ok);
-    // chunk of steps between drains: the history must hold every spike
-    // (at most one per cell per step); a whole number of epochs
-    uint64_t chunk = std::max<uint64_t>(1, d.hist_cap / std::max<uint32_t>(1, nc));
+    d.pr_stride = upload(s, s->pr_stride, ok);
+    // chunk of steps between drains: the history must hold every spike (a
+    // cell crosses at most every second step) and the probe buffer every
+    // sample (at most 8 M values); a whole number of epochs
+    uint64_t chunk = std::max<uint64_t>(1, 2 * (d.hist_cap / std::max<uint32_t>(1, nc)));
     chunk = std::min<uint64_t>(chunk, 1u << 20);
+    double per_step = 0.0;
+    for (uint32_t str : s->pr_stride) per_step += 1.0 / str;
+    if (per_step > 0) chunk = std::min<uint64_t>(chunk, std::max<uint64_t>(1, (uint64_t)((8u << 20) / per_step)));
     chunk = std::max<uint64_t>(chunk / K * K, K);
     s->chunk = chunk;
-    d.pr_buf = zeros<double>(s, (chunk / s->cfg.probe_stride + 2) * std::max<uint32_t>(1, d.n_probes), ok);
+    s->pr_off_host.assign(d.n_probes + 1, 0);
+    for (uint32_t k = 0; k < d.n_probes; ++k) s->pr_off_host[k + 1] = s->pr_off_host[k] + chunk / s->pr_stride[k] + 2;
+    s->pr_buf_len = s->pr_off_host[d.n_probes];
+    s->probe_samples.assign(d.n_probes, {});
+    d.pr_off = upload(s, s->pr_off_host, ok);
+    d.pr_buf = zeros<double>(s, std::max<uint64_t>(1, s->pr_buf_len), ok);
+    if (ok && (hipHostMalloc((void **)&s->ctr_host, sizeof(Counters) + 64, hipHostMallocDefault) != hipSuccess ||
+               hipHostMalloc((void **)&s->pr_host, std::max<uint64_t>(1, s->pr_buf_len) * 8, hipHostMallocDefault) != hipSuccess ||
+               hipHostMalloc((void **)&s->sp_host, SP_STAGE * 20, hipHostMallocDefault) != hipSuccess))
+        ok = false;
+    if (ok) std::memset((uint8_t *)s->ctr_host + sizeof(Counters), 0, 64);
     if (!ok) return fail(s, PA_ENOMEM, "device allocation or upload failed (%.1f MB requested so far)",
                          s->device_bytes / 1048576.0);
     return PA_OK;
@@ -832,8 +902,8 @@ pa_status batched_setup(pa_sim *s);
 void batched_release(pa_sim *s);
 uint32_t batched_cells_per_block(pa_sim *s);
 void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves, uint32_t &exchange);
-uint32_t batched_multi_epochs(pa_sim *s);
-pa_status run_multi_batched(pa_sim *s, uint32_t n_epochs, hipEvent_t e0, hipEvent_t e1);
+uint32_t batched_resident_steps(pa_sim *s);
+pa_status run_resident_batched(pa_sim *s, uint32_t nsteps, hipEvent_t e0, hipEvent_t e1);
 pa_status run_epoch_batched(pa_sim *s, uint32_t nsteps, hipEvent_t e0, hipEvent_t e1);
 pa_status run_graph_batched(pa_sim *s, uint32_t &steps_done);
 uint32_t batched_graph_steps(pa_sim *s);
@@ -866,39 +936,58 @@ extern "C" pa_status pa_finalize(pa_sim *s) {
 // Epoch loop.
 namespace {
 
-pa_status drain(pa_sim *s, uint64_t rows) {
+// After an advance: reads the device counters and the probe samples of the
+// steps since the last drain with one synchronisation of the stream, then
+// the spikes recorded (if any) and resets the spike history.
+pa_status drain(pa_sim *s) {
     DevNet &d = s->d;
-    Counters c{};
-    HIPCHECK(s, hipMemcpyAsync(&c, d.ctr, sizeof c, hipMemcpyDeviceToHost, s->stream), "read counters");
+    const uint64_t first = s->drained_to, last = s->step;
+    HIPCHECK(s, hipMemcpyAsync(s->ctr_host, d.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s->stream), "read counters");
+    bool samples = false;
+    for (uint32_t k = 0; k < d.n_probes; ++k) samples |= last / s->pr_stride[k] > first / s->pr_stride[k];
+    if (samples)
+        HIPCHECK(s, hipMemcpyAsync(s->pr_host, d.pr_buf, s->pr_buf_len * 8, hipMemcpyDeviceToHost, s->stream), "read probes");
     HIPCHECK(s, hipStreamSynchronize(s->stream), "drain");
+    const Counters c = *s->ctr_host;
+    for (uint32_t k = 0; samples && k < d.n_probes; ++k) {
+        const uint64_t m = last / s->pr_stride[k] - first / s->pr_stride[k];
+        const double *src = s->pr_host + s->pr_off_host[k];
+        s->probe_samples[k].insert(s->probe_samples[k].end(), src, src + m);
+    }
+    s->drained_to = last;
     if (c.hist_n) {
-        const size_t n0 = s->sp_gid.size();
         const uint64_t n = std::min<uint64_t>(c.hist_n, d.hist_cap);
+        const size_t n0 = s->sp_gid.size();
         s->sp_gid.resize(n0 + n);
         s->sp_step.resize(n0 + n);
         s->sp_t.resize(n0 + n);
-        HIPCHECK(s, hipMemcpyAsync(s->sp_gid.data() + n0, d.hist_gid, n * 4, hipMemcpyDeviceToHost, s->stream), "read spikes");
-        HIPCHECK(s, hipMemcpyAsync(s->sp_step.data() + n0, d.hist_step, n * 8, hipMemcpyDeviceToHost, s->stream), "read spikes");
-        HIPCHECK(s, hipMemcpyAsync(s->sp_t.data() + n0, d.hist_t, n * 8, hipMemcpyDeviceToHost, s->stream), "read spikes");
+        uint32_t *hg = (uint32_t *)s->sp_host;
+        uint64_t *hs = (uint64_t *)(s->sp_host + SP_STAGE * 4);
+        double *ht = (double *)(s->sp_host + SP_STAGE * 12);
+        for (uint64_t a = 0; a < n; a += SP_STAGE) {
+            const uint64_t m = std::min<uint64_t>(SP_STAGE, n - a);
+            HIPCHECK(s, hipMemcpyAsync(hg, d.hist_gid + a, m * 4, hipMemcpyDeviceToHost, s->stream), "read spikes");
+            HIPCHECK(s, hipMemcpyAsync(hs, d.hist_step + a, m * 8, hipMemcpyDeviceToHost, s->stream), "read spikes");
+            HIPCHECK(s, hipMemcpyAsync(ht, d.hist_t + a, m * 8, hipMemcpyDeviceToHost, s->stream), "read spikes");
+            HIPCHECK(s, hipStreamSynchronize(s->stream), "drain");
+            std::memcpy(s->sp_gid.data() + n0 + a, hg, m * 4);
+            std::memcpy(s->sp_step.data() + n0 + a, hs, m * 8);
+            std::memcpy(s->sp_t.data() + n0 + a, ht, m * 8);
+        }
         s->spikes_sorted = false;
+        // the next advance starts an empty history (ordered before its kernels)
+        HIPCHECK(s, hipMemcpyAsync(&d.ctr->hist_n, (uint8_t *)s->ctr_host + sizeof(Counters), 8,
+                                   hipMemcpyHostToDevice, s->stream), "reset history");
     }
-    if (rows && d.n_probes) {
-        const size_t n0 = s->probe_rows.size();
-        s->probe_rows.resize(n0 + rows * d.n_probes);
-        HIPCHECK(s, hipMemcpyAsync(s->probe_rows.data() + n0, d.pr_buf, rows * d.n_probes * 8, hipMemcpyDeviceToHost, s->stream), "read probes");
-        s->n_probe_rows += rows;
-    }
-    Counters z{};
-    z.events = c.events;
-    z.step = c.step;
-    HIPCHECK(s, hipMemcpyAsync(d.ctr, &z, sizeof z, hipMemcpyHostToDevice, s->stream), "reset counters");
-    HIPCHECK(s, hipStreamSynchronize(s->stream), "drain");
     if (c.flags) {
         s->state = 2;
         if (c.flags & FLAG_NONFINITE) return fail(s, PA_ENUMERIC, "non-finite voltage in cell %u", c.bad_cell);
-        if (c.flags & FLAG_OVERFLOW) return fail(s, PA_EOVERFLOW, "event slot of cell %u overflowed (slot_capacity %u)", c.bad_cell, d.Q);
+        if (c.flags & FLAG_QUEUE)
+            return fail(s, PA_EOVERFLOW, "the events of one epoch exceeded the queue of the cells from cell %u "
+                                         "(Poisson arrivals far above their rate)", c.bad_cell);
+        if (c.flags & FLAG_HISTORY) return fail(s, PA_EOVERFLOW, "spike history overflowed (cell %u)", c.bad_cell);
         if (c.flags & FLAG_BARRIER) return fail(s, PA_EDEVICE, "grid barrier of the multi-epoch kernel timed out");
-        return fail(s, PA_ERANGE, "event for cell %u scheduled in the past", c.bad_cell);
+        return fail(s, PA_ERANGE, "an event of a spike of cell %u was due before the spike", c.bad_cell);
     }
     return PA_OK;
 }
@@ -936,73 +1025,76 @@ pa_status timing_events(pa_sim *s, hipEvent_t &b, hipEvent_t &e) {
 
 }  // namespace
 
+// The first step after `after` at which some probe samples (UINT64_MAX
+// without probes).
+static uint64_t next_sample(const pa_sim *s, uint64_t after) {
+    uint64_t best = UINT64_MAX;
+    for (uint32_t str : s->pr_stride) best = std::min<uint64_t>(best, (after / str + 1) * str);
+    return best;
+}
+
 extern "C" pa_status pa_advance_steps(pa_sim *s, uint64_t n_steps) {
     if (!s) return PA_EINVAL;
     if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
     if (s->state == 2) return fail(s, PA_ESTATE, "simulation failed earlier: %s", s->err.c_str());
     if (n_steps == 0) return PA_OK;
+    if (s->step + n_steps >= 0xffffffffull) return fail(s, PA_ERANGE, "step counts beyond 2^32 - 1 are not supported");
     auto t_start = std::chrono::steady_clock::now();
     DevNet &d = s->d;
-    const uint32_t stride = s->cfg.probe_stride;
     const uint64_t chunk = s->chunk;
     const uint64_t n_end = s->step + n_steps;
     while (s->step < n_end) {
         const uint64_t c_end = std::min(n_end, s->step + chunk);
-        // probe rows this chunk
-        const uint64_t first_row = (s->step) / stride;   // rows completed before
-        const uint64_t last_row = c_end / stride;
-        const uint64_t rows = last_row - first_row;
         while (s->step < c_end) {
             const uint64_t e0 = s->step;
+            const uint64_t sample = next_sample(s, e0);
             if (s->cfg.mode == PA_BATCHED) {
-                // whole epochs in one resident launch when nothing needs the
-                // host between steps
-                const uint32_t max_ep = batched_multi_epochs(s);
-                if (!d.n_probes && max_ep && c_end - e0 >= d.K) {
-                    const uint32_t ne = (uint32_t)std::min<uint64_t>((c_end - e0) / d.K, max_ep);
-                    hipEvent_t tb = nullptr, te = nullptr;
-                    if (s->timing && timing_events(s, tb, te) != PA_OK) return PA_EDEVICE;
-                    pa_status st = run_multi_batched(s, ne, tb, te);
-                    if (st != PA_OK) return st;
-                    s->step = e0 + (uint64_t)ne * d.K;
-                    continue;
-                }
-                // replay the captured graph of whole epochs when nothing needs
-                // the host between steps
+                // epochs end at probe samples
+                const uint64_t stop = std::min(c_end, sample);
+                const uint32_t max_res = batched_resident_steps(s);
                 const uint32_t gsteps = batched_graph_steps(s);
-                if (!d.n_probes && !s->timing && gsteps && c_end - e0 >= gsteps) {
+                hipEvent_t tb = nullptr, te = nullptr;
+                if (max_res) {
+                    // steps in one resident launch
+                    const uint32_t ns = (uint32_t)std::min<uint64_t>(stop - e0, max_res);
+                    if (s->timing && timing_events(s, tb, te) != PA_OK) return PA_EDEVICE;
+                    pa_status st = run_resident_batched(s, ns, tb, te);
+                    if (st != PA_OK) return st;
+                    s->step = e0 + ns;
+                } else if (!s->timing && gsteps && stop - e0 >= gsteps) {
+                    // replay the captured graph of whole epochs
                     uint32_t done = 0;
                     pa_status st = run_graph_batched(s, done);
                     if (st != PA_OK) return st;
                     s->step = e0 + done;
-                    continue;
+                } else {
+                    const uint64_t e1 = std::min(stop, e0 + d.K);
+                    if (s->timing && timing_events(s, tb, te) != PA_OK) return PA_EDEVICE;
+                    pa_status st = run_epoch_batched(s, (uint32_t)(e1 - e0), tb, te);
+                    if (st != PA_OK) return st;
+                    s->step = e1;
                 }
-                // one epoch; with probes it ends on the next sample step
-                uint64_t e1 = std::min(c_end, e0 + d.K);
-                if (d.n_probes) e1 = std::min<uint64_t>(e1, (e0 / stride + 1) * stride);
-                hipEvent_t tb = nullptr, te = nullptr;
-                if (s->timing && timing_events(s, tb, te) != PA_OK) return PA_EDEVICE;
-                pa_status st = run_epoch_batched(s, (uint32_t)(e1 - e0), tb, te);
-                if (st != PA_OK) return st;
-                s->step = e1;
-                if (d.n_probes && e1 % stride == 0)
-                    if (launch_probe(d, e1 / stride - 1 - first_row, s->stream)) return hip_fail(s, hipGetLastError(), "probe");
+                if (s->step == sample && launch_probe(d, sample, s->drained_to, s->stream))
+                    return hip_fail(s, hipGetLastError(), "probe");
                 continue;
             }
-            const uint64_t e1 = std::min(c_end, (e0 / d.K + 1) * d.K);
-            const uint32_t len = (uint32_t)(e1 - e0);
-            if (launch_inject(d, len, s->stream)) return hip_fail(s, hipGetLastError(), "inject");
+            // plain form: gather the epoch's events, then one kernel per stage
+            // and step; probes after the steps they sample
+            const uint64_t e1 = std::min(c_end, e0 + d.K);
+            if (launch_gather(d, e0, (uint32_t)(e1 - e0), s->stream)) return hip_fail(s, hipGetLastError(), "gather");
+            uint64_t smp = sample;
             for (uint64_t n = e0; n < e1; ++n) {
                 hipEvent_t tb = nullptr, te = nullptr;
                 if (s->timing && timing_events(s, tb, te) != PA_OK) return PA_EDEVICE;
-                if (launch_step_plain(d, n, s->stream, tb, te)) return hip_fail(s, hipGetLastError(), "step");
-                if (d.n_probes && (n + 1) % stride == 0)
-                    if (launch_probe(d, (n + 1) / stride - 1 - first_row, s->stream)) return hip_fail(s, hipGetLastError(), "probe");
+                if (launch_step_plain(d, n, e0, s->stream, tb, te)) return hip_fail(s, hipGetLastError(), "step");
+                if (n + 1 == smp) {
+                    if (launch_probe(d, n + 1, s->drained_to, s->stream)) return hip_fail(s, hipGetLastError(), "probe");
+                    smp = next_sample(s, n + 1);
+                }
             }
-            if (launch_expand(d, len, s->stream)) return hip_fail(s, hipGetLastError(), "expand");
             s->step = e1;
         }
-        pa_status st = drain(s, rows);
+        pa_status st = drain(s);
         if (st != PA_OK) return st;
     }
     if (s->timing && fold_timing(s) != PA_OK) return PA_EDEVICE;
@@ -1040,7 +1132,7 @@ extern "C" pa_status pa_spikes_read(const pa_sim *cs, uint32_t *gid, uint64_t *s
         std::vector<size_t> idx(m);
         std::iota(idx.begin(), idx.end(), 0);
         std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
-            if (s->sp_step[a] != s->sp_step[b]) return s->sp_step[a] < s->sp_step[b];
+            if (s->sp_t[a] != s->sp_t[b]) return s->sp_t[a] < s->sp_t[b];
             return s->sp_gid[a] < s->sp_gid[b];
         });
         std::vector<uint32_t> g2(m);
@@ -1062,16 +1154,19 @@ extern "C" pa_status pa_spikes_read(const pa_sim *cs, uint32_t *gid, uint64_t *s
     return PA_OK;
 }
 
-extern "C" pa_status pa_probe_count(const pa_sim *s, uint64_t *n) {
+extern "C" pa_status pa_probe_count(const pa_sim *s, uint32_t probe_id, uint64_t *n) {
     if (!s || !n) return PA_EINVAL;
-    *n = s->n_probe_rows;
+    if (probe_id >= s->probe_samples.size()) return PA_EINVAL;
+    *n = s->probe_samples[probe_id].size();
     return PA_OK;
 }
 
-extern "C" pa_status pa_probe_read(const pa_sim *s, double *out, uint64_t cap, uint64_t *n) {
+extern "C" pa_status pa_probe_read(const pa_sim *s, uint32_t probe_id, double *out, uint64_t cap, uint64_t *n) {
     if (!s || !n || (cap && !out)) return PA_EINVAL;
-    const uint64_t m = std::min<uint64_t>(cap, s->probe_rows.size());
-    std::memcpy(out, s->probe_rows.data(), m * 8);
+    if (probe_id >= s->probe_samples.size()) return PA_EINVAL;
+    const std::vector<double> &v = s->probe_samples[probe_id];
+    const uint64_t m = std::min<uint64_t>(cap, v.size());
+    if (m) std::memcpy(out, v.data(), m * 8);
     *n = m;
     return PA_OK;
 }
@@ -1133,6 +1228,20 @@ extern "C" pa_status pa_state_read(pa_sim *s, int32_t what, void *out, uint64_t 
     return PA_OK;
 }
 
+extern "C" pa_status pa_state_read_device(pa_sim *s, int32_t what, void *out, uint64_t n) {
+    if (!s || !out) return PA_EINVAL;
+    if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
+    View v;
+    if (!view_of(s, what, v)) return fail(s, PA_EINVAL, "unknown state array %d", what);
+    const uint64_t count = (what >= PA_STATE_EVCOUNT) ? 2 * v.n : v.n;
+    if (n != count) return fail(s, PA_EINVAL, "state array %d has %llu elements", what, (unsigned long long)count);
+    const uint32_t words = v.narrow ? 1u : (uint32_t)(v.esize / 8);
+    if (launch_state_out(v.p, words, v.narrow, v.perm == 1 ? s->d.syn_sid : nullptr, v.n, out, s->stream))
+        return hip_fail(s, hipGetLastError(), "state copy");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "state copy");
+    return PA_OK;
+}
+
 extern "C" pa_status pa_state_write(pa_sim *s, int32_t what, const void *in, uint64_t n) {
     if (!s || !in) return PA_EINVAL;
     if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
@@ -1175,8 +1284,8 @@ extern "C" pa_status pa_stats_get(const pa_sim *s, pa_stats *o) {
     o->steps = s->step;
     o->spikes = s->sp_gid.size();
     o->epoch_steps = s->d.K;
-    o->ring_slots = s->d.R;
-    o->slot_capacity = s->d.Q;
+    o->spike_ring = s->d.H;
+    o->queue_events = s->queue_events;
     o->cells_per_block = batched_cells_per_block(const_cast<pa_sim *>(s));
     batched_plan_shape(const_cast<pa_sim *>(s), o->block_threads, o->solver_waves, o->exchange);
     o->advance_ms = s->advance_ms;
@@ -1229,9 +1338,11 @@ pa_status pa_snapshot(pa_sim *s, int restore) {
         {d.S, (size_t)d.n_cells * 8}, {d.vdet_old, (size_t)d.n_cells * 8}, {d.post, (size_t)d.n_cells},
         {d.ev_cnt, (size_t)d.n_syn * 16}, {d.ev_sum, (size_t)d.n_syn * 16},
         {d.gsum, d.gsum ? (size_t)d.n_cv * 8 : 0}, {d.gesum, d.gesum ? (size_t)d.n_cv * 8 : 0},
-        {d.ev_n, (size_t)d.n_cells * d.R * 4}, {d.blk_done, (size_t)d.n_cells * 8}, {d.bar_grp, 34 * 32 * 4},
+        {d.spk, (size_t)d.n_cells * d.H * sizeof(SpikeRec)}, {d.spk_n, (size_t)d.n_cells * 4},
+        {d.spk_last, (size_t)d.n_cells * 4},
+        {d.blk_done, (size_t)d.n_cells * 8}, {d.bar_grp, 34 * 32 * 4},
         {d.tr_cur, (size_t)d.n_trains * 16},
-        {d.pois_t, (size_t)d.n_pois * 8}, {d.pois_j, (size_t)d.n_pois * 8},
+        {d.pois_t, (size_t)d.n_pois * 16}, {d.pois_j, (size_t)d.n_pois * 16},
         {d.ctr, sizeof(Counters)}};
     size_t total = 0;
     for (const Span &x : spans) total += (x.n + 255) & ~size_t(255);

@@ -196,9 +196,9 @@ __device__ __forceinline__ float gate_next<float>(float x, float v, float dt, in
 
 // --------------------------------------------------------------- coherent access
 // Loads and stores that are coherent across the whole device (they do not
-// stop in the non-coherent per-XCD L2 cache).  Event rings and their counts
-// are written by one workgroup and read by another within a launch of the
-// resident multi-epoch kernel, so they are accessed only this way.
+// stop in the non-coherent per-XCD L2 cache).  Spike rings and their
+// counters are written by one workgroup and read by another within a launch
+// of the resident multi-epoch kernel, so they are accessed only this way.
 template <class U>
 __device__ __forceinline__ U ld_coh(const U *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -208,24 +208,6 @@ __device__ __forceinline__ void st_coh(U *p, U v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ Event ld_event(const Event *p) {
-    const uint64_t *q = (const uint64_t *)p;
-    uint64_t w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = ld_coh(q + k);
-    Event e;
-    __builtin_memcpy(&e, w, sizeof e);
-    return e;
-}
-
-__device__ __forceinline__ void st_event(Event *p, const Event &e) {
-    uint64_t w[4];
-    __builtin_memcpy(w, &e, sizeof e);
-    uint64_t *q = (uint64_t *)p;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) st_coh(q + k, w[k]);
-}
-
 // --------------------------------------------------------------- flags
 __device__ inline void raise_flag(const DevNet &d, uint32_t flag, uint32_t cell) {
     uint32_t old = atomicOr(&d.ctr->flags, flag);
@@ -233,31 +215,6 @@ __device__ inline void raise_flag(const DevNet &d, uint32_t flag, uint32_t cell)
 }
 
 // --------------------------------------------------------------- events
-// Appends event e for delivery at step s to the ring of `cell`; steps before
-// `min_step` are in the past (epoch already running) and raise FLAG_LATE.
-__device__ inline void push_event(const DevNet &d, uint32_t cell, uint64_t s, const Event &e,
-                                  uint64_t min_step) {
-    if (s < min_step) {
-        raise_flag(d, FLAG_LATE, cell);
-        return;
-    }
-    if (s >= min_step + d.R - d.K) {
-        raise_flag(d, FLAG_OVERFLOW, cell);
-        return;
-    }
-    const uint32_t slot = (uint32_t)(s % d.R);
-    const uint64_t ring = (uint64_t)cell * d.R + slot;
-    const uint32_t pos = atomicAdd(&d.ev_n[ring], 1u);
-    if (pos < d.Q) st_event(d.ev + ring * d.Q + pos, e);
-    else raise_flag(d, FLAG_OVERFLOW, cell);
-}
-
-// Moves the arrivals of explicit train tr whose delivery step falls before
-// epoch_end into the target cell's ring.
-__device__ inline void inject_train(const DevNet &d, uint32_t tr, uint64_t epoch_start, uint64_t epoch_end);
-// Draws the arrivals of Poisson source k due before epoch_end into the ring.
-__device__ inline void inject_poisson(const DevNet &d, uint32_t k, uint64_t epoch_start, uint64_t epoch_end);
-
 __device__ __forceinline__ bool ev_before(const Event &a, const Event &b) {
     if (a.t != b.t) return a.t < b.t;
     if (a.src != b.src) return a.src < b.src;
@@ -286,7 +243,8 @@ __device__ __forceinline__ T apply_event(const DevNet &d, uint32_t s, uint32_t p
     return T(0);
 }
 
-// Sorts the cnt events of a ring slot in place into delivery order.
+// Sorts cnt events in place into delivery order (t_e, source, connection,
+// port); the events of one (cell, step) slot are few, so insertion sort.
 __device__ inline void sort_slot(Event *ev, uint32_t cnt) {
     for (uint32_t i = 1; i < cnt; ++i) {
         Event x = ev[i];
@@ -299,98 +257,153 @@ __device__ inline void sort_slot(Event *ev, uint32_t cnt) {
     }
 }
 
-// The same for a slot left in the ring (coherent accesses).
-__device__ inline void sort_slot_coh(Event *ev, uint32_t cnt) {
-    for (uint32_t i = 1; i < cnt; ++i) {
-        const Event x = ld_event(ev + i);
-        uint32_t j = i;
-        while (j > 0) {
-            const Event y = ld_event(ev + j - 1);
-            if (!ev_before(x, y)) break;
-            st_event(ev + j, y);
-            --j;
+// Records the spike of `cell` at step n (crossing time ts) in the cell's
+// ring and in the spike history.  Only the cell's own lane writes its ring;
+// entries and counters are written with device-coherent stores, so that
+// workgroups of a resident launch read them after the grid barrier.
+__device__ inline void record_spike(const DevNet &d, uint32_t cell, uint64_t n, double ts) {
+    const uint32_t k = ld_coh(d.spk_n + cell);
+    uint64_t *r = (uint64_t *)(d.spk + (uint64_t)cell * d.H + (k & (d.H - 1)));
+    st_coh(r, (uint64_t)__double_as_longlong(ts));
+    st_coh(r + 1, (uint64_t)(uint32_t)n | ((uint64_t)k << 32));
+    st_coh(d.spk_n + cell, k + 1);
+    st_coh(d.spk_last + cell, (uint32_t)n + 1u);
+    const uint64_t pos = atomicAdd((unsigned long long *)&d.ctr->hist_n, 1ull);
+    if (pos < d.hist_cap) {
+        d.hist_gid[pos] = cell;
+        d.hist_step[pos] = n;
+        d.hist_t[pos] = ts;
+    } else {
+        raise_flag(d, FLAG_HISTORY, cell);
+    }
+}
+
+// The events of incoming connection q due in the steps [n0, n0 + nst):
+// for every spike of the source recent enough to matter, a conductance
+// event at t_e = t* + d and, with the calcium port, a calcium event at
+// t_e + t_c,delay, each due at step floor(t_e / dt); emit(st, e) receives
+// the step within the epoch and the event.  Spikes of the running epoch
+// (step >= n0) and ring entries not yet holding the spike looked for are
+// skipped.  The ring holds every spike that can still be due (sized on the
+// host from the longest delay, a cell fires at most every second step).
+template <class F>
+__device__ __forceinline__ void conn_events(const DevNet &d, uint64_t q, uint64_t n0, uint32_t nst, F &&emit) {
+    const uint32_t src = d.in_src[q];
+    const uint32_t last = ld_coh(d.spk_last + src);
+    const int64_t lo = (int64_t)n0 - (int64_t)d.in_lag[q];
+    if (last == 0 || (int64_t)last - 1 < lo) return;
+    const uint32_t cnt = ld_coh(d.spk_n + src);
+    const uint32_t stop = cnt > d.H ? cnt - d.H : 0u;
+    const uint8_t ports = d.in_ports[q];
+    const double dly = d.in_d[q];
+    Event e;
+    e.w = d.in_w[q];
+    e.syn = d.in_syn[q];
+    e.src = src;
+    e.conn = d.in_cid[q];
+    const uint64_t n1 = n0 + nst;
+    for (uint32_t k = cnt; k-- > stop;) {
+        const uint64_t *r = (const uint64_t *)(d.spk + (uint64_t)src * d.H + (k & (d.H - 1)));
+        const uint64_t w1 = ld_coh(r + 1);
+        if ((uint32_t)(w1 >> 32) != k) continue;
+        const uint64_t ns = (uint32_t)w1;
+        if (ns >= n0) continue;
+        if ((int64_t)ns < lo) break;
+        const double ts = __longlong_as_double((long long)ld_coh(r));
+        const double te = ts + dly;
+        if (ports & 1) {
+            const uint64_t s = (uint64_t)floor(te / d.dt);
+            if (s <= ns) raise_flag(d, FLAG_LATE, src);
+            if (s >= n0 && s < n1) {
+                e.t = te;
+                e.port = 1;
+                emit((uint32_t)(s - n0), e);
+            }
         }
-        st_event(ev + j, x);
+        if (ports & 2) {
+            const double tc = te + d.stc.t_cd;
+            const uint64_t s = (uint64_t)floor(tc / d.dt);
+            if (s <= ns) raise_flag(d, FLAG_LATE, src);
+            if (s >= n0 && s < n1) {
+                e.t = tc;
+                e.port = 2;
+                emit((uint32_t)(s - n0), e);
+            }
+        }
     }
 }
 
-// Delivers the cnt events waiting in the ring slot of step n of one cell in
-// (t_e, src, conn, port) order and empties the slot.  The post-synaptic hook
-// is applied with the synapse update (syn_update).
-template <class T>
-__device__ inline void deliver_slot(const DevNet &d, uint32_t cell, uint64_t n, uint32_t cnt,
-                                    const SynView<T> &sv, const SynConst<T> &sc) {
-    const uint64_t ring = (uint64_t)cell * d.R + (uint32_t)(n % d.R);
-    if (cnt > d.Q) cnt = d.Q;  // overflow was flagged at insertion
-    Event *ev = d.ev + ring * d.Q;
-    sort_slot(ev, cnt);
-    for (uint32_t i = 0; i < cnt; ++i) {
-        const Event e = ev[i];
-        apply_event<T>(d, e.syn, e.port, e.w, sv, sc);
-        d.ev_cnt[2 * e.syn + e.port - 1] += 1ull;
-        d.ev_sum[2 * e.syn + e.port - 1] += (unsigned long long)n;
-    }
-}
-
-__device__ inline void inject_train(const DevNet &d, uint32_t tr, uint64_t epoch_start, uint64_t epoch_end) {
-    const uint32_t cell = d.tr_cell[tr];
-    const uint64_t end = d.tr_off[tr + 1];
+// The arrivals of explicit train tr due in [n0, n0 + nst), per port from
+// that port's cursor (the calcium port t_c,delay later); `advance` moves
+// the cursors past them.
+template <class F>
+__device__ inline void train_events(const DevNet &d, uint32_t tr, uint64_t n0, uint32_t nst, bool advance,
+                                    F &&emit) {
+    const uint64_t end = d.tr_off[tr + 1], n1 = n0 + nst;
     Event e;
     e.w = d.tr_w[tr];
     e.syn = d.tr_syn[tr];
     e.src = d.n_cells + tr;
     e.conn = 0;
-    if (d.tr_ports[tr] & 1) {
-        uint64_t j = d.tr_cur[2 * tr];
+    const uint8_t ports = d.tr_ports[tr];
+    for (uint32_t p = 1; p <= 2; ++p) {
+        if (!(ports & p)) continue;
+        const double shift = p == 2 ? d.stc.t_cd : 0.0;
+        uint64_t j = d.tr_cur[2 * tr + p - 1];
         for (; j < end; ++j) {
-            const double t = d.tr_t[j];
+            const double t = p == 2 ? d.tr_t[j] + shift : d.tr_t[j];
             const uint64_t s = (uint64_t)floor(t / d.dt);
-            if (s >= epoch_end) break;
+            if (s >= n1) break;
+            if (s < n0) {
+                // an arrival before the epoch: the cursor missed it
+                raise_flag(d, FLAG_LATE, d.tr_cell[tr]);
+                continue;
+            }
             e.t = t;
-            e.port = 1;
-            push_event(d, cell, s, e, epoch_start);
+            e.port = p;
+            emit((uint32_t)(s - n0), e);
         }
-        d.tr_cur[2 * tr] = j;
-    }
-    if (d.tr_ports[tr] & 2) {
-        uint64_t j = d.tr_cur[2 * tr + 1];
-        for (; j < end; ++j) {
-            const double t = d.tr_t[j] + d.stc.t_cd;
-            const uint64_t s = (uint64_t)floor(t / d.dt);
-            if (s >= epoch_end) break;
-            e.t = t;
-            e.port = 2;
-            push_event(d, cell, s, e, epoch_start);
-        }
-        d.tr_cur[2 * tr + 1] = j;
+        if (advance) d.tr_cur[2 * tr + p - 1] = j;
     }
 }
 
-__device__ inline void inject_poisson(const DevNet &d, uint32_t k, uint64_t epoch_start, uint64_t epoch_end) {
-    double t = d.pois_t[k];
-    uint64_t j = d.pois_j[k];
-    const uint32_t cell = d.pois_cell[k];
+// The arrivals of Poisson source k due in [n0, n0 + nst): each port walks
+// the source's arrival sequence with a state of its own (next arrival time
+// and index), the calcium port t_c,delay later; `advance` stores the state.
+template <class F>
+__device__ inline void poisson_events(const DevNet &d, uint32_t k, uint64_t n0, uint32_t nst, bool advance,
+                                      F &&emit) {
+    const uint64_t n1 = n0 + nst;
     Event e;
     e.w = d.pois_w[k];
     e.syn = d.pois_syn[k];
     e.src = d.n_cells + d.n_trains + k;
     e.conn = 0;
-    while (floor(t / d.dt) < (double)epoch_end) {
-        if (d.pois_ports[k] & 1) {
-            e.t = t;
-            e.port = 1;
-            push_event(d, cell, (uint64_t)floor(t / d.dt), e, epoch_start);
+    const uint8_t ports = d.pois_ports[k];
+    const double rate = d.pois_rate[k];
+    for (uint32_t p = 1; p <= 2; ++p) {
+        if (!(ports & p)) continue;
+        double t = d.pois_t[2 * k + p - 1];
+        uint64_t j = d.pois_j[2 * k + p - 1];
+        for (;;) {
+            const double te = p == 2 ? t + d.stc.t_cd : t;
+            const double sf = floor(te / d.dt);
+            if (!(sf < (double)n1)) break;
+            if (sf >= (double)n0) {
+                e.t = te;
+                e.port = p;
+                emit((uint32_t)((uint64_t)sf - n0), e);
+            } else {
+                raise_flag(d, FLAG_LATE, d.pois_cell[k]);
+            }
+            ++j;
+            t = t + poisson_isi(d.seed, k, j, rate);
         }
-        if (d.pois_ports[k] & 2) {
-            e.t = t + d.stc.t_cd;
-            e.port = 2;
-            push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, epoch_start);
+        if (advance) {
+            d.pois_t[2 * k + p - 1] = t;
+            d.pois_j[2 * k + p - 1] = j;
         }
-        ++j;
-        t = t + poisson_isi(d.seed, k, j, d.pois_rate[k]);
     }
-    d.pois_t[k] = t;
-    d.pois_j[k] = j;
 }
 
 // --------------------------------------------------------------- currents
@@ -488,6 +501,16 @@ __device__ __forceinline__ double dpp_shift_add(double x) {
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
     return x + __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane) {
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -770,44 +793,6 @@ __device__ __forceinline__ bool crossed(const DevNet &d, double v0, double v1) {
 __device__ __forceinline__ double spike_time(const DevNet &d, uint64_t n, double v0, double v1) {
     const double tn = (double)n * d.dt;
     return tn + d.dt * ((d.theta - v0) / (v1 - v0));
-}
-
-// Threshold detection: records the spike in the epoch's spike buffer;
-// returns whether the cell fired.
-__device__ inline bool detect(const DevNet &d, uint32_t cell, uint64_t n, double v0, double v1) {
-    if (!crossed(d, v0, v1)) return false;
-    const double ts = spike_time(d, n, v0, v1);
-    const uint32_t pos = atomicAdd(&d.ctr->ep_n, 1u);
-    d.ep_gid[pos] = cell;
-    d.ep_step[pos] = (uint32_t)n;
-    d.ep_t[pos] = ts;
-    return true;
-}
-
-// The events of one spike (source gid at time ts): lanes of a wavefront over
-// the source's outgoing connections; each connection port becomes one event
-// in the target cell's ring, due no earlier than min_step.
-__device__ inline void expand_spike(const DevNet &d, uint32_t gid, double ts, uint32_t lane, uint64_t min_step) {
-    for (uint64_t q = d.out_off[gid] + lane; q < d.out_off[gid + 1]; q += 64) {
-        Event e;
-        e.w = d.out_w[q];
-        e.syn = d.out_syn[q];
-        e.src = gid;
-        e.conn = d.out_cid[q];
-        const uint32_t cell = d.out_cell[q];
-        const uint8_t ports = d.out_ports[q];
-        const double te = ts + d.out_d[q];
-        if (ports & 1) {
-            e.t = te;
-            e.port = 1;
-            push_event(d, cell, (uint64_t)floor(te / d.dt), e, min_step);
-        }
-        if (ports & 2) {
-            e.t = te + d.stc.t_cd;
-            e.port = 2;
-            push_event(d, cell, (uint64_t)floor(e.t / d.dt), e, min_step);
-        }
-    }
 }
 
 }  // namespace pa

@@ -1,8 +1,9 @@
 // HIP kernels (gfx950) of one implicit-Euler step of a plastic network of
 // multi-compartment neurons, and of the spike exchange between epochs.
 //
-// Plain form: one kernel per stage per step (deliver, currents, solve,
-// gates+sum, synapses, cells), each one lane per cell / CV / synapse.
+// Plain form: per epoch one kernel gathering every cell's events of the
+// epoch into its queue; per step one kernel per stage (deliver, currents,
+// solve, gates+sum, synapses, cells), each one lane per cell / CV / synapse.
 // Batched form (kernels_fused.hip): one kernel per epoch.
 //
 // Arithmetic follows the definitions of the model term by term, in a fixed
@@ -32,21 +33,68 @@ __global__ void k_init(DevNet d) {
     ((T *)d.gn)[k] = r[4] / (r[4] + r[5]);
 }
 
+// Both arrival streams of Poisson source k (conductance and calcium port)
+// start at its first arrival.
 __global__ void k_init_poisson(DevNet d) {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n_pois) return;
-    d.pois_j[k] = 0;
-    d.pois_t[k] = d.pois_rate[k] > 0.0 ? poisson_isi(d.seed, k, 0, d.pois_rate[k]) : INFINITY;
+    const double t0 = d.pois_rate[k] > 0.0 ? poisson_isi(d.seed, k, 0, d.pois_rate[k]) : INFINITY;
+    d.pois_j[2 * k] = d.pois_j[2 * k + 1] = 0;
+    d.pois_t[2 * k] = d.pois_t[2 * k + 1] = t0;
 }
 
-// ----------------------------------------------------------------- trains
-// At the start of an epoch ending at `epoch_end`, move every train arrival
-// whose delivery step falls before epoch_end into the target cell's ring.
-__global__ void k_inject(DevNet d, uint32_t nsteps) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t epoch_start = d.ctr->step, epoch_end = epoch_start + nsteps;
-    if (x < d.n_trains) inject_train(d, x, epoch_start, epoch_end);
-    else if (x - d.n_trains < d.n_pois) inject_poisson(d, x - d.n_trains, epoch_start, epoch_end);
+// ----------------------------------------------------------------- gather
+// The events of the epoch [n0, n0 + nst) of one cell per wavefront, into
+// the cell's queue: a counting pass over its incoming connections, trains
+// and Poisson sources (count per step of the epoch), a wavefront prefix sum
+// over the steps, a scatter pass, then each step's events sorted into
+// delivery order (one lane per step).  LDS: 2 K words per wavefront.
+__global__ void k_gather(DevNet d, uint64_t n0, uint32_t nst) {
+    extern __shared__ uint32_t gsh[];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t cell = blockIdx.x * (blockDim.x >> 6) + wave;
+    if (cell >= d.n_cells) return;
+    const uint32_t K = d.K;
+    uint32_t *cnt = gsh + 2 * K * wave, *cur = cnt + K;
+    for (uint32_t st = lane; st < nst; st += 64) cnt[st] = 0;
+    wave_sync();
+    const uint64_t qa = d.in_off[cell], qb = d.in_off[cell + 1];
+    const uint32_t ta = d.tr_cell_off[cell], tb = d.tr_cell_off[cell + 1];
+    const uint32_t pa = d.po_cell_off[cell], pb = d.po_cell_off[cell + 1];
+    auto count = [&](uint32_t st, const Event &) { atomicAdd(&cnt[st], 1u); };
+    for (uint64_t q = qa + lane; q < qb; q += 64) conn_events(d, q, n0, nst, count);
+    for (uint32_t x = ta + lane; x < tb; x += 64) train_events(d, d.tr_by_cell[x], n0, nst, false, count);
+    for (uint32_t x = pa + lane; x < pb; x += 64) poisson_events(d, d.po_by_cell[x], n0, nst, false, count);
+    wave_sync();
+    uint32_t base = 0;
+    for (uint32_t s0 = 0; s0 < nst; s0 += 64) {
+        const uint32_t st = s0 + lane;
+        const uint32_t v = st < nst ? cnt[st] : 0u;
+        const uint32_t inc = wave_incl_scan(v, lane);
+        if (st < nst) cur[st] = base + inc - v;
+        base += (uint32_t)__shfl((int)inc, 63, 64);
+    }
+    const uint64_t q0 = d.q_off[cell];
+    const uint64_t room = d.q_off[cell + 1] - q0;
+    if (base > room && lane == 0) raise_flag(d, FLAG_QUEUE, cell);
+    wave_sync();
+    Event *Q = d.q_ev + q0;
+    auto place = [&](uint32_t st, const Event &e) {
+        const uint32_t pos = atomicAdd(&cur[st], 1u);
+        if (pos < room) Q[pos] = e;
+    };
+    for (uint64_t q = qa + lane; q < qb; q += 64) conn_events(d, q, n0, nst, place);
+    for (uint32_t x = ta + lane; x < tb; x += 64) train_events(d, d.tr_by_cell[x], n0, nst, true, place);
+    for (uint32_t x = pa + lane; x < pb; x += 64) poisson_events(d, d.po_by_cell[x], n0, nst, true, place);
+    wave_sync();
+    for (uint32_t st = lane; st < nst; st += 64) {
+        const uint32_t c = cnt[st];
+        const uint32_t off = cur[st] - c;
+        const uint32_t m = off >= room ? 0u : (uint32_t)min<uint64_t>(c, room - off);
+        sort_slot(Q + off, m);
+        d.ev_n[(uint64_t)cell * K + st] = m;
+        d.ev_off[(uint64_t)cell * K + st] = off;
+    }
 }
 
 // ----------------------------------------------------------------- views
@@ -65,15 +113,24 @@ __device__ __forceinline__ SynConst<T> global_const(const DevNet &d) {
 }
 
 // ----------------------------------------------------------------- deliver
+// The events of step n of each cell (lane per cell), in their sorted order;
+// n0 is the first step of the epoch the queues were gathered for.
 template <class T>
-__global__ void k_deliver(DevNet d, uint64_t n) {
+__global__ void k_deliver(DevNet d, uint64_t n, uint64_t n0) {
     uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= d.n_cells) return;
-    const uint64_t ring = (uint64_t)cell * d.R + (uint32_t)(n % d.R);
-    const uint32_t cnt = d.ev_n[ring];
+    const uint64_t slot = (uint64_t)cell * d.K + (n - n0);
+    const uint32_t cnt = d.ev_n[slot];
     if (!cnt) return;
-    deliver_slot<T>(d, cell, n, cnt, global_syn<T>(d), global_const<T>(d));
-    d.ev_n[ring] = 0;
+    const Event *ev = d.q_ev + d.q_off[cell] + d.ev_off[slot];
+    const SynView<T> sv = global_syn<T>(d);
+    const SynConst<T> sc = global_const<T>(d);
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const Event e = ev[i];
+        apply_event<T>(d, e.syn, e.port, e.w, sv, sc);
+        d.ev_cnt[2 * e.syn + e.port - 1] += 1ull;
+        d.ev_sum[2 * e.syn + e.port - 1] += (unsigned long long)n;
+    }
     atomicAdd((unsigned long long *)&d.ctr->events, (unsigned long long)cnt);
 }
 
@@ -151,59 +208,22 @@ __global__ void k_cellpost(DevNet d, uint64_t n) {
     uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= d.n_cells) return;
     d.p[cell] = prp_next(d, d.p[cell], d.S[cell]);
-    d.post[cell] = detect(d, cell, n, d.vdet_old[cell], d.V[d.det_cv[cell]]) ? 1 : 0;
+    const double v0 = d.vdet_old[cell], v1 = d.V[d.det_cv[cell]];
+    const bool fired = crossed(d, v0, v1);
+    if (fired) record_spike(d, cell, n, spike_time(d, n, v0, v1));
+    d.post[cell] = fired ? 1 : 0;
 }
-
-// ----------------------------------------------------------------- exchange
-// One wavefront per spike of the epoch (grid-stride), lanes over the
-// source's outgoing connections; each connection port becomes one event in
-// the target cell's ring.  Also appends the epoch's spikes to the history.
-__global__ void k_expand(DevNet d, uint32_t nsteps) {
-    const uint64_t epoch_end = d.ctr->step + nsteps;
-    const uint32_t n_sp = d.ctr->ep_n;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
-    const uint64_t hist0 = d.ctr->hist_n;
-    for (uint32_t k = wave; k < n_sp; k += n_waves) {
-        const uint32_t gid = d.ep_gid[k];
-        const double ts = d.ep_t[k];
-        if (lane == 0) {
-            uint64_t hpos = hist0 + k;
-            if (hpos < d.hist_cap) {
-                d.hist_gid[hpos] = gid;
-                d.hist_step[hpos] = d.ep_step[k];
-                d.hist_t[hpos] = ts;
-            } else {
-                raise_flag(d, FLAG_OVERFLOW, gid);
-            }
-        }
-        expand_spike(d, gid, ts, lane, epoch_end);
-    }
-    // the last workgroup to finish closes the epoch: the spikes join the
-    // history and the epoch's first step advances
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(&d.ctr->blocks_done, 1u);
-        if (prev == gridDim.x - 1) {
-            __threadfence();
-            d.ctr->hist_n += n_sp;
-            d.ctr->ep_n = 0;
-            d.ctr->step += nsteps;
-            d.ctr->blocks_done = 0;
-            __threadfence();
-        }
-    }
-}
-
-
 
 // ----------------------------------------------------------------- probes
+// Probes due after step n (stride dividing n): probe k's sample of step n
+// goes to entry n / stride - first / stride - 1 of its region, `first` being
+// the first step of the present drain interval.
 template <class T>
-__global__ void k_probe(DevNet d, uint64_t row) {
+__global__ void k_probe(DevNet d, uint64_t n, uint64_t first) {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n_probes) return;
+    const uint32_t str = d.pr_stride[k];
+    if (n % str != 0) return;
     const uint64_t i = d.pr_idx[k];
     double v = 0.0;
     switch (d.pr_what[k]) {
@@ -214,7 +234,21 @@ __global__ void k_probe(DevNet d, uint64_t row) {
     case 4: v = d.z[i]; break;
     default: v = d.p[i]; break;
     }
-    d.pr_buf[row * d.n_probes + k] = v;
+    d.pr_buf[d.pr_off[k] + n / str - first / str - 1] = v;
+}
+
+// A state array into a caller's device buffer: element q (words 64-bit
+// words each, or one FP32 value widened) to position perm[q] (or q).
+__global__ void k_state_out(const void *src, uint32_t words, uint32_t narrow, const uint32_t *perm, uint64_t n,
+                            void *dst) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const uint64_t o = perm ? perm[q] : q;
+    if (narrow) {
+        ((double *)dst)[o] = (double)((const float *)src)[q];
+    } else {
+        for (uint32_t j = 0; j < words; ++j) ((uint64_t *)dst)[o * words + j] = ((const uint64_t *)src)[q * words + j];
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
@@ -237,18 +271,17 @@ int launch_init(const DevNet &d, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_inject(const DevNet &d, uint32_t nsteps, void *stream) {
-    if (d.n_trains + d.n_pois == 0) return 0;
-    hipLaunchKernelGGL(k_inject, grid_for((uint64_t)d.n_trains + d.n_pois, 256), dim3(256), 0,
-                       (hipStream_t)stream, d, nsteps);
+int launch_gather(const DevNet &d, uint64_t n0, uint32_t nsteps, void *stream) {
+    hipLaunchKernelGGL(k_gather, grid_for((uint64_t)d.n_cells * 64, 256), dim3(256), 4 * 2 * d.K * sizeof(uint32_t),
+                       (hipStream_t)stream, d, n0, nsteps);
     return (int)hipGetLastError();
 }
 
 template <class T>
-static int step_plain(const DevNet &d, uint64_t n, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static int step_plain(const DevNet &d, uint64_t n, uint64_t n0, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 b(256);
     const double tn = (double)n * d.dt;
-    hipLaunchKernelGGL(k_deliver<T>, grid_for(d.n_cells, 256), b, 0, s, d, n);
+    hipLaunchKernelGGL(k_deliver<T>, grid_for(d.n_cells, 256), b, 0, s, d, n, n0);
     hipLaunchKernelGGL(k_current<T>, grid_for(d.n_cv, 256), b, 0, s, d, tn);
     hipLaunchKernelGGL(k_solve, grid_for(d.n_cells, 64), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_cellpre<T>, grid_for((uint64_t)d.n_cells * 64, 256), b, 0, s, d);
@@ -259,28 +292,26 @@ static int step_plain(const DevNet &d, uint64_t n, hipStream_t s, hipEvent_t e0,
     return (int)hipGetLastError();
 }
 
-int launch_step_plain(const DevNet &d, uint64_t n, void *stream, void *ev_begin, void *ev_end) {
+int launch_step_plain(const DevNet &d, uint64_t n, uint64_t n0, void *stream, void *ev_begin, void *ev_end) {
     if (d.mixed)
-        return step_plain<float>(d, n, (hipStream_t)stream, (hipEvent_t)ev_begin, (hipEvent_t)ev_end);
-    return step_plain<double>(d, n, (hipStream_t)stream, (hipEvent_t)ev_begin, (hipEvent_t)ev_end);
+        return step_plain<float>(d, n, n0, (hipStream_t)stream, (hipEvent_t)ev_begin, (hipEvent_t)ev_end);
+    return step_plain<double>(d, n, n0, (hipStream_t)stream, (hipEvent_t)ev_begin, (hipEvent_t)ev_end);
 }
 
-int launch_expand(const DevNet &d, uint32_t nsteps, void *stream) {
-    hipStream_t s = (hipStream_t)stream;
-    // enough wavefronts for a busy epoch, bounded so an idle epoch is cheap
-    uint64_t waves = (uint64_t)d.n_cells * d.K;
-    if (waves > 4096) waves = 4096;
-    if (waves < 4) waves = 4;
-    hipLaunchKernelGGL(k_expand, grid_for(waves * 64, 256), dim3(256), 0, s, d, nsteps);
+int launch_probe(const DevNet &d, uint64_t n, uint64_t first, void *stream) {
+    if (d.n_probes == 0) return 0;
+    if (d.mixed)
+        hipLaunchKernelGGL(k_probe<float>, grid_for(d.n_probes, 256), dim3(256), 0, (hipStream_t)stream, d, n, first);
+    else
+        hipLaunchKernelGGL(k_probe<double>, grid_for(d.n_probes, 256), dim3(256), 0, (hipStream_t)stream, d, n, first);
     return (int)hipGetLastError();
 }
 
-int launch_probe(const DevNet &d, uint64_t row, void *stream) {
-    if (d.n_probes == 0) return 0;
-    if (d.mixed)
-        hipLaunchKernelGGL(k_probe<float>, grid_for(d.n_probes, 256), dim3(256), 0, (hipStream_t)stream, d, row);
-    else
-        hipLaunchKernelGGL(k_probe<double>, grid_for(d.n_probes, 256), dim3(256), 0, (hipStream_t)stream, d, row);
+int launch_state_out(const void *src, uint32_t words, bool narrow, const uint32_t *perm, uint64_t n, void *dst,
+                     void *stream) {
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_state_out, grid_for(n, 256), dim3(256), 0, (hipStream_t)stream, src, words,
+                       narrow ? 1u : 0u, perm, n, dst);
     return (int)hipGetLastError();
 }
 

@@ -55,8 +55,6 @@ struct FusedLayout {
     uint32_t G, C, Dec, M, HH, N;
     // 32-bit
     uint32_t Par, HHk, CvSyn, CvCl, Cb0, Cs0, Cg0, Ch0, Det, HHcv, EvN, EvOff, Scan;
-    // spikes of the workgroup's cells in the current epoch (multi-epoch form)
-    uint32_t SpkT, SpkC;
     // events of the epoch, each slot's records sorted into delivery order
     uint32_t EvBuf, ev_cap;
     // 16-bit, 8-bit
@@ -94,8 +92,7 @@ struct FusedLayout {
         CvCl = take(4 * (nv + 1), 4); Cb0 = take(4 * (nc + 1), 4); Cs0 = take(4 * (nc + 1), 4);
         Cg0 = take(4 * (nc + 1), 4); Ch0 = take(4 * (nc + 1), 4);
         Det = take(4 * nc, 4); HHcv = take(4 * nh, 4); EvN = take(4 * nc * K, 4);
-        EvOff = take(4 * nc * K, 4); Scan = take(12, 4);
-        SpkT = take(8 * nc * K, 8); SpkC = take(4 * nc * K, 4);
+        EvOff = take(4 * nc * K, 4); Scan = take(16, 4);
         ev_cap = 2 * nc * K + 32;
         EvBuf = take(32 * ev_cap, 16);
         SynCv = take(2 * (tsize == 4 ? ns : 0), 2);
@@ -343,10 +340,12 @@ __device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) 
     return *ok_word != 0;
 }
 
-// One epoch of nsteps (<= K) steps for the cells blk[b] .. blk[b+1]-1 of
-// workgroup b.  Mutable state of those cells (V, gates, g, c, h, z, p, post
-// flag), their constants and the epoch's events live in LDS, so a step
-// touches global memory only for spikes, clamps and rare noise keys.
+// Steps of the cells blk[b] .. blk[b+1]-1 of workgroup b: one epoch of
+// nsteps (<= K) steps, or, resident, nsteps steps in epochs of K (the last
+// one shorter) with a grid barrier between epochs.  Mutable state of those
+// cells (V, gates, g, c, h, z, p, post flag), their constants and the
+// epoch's events live in LDS, so a step touches global memory only for
+// spikes, clamps and rare noise keys.
 #ifdef PA_MIN_WAVES_PER_EU
 #define PA_EPOCH_BOUNDS(BS_) __launch_bounds__(BS_, PA_MIN_WAVES_PER_EU)
 #else
@@ -354,7 +353,7 @@ __device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) 
 #endif
 template <class T, uint32_t BS>
 __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk, uint32_t nsteps,
-                                              uint32_t n_epochs, uint32_t solver_waves) {
+                                              uint32_t resident, uint32_t solver_waves) {
     extern __shared__ double lds[];
     uint8_t *L = (uint8_t *)lds;
     const uint32_t tid = threadIdx.x;
@@ -406,15 +405,15 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     const bool chains = (ng == ncb);
     const SynConst<T> sc{sErev, sDec, sKind, s0};
     const GateView<T> gv{sM, sHH, sN, k0};
-    // first step of the launch; the multi-epoch form runs n_epochs epochs of
-    // K steps, the single-epoch form one epoch of nsteps
+    // first step of the launch; the resident form runs nsteps steps in
+    // epochs of K, the single-epoch form one epoch of nsteps
     const uint64_t nbase = d.ctr->step;
-    const bool multi = n_epochs > 0;
-    const uint32_t n_ep = multi ? n_epochs : 1u;
+    const bool multi = resident != 0;
     uint64_t n0 = nbase;
-    uint32_t *sSpkN = (uint32_t *)(L + lay.Scan) + 1;
-    double *sSpkT = (double *)(L + lay.SpkT);
-    uint32_t *sSpkC = (uint32_t *)(L + lay.SpkC);
+    // the epoch's events are in LDS, or, when they do not fit, in the
+    // workgroup's queue in global memory
+    Event *gEv = d.q_ev + d.q_off[c0];
+    const uint64_t groom = d.q_off[c1] - d.q_off[c0];
     STAGE_INIT();
 
     // ---- stage in: state, constants, this epoch's events
@@ -482,7 +481,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     }
     for (uint32_t c = tid; c < ncb; c += BS)
         for (uint32_t g = d.seg_off[c0 + c]; g < d.seg_off[c0 + c + 1]; ++g) sSegCell[g - g0] = (uint16_t)c;
-    if (tid == 0) *sSpkN = 0;
     __syncthreads();
     // the cells of this wavefront: a solver wavefront's share split by CV
     // count, a synapse wavefront's share split by synapse count
@@ -515,21 +513,19 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     // delivery order
     auto deliver = [&](uint32_t st, T *gh, uint32_t half) {
         const SynView<T> sv{gh, sC, sH, sZ, s0};
+        const bool inlds = sScan[3] == 0;
         for (uint32_t c = uc0 + lane; c < uc1; c += 64) {
             const uint32_t cnt = sEvN[c * K + st];
             if (!cnt) continue;
-            const uint32_t off = sEvOff[c * K + st];
-            const Event *ev = off != 0xffffffffu
-                                  ? sEv + off
-                                  : d.ev + ((uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R)) * d.Q;
+            const Event *ev = (inlds ? sEv : gEv) + sEvOff[c * K + st];
             for (uint32_t i = 0; i < cnt; ++i) {
-                const Event e = off != 0xffffffffu ? ev[i] : ld_event(ev + i);
+                const Event e = ev[i];
                 const uint32_t sy = e.syn;
                 const T dg = apply_event<T>(d, sy, e.port, e.w, sv, sc);
                 if (lay.carried && dg != T(0)) {
                     // the reversal potential: in the record's time field
                     // for an event staged in LDS, else from global memory
-                    const double E = off != 0xffffffffu ? e.t : d.syn_erev[sy];
+                    const double E = inlds ? e.t : d.syn_erev[sy];
                     const uint32_t cv = sSynCv[sy - s0];
                     sGs[half * nv + cv] += (double)dg;
                     sGsE[half * nv + cv] += (double)dg * E;
@@ -555,53 +551,80 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     };
 
     STAGE_MARK(6);
-    for (uint32_t ep = 0; ep < n_ep; ++ep) {
-    n0 = nbase + (uint64_t)ep * K;
-    const uint32_t nst = multi ? K : nsteps;
-    // external arrivals of this epoch for the workgroup's cells enter the
-    // rings (trains and Poisson sources grouped by target cell)
-    {
-        const uint64_t epoch_end = n0 + nst;
-        const uint32_t t0 = d.tr_cell_off[c0], t1 = d.tr_cell_off[c1];
-        for (uint32_t x = t0 + tid; x < t1; x += BS) inject_train(d, d.tr_by_cell[x], n0, epoch_end);
-        const uint32_t p0 = d.po_cell_off[c0], p1 = d.po_cell_off[c1];
-        for (uint32_t x = p0 + tid; x < p1; x += BS) inject_poisson(d, d.po_by_cell[x], n0, epoch_end);
-    }
-    if (tid == 0) sScan[0] = 0;
-    __syncthreads();
-    STAGE_MARK(9);
-    // events of the epoch: one lane per (cell, step) slot takes the slot's
-    // count, claims room in the LDS event buffer, copies the records there
-    // and sorts them into delivery order (a slot that does not fit is
-    // sorted in place in the ring); the delivery statistics are counted
-    // here, in parallel
+    const uint32_t n_total = nsteps;
+    for (uint32_t done = 0; done < n_total;) {
+    n0 = nbase + done;
+    const uint32_t nst = multi ? min(K, n_total - done) : nsteps;
+    // ---- the epoch's events of the workgroup's cells: a counting pass over
+    // their incoming connections, trains and Poisson sources (count per
+    // (cell, step) slot), a prefix sum over the slots, a scatter pass into
+    // LDS (or, if they do not fit, the workgroup's queue in global memory),
+    // then each slot sorted into delivery order (one lane per slot); the
+    // delivery statistics are counted there
     const uint32_t nslot = ncb * nst;
     for (uint32_t x = tid; x < nslot; x += BS) {
         const uint32_t c = x / nst, st = x - c * nst;
-        const uint64_t ring = (uint64_t)(c0 + c) * d.R + (uint32_t)((n0 + st) % d.R);
-        const uint32_t cnt = min(ld_coh(d.ev_n + ring), d.Q);
-        sEvN[c * K + st] = cnt;
-        if (!cnt) continue;
-        st_coh(d.ev_n + ring, 0u);
-        Event *ev = d.ev + ring * d.Q;
-        const uint32_t off = atomicAdd(&sScan[0], cnt);
-        if (off + cnt <= lay.ev_cap) {
-            Event *dst = sEv + off;
-            for (uint32_t i = 0; i < cnt; ++i) dst[i] = ld_event(ev + i);
-            sort_slot(dst, cnt);
-            sEvOff[c * K + st] = off;
-        } else {
-            sort_slot_coh(ev, cnt);
-            sEvOff[c * K + st] = 0xffffffffu;
+        sEvN[c * K + st] = 0;
+    }
+    __syncthreads();
+    const uint64_t qa = d.in_off[c0], qb = d.in_off[c1];
+    const uint32_t ta = d.tr_cell_off[c0], tb = d.tr_cell_off[c1];
+    const uint32_t pa = d.po_cell_off[c0], pb = d.po_cell_off[c1];
+    {
+        auto count = [&](uint32_t st, const Event &e) { atomicAdd(&sEvN[(d.syn_cell[e.syn] - c0) * K + st], 1u); };
+        for (uint64_t q = qa + tid; q < qb; q += BS) conn_events(d, q, n0, nst, count);
+        for (uint32_t x = ta + tid; x < tb; x += BS) train_events(d, d.tr_by_cell[x], n0, nst, false, count);
+        for (uint32_t x = pa + tid; x < pb; x += BS) poisson_events(d, d.po_by_cell[x], n0, nst, false, count);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t base = 0;
+        for (uint32_t x0 = 0; x0 < nslot; x0 += 64) {
+            const uint32_t x = x0 + lane;
+            const uint32_t c = x / nst, st = x - c * nst;
+            const uint32_t v = x < nslot ? sEvN[c * K + st] : 0u;
+            const uint32_t inc = wave_incl_scan(v, lane);
+            if (x < nslot) sEvOff[c * K + st] = base + inc - v;
+            base += (uint32_t)__shfl((int)inc, 63, 64);
         }
-        const bool staged = off + cnt <= lay.ev_cap;
-        for (uint32_t i = 0; i < cnt; ++i) {
-            const Event e = staged ? sEv[off + i] : ld_event(ev + i);
+        if (lane == 0) {
+            sScan[1] = base;
+            sScan[3] = base > lay.ev_cap ? 1u : 0u;
+            if (base > lay.ev_cap && base > groom) raise_flag(d, FLAG_QUEUE, c0);
+        }
+    }
+    __syncthreads();
+    const bool evlds = sScan[3] == 0;
+    const uint64_t room = evlds ? lay.ev_cap : groom;
+    Event *evb = evlds ? sEv : gEv;
+    {
+        auto place = [&](uint32_t st, const Event &e) {
+            const uint32_t pos = atomicAdd(&sEvOff[(d.syn_cell[e.syn] - c0) * K + st], 1u);
+            if (pos < room) evb[pos] = e;
+        };
+        for (uint64_t q = qa + tid; q < qb; q += BS) conn_events(d, q, n0, nst, place);
+        for (uint32_t x = ta + tid; x < tb; x += BS) train_events(d, d.tr_by_cell[x], n0, nst, true, place);
+        for (uint32_t x = pa + tid; x < pb; x += BS) poisson_events(d, d.po_by_cell[x], n0, nst, true, place);
+    }
+    __syncthreads();
+    STAGE_MARK(9);
+    for (uint32_t x = tid; x < nslot; x += BS) {
+        const uint32_t c = x / nst, st = x - c * nst;
+        const uint32_t cnt = sEvN[c * K + st];
+        const uint32_t off = sEvOff[c * K + st] - cnt;
+        const uint32_t m = off >= room ? 0u : (uint32_t)min<uint64_t>(cnt, room - off);
+        sEvN[c * K + st] = m;
+        sEvOff[c * K + st] = off;
+        if (!m) continue;
+        Event *ev = evb + off;
+        sort_slot(ev, m);
+        for (uint32_t i = 0; i < m; ++i) {
+            const Event e = ev[i];
             atomicAdd(&d.ev_cnt[2 * e.syn + e.port - 1], 1ull);
             atomicAdd(&d.ev_sum[2 * e.syn + e.port - 1], (unsigned long long)(n0 + st));
-            // once sorted, a staged record's time field carries the target's
-            // reversal potential for the carried sums
-            if (lay.carried && staged) sEv[off + i].t = d.syn_erev[e.syn];
+            // once sorted, a record's time field in LDS carries the
+            // target's reversal potential for the carried sums
+            if (lay.carried && evlds) ev[i].t = d.syn_erev[e.syn];
         }
     }
     __syncthreads();
@@ -707,27 +730,9 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             *x = gate_next<T>(*x, (T)sV[sHHcv[k]], (T)d.dt, (int)j);
         }
         for (uint32_t c = wc0 + lane; c < wc1; c += 64) {
-            bool fired;
-            if (!multi) {
-                fired = detect(d, c0 + c, n, sVold[c], sV[sDet[c]]);
-            } else {
-                const double v0 = sVold[c], v1 = sV[sDet[c]];
-                fired = crossed(d, v0, v1);
-                if (fired) {
-                    const double ts = spike_time(d, n, v0, v1);
-                    const uint64_t pos = atomicAdd((unsigned long long *)&d.ctr->hist_n, 1ull);
-                    if (pos < d.hist_cap) {
-                        d.hist_gid[pos] = c0 + c;
-                        d.hist_step[pos] = n;
-                        d.hist_t[pos] = ts;
-                    } else {
-                        raise_flag(d, FLAG_OVERFLOW, c0 + c);
-                    }
-                    const uint32_t k = atomicAdd(sSpkN, 1u);
-                    sSpkC[k] = c;
-                    sSpkT[k] = ts;
-                }
-            }
+            const double v0 = sVold[c], v1 = sV[sDet[c]];
+            const bool fired = crossed(d, v0, v1);
+            if (fired) record_spike(d, c0 + c, n, spike_time(d, n, v0, v1));
             postn[c] = fired ? 1 : 0;
         }
         STAGE_MARK(2);
@@ -803,22 +808,18 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             __syncthreads();
         }
     }
-    if (multi) {
-        // this epoch's spikes of the workgroup's cells become events in
-        // the target cells' rings (due in a later epoch), then every
-        // workgroup waits for all the others before the next epoch reads
-        // its rings
-        const uint32_t nsp = *sSpkN;
-        for (uint32_t k = wave; k < nsp; k += NW) expand_spike(d, c0 + sSpkC[k], sSpkT[k], lane, n0 + K);
+    done += nst;
+    if (multi && done < n_total) {
+        // the epoch's spikes are in their cells' rings; every workgroup
+        // waits for all the others before the next epoch gathers from them
         const bool ok = grid_sync(d, gridDim.x, sScan + 2);
         STAGE_MARK(8);
-        if (tid == 0) *sSpkN = 0;
         if (!ok) break;
     }
     }
     STAGE_MARK(5);
     // ---- stage out
-    const uint32_t hfin = (uint32_t)((multi ? (uint64_t)n_ep * K : nsteps) & 1u);
+    const uint32_t hfin = n_total & 1u;
     const T *gfin = sG + gofs(hfin);
     const uint8_t *pfin = sPost + hfin * ncb;
     for (uint32_t i = tid; i < nv; i += BS) {
@@ -844,7 +845,23 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         d.post[c0 + c] = pfin[c];
     }
     if (delivered) atomicAdd((unsigned long long *)&d.ctr->events, delivered);
-    if (multi && blockIdx.x == 0 && tid == 0) d.ctr->step = nbase + (uint64_t)n_ep * K;
+    // close the launch: the resident form's first workgroup moves the epoch
+    // counter past its steps (every workgroup read it at its start); in the
+    // single-epoch form the last workgroup to finish does
+    if (multi) {
+        if (blockIdx.x == 0 && tid == 0) d.ctr->step = nbase + n_total;
+    } else {
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            const uint32_t prev = atomicAdd(&d.ctr->blocks_done, 1u);
+            if (prev == gridDim.x - 1) {
+                d.ctr->blocks_done = 0;
+                d.ctr->step = nbase + n_total;
+                __threadfence();
+            }
+        }
+    }
     STAGE_MARK(7);
     STAGE_FLUSH();
 }
@@ -871,9 +888,9 @@ int launch_carried_sums(const DevNet &d, void *stream) {
 }
 
 template <class T, uint32_t BS>
-static int launch_fused_t(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, const uint32_t *blk, uint32_t n_blocks,
+static int launch_fused_t(const DevNet &d, uint32_t nsteps, uint32_t resident, const uint32_t *blk, uint32_t n_blocks,
                           size_t lds_bytes, uint32_t solver_waves, hipStream_t s) {
-    if (n_epochs == 0) {
+    if (!resident) {
         hipLaunchKernelGGL((k_epoch<T, BS>), dim3(n_blocks), dim3(BS), lds_bytes, s, d, blk, nsteps, 0u, solver_waves);
         return (int)hipGetLastError();
     }
@@ -881,22 +898,22 @@ static int launch_fused_t(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, c
     // launch guarantees it or fails
     DevNet dc = d;
     const uint32_t *b = blk;
-    uint32_t a_ns = nsteps, a_ne = n_epochs, a_sw = solver_waves;
-    void *args[] = {&dc, &b, &a_ns, &a_ne, &a_sw};
+    uint32_t a_ns = nsteps, a_res = 1u, a_sw = solver_waves;
+    void *args[] = {&dc, &b, &a_ns, &a_res, &a_sw};
     return (int)hipLaunchCooperativeKernel((const void *)k_epoch<T, BS>, dim3(n_blocks), dim3(BS), args,
                                            (unsigned)lds_bytes, s);
 }
 
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, const uint32_t *blk, uint32_t n_blocks,
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, uint32_t resident, const uint32_t *blk, uint32_t n_blocks,
                        size_t lds_bytes, uint32_t block_threads, uint32_t solver_waves, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     switch (block_threads) {
-    case 64: return d.mixed ? launch_fused_t<float, 64>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s)
-                            : launch_fused_t<double, 64>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s);
-    case 128: return d.mixed ? launch_fused_t<float, 128>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s)
-                             : launch_fused_t<double, 128>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s);
-    case 256: return d.mixed ? launch_fused_t<float, 256>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s)
-                             : launch_fused_t<double, 256>(d, nsteps, n_epochs, blk, n_blocks, lds_bytes, solver_waves, s);
+    case 64: return d.mixed ? launch_fused_t<float, 64>(d, nsteps, resident, blk, n_blocks, lds_bytes, solver_waves, s)
+                            : launch_fused_t<double, 64>(d, nsteps, resident, blk, n_blocks, lds_bytes, solver_waves, s);
+    case 128: return d.mixed ? launch_fused_t<float, 128>(d, nsteps, resident, blk, n_blocks, lds_bytes, solver_waves, s)
+                             : launch_fused_t<double, 128>(d, nsteps, resident, blk, n_blocks, lds_bytes, solver_waves, s);
+    case 256: return d.mixed ? launch_fused_t<float, 256>(d, nsteps, resident, blk, n_blocks, lds_bytes, solver_waves, s)
+                             : launch_fused_t<double, 256>(d, nsteps, resident, blk, n_blocks, lds_bytes, solver_waves, s);
     default: return (int)hipErrorInvalidValue;
     }
 }
@@ -1014,15 +1031,14 @@ int enqueue_epoch(const DevNet &d, const BatchedPlan &P, uint32_t nsteps, hipStr
     if (e0) (void)hipEventRecord(e0, st);
     r |= launch_epoch_fused(d, nsteps, 0u, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, P.threads, P.solver_waves, st);
     if (e1) (void)hipEventRecord(e1, st);
-    r |= launch_expand(d, nsteps, st);
     return r;
 }
 
-int enqueue_epochs_multi(const DevNet &d, const BatchedPlan &P, uint32_t n_epochs, hipStream_t st, hipEvent_t e0,
-                         hipEvent_t e1) {
+int enqueue_resident(const DevNet &d, const BatchedPlan &P, uint32_t nsteps, hipStream_t st, hipEvent_t e0,
+                     hipEvent_t e1) {
     int r = 0;
     if (e0) (void)hipEventRecord(e0, st);
-    r |= launch_epoch_fused(d, d.K, n_epochs, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, P.threads, P.solver_waves,
+    r |= launch_epoch_fused(d, nsteps, 1u, P.d_blk, (uint32_t)P.blk.size() - 1, P.lds, P.threads, P.solver_waves,
                             st);
     if (e1) (void)hipEventRecord(e1, st);
     return r;
@@ -1119,7 +1135,7 @@ pa_status batched_setup(pa_sim *s) {
         if (tr.multi) {
             // a cooperative launch the device refuses (too many workgroups to
             // be resident) only rules this trial out
-            if (enqueue_epochs_multi(d, P, 4, st, nullptr, nullptr) != 0) {
+            if (enqueue_resident(d, P, 4 * d.K, st, nullptr, nullptr) != 0) {
                 (void)hipGetLastError();
                 (void)hipEventDestroy(a);
                 (void)hipEventDestroy(b);
@@ -1183,16 +1199,16 @@ void batched_plan_shape(pa_sim *s, uint32_t &threads, uint32_t &solver_waves, ui
     exchange = p ? (p->multi ? PA_EXCHANGE_RESIDENT : PA_EXCHANGE_KERNEL) : 0;
 }
 
-// Epochs one resident launch may run (0 when the plan exchanges spikes with
-// a separate kernel); bounded so that a launch stays well under a second.
-uint32_t batched_multi_epochs(pa_sim *s) {
+// Steps one resident launch may run (0 when the plan exchanges spikes
+// between launches); bounded so that a launch stays well under a second.
+uint32_t batched_resident_steps(pa_sim *s) {
     BatchedPlan *p = pa_plan(s);
-    return p && p->multi ? 256u : 0u;
+    return p && p->multi ? 256u * pa_devnet(s).K : 0u;
 }
 
-pa_status run_multi_batched(pa_sim *s, uint32_t n_epochs, hipEvent_t e0, hipEvent_t e1) {
+pa_status run_resident_batched(pa_sim *s, uint32_t nsteps, hipEvent_t e0, hipEvent_t e1) {
     const BatchedPlan &P = *pa_plan(s);
-    if (enqueue_epochs_multi(pa_devnet(s), P, n_epochs, pa_stream(s), e0, e1))
+    if (enqueue_resident(pa_devnet(s), P, nsteps, pa_stream(s), e0, e1))
         return pa_fail(s, PA_EDEVICE, "resident epoch launch");
     return PA_OK;
 }

@@ -4,8 +4,10 @@
 // synapses and connections of any network that fits its 288 GB).  Synapses
 // are stored sorted by (cell, CV, id) so that each CV's synapses and each
 // cell's synapses are contiguous; connections are stored as a table by
-// source cell.  Per cell, events wait in a ring of R slots indexed by
-// delivery step modulo R, each slot holding up to Q events.
+// target cell.  Every cell keeps its last H spikes in a ring; at the start
+// of an epoch each target cell gathers from its incoming connections the
+// events due in the epoch into a queue of its own, counted and sorted per
+// delivery step (no event is stored between epochs).
 #pragma once
 
 #include <cstddef>
@@ -23,20 +25,36 @@ struct Event {
 };
 static_assert(sizeof(Event) == 32, "event record is 32 bytes");
 
-// Error flags raised on the device, read back after every chunk of steps.
-enum : uint32_t { FLAG_OVERFLOW = 1u, FLAG_LATE = 2u, FLAG_NONFINITE = 4u, FLAG_BARRIER = 8u };
+// Error flags raised on the device, read back after every advance.
+//   QUEUE: a cell's events of one epoch exceeded its queue (possible only
+//     through device Poisson sources far above their rate's bound);
+//   LATE: an event due before the step of the spike that caused it;
+//   NONFINITE: a membrane voltage became non-finite;
+//   BARRIER: the grid barrier of the resident form gave up;
+//   HISTORY: the spike history of one advance overflowed.
+enum : uint32_t {
+    FLAG_QUEUE = 1u, FLAG_LATE = 2u, FLAG_NONFINITE = 4u, FLAG_BARRIER = 8u, FLAG_HISTORY = 16u
+};
 
 struct Counters {
     uint64_t step;      // first step of the current epoch (advanced by the epoch close)
-    uint32_t ep_n;      // spikes of the current epoch
+    uint32_t blocks_done;  // workgroups of a single-epoch launch that finished
     uint32_t flags;     // FLAG_*
-    uint64_t hist_n;    // spikes in the history buffer of the current chunk
+    uint64_t hist_n;    // spikes in the history buffer
     uint64_t events;    // events delivered
     uint32_t bad_cell;  // first cell that raised a flag
-    uint32_t blocks_done;  // workgroups of the exchange kernel that finished
-    uint32_t bar_count;    // grid barrier of the multi-epoch kernel: arrivals
-    uint32_t bar_gen;      // and generation
+    uint32_t pad;
 };
+
+// One entry of a cell's spike ring: the crossing time, and its step and
+// index in the cell's spike sequence (the index tells a reader whether the
+// entry already holds the spike it looks for).
+struct SpikeRec {
+    double t;
+    uint32_t step;
+    uint32_t idx;
+};
+static_assert(sizeof(SpikeRec) == 16, "spike record is 16 bytes");
 
 struct Stc {
     double tau_c, tau_h, tau_p, tau_z, gamma_p, gamma_d, theta_p, theta_d;
@@ -46,7 +64,8 @@ struct Stc {
 // Everything a kernel needs, passed by value.
 struct DevNet {
     uint32_t n_cells, n_cv, n_syn, n_hh, n_trains, n_probes;
-    uint32_t R, Q, K;
+    uint32_t K;          // steps per epoch
+    uint32_t H;          // spike ring entries per cell
     uint32_t mixed;      // gates, g and c stored in FP32
     double dt, theta;
     uint64_t seed;
@@ -101,11 +120,18 @@ struct DevNet {
     double *h, *z;
     unsigned long long *ev_cnt, *ev_sum;  // 2 per synapse
 
-    // connections by source
-    const uint64_t *out_off;     // n_cells + 1
-    const uint32_t *out_syn, *out_cell, *out_cid;
-    const uint8_t *out_ports;
-    const double *out_w, *out_d;
+    // incoming connections by target cell (in connection id order)
+    const uint64_t *in_off;      // n_cells + 1
+    const uint32_t *in_src, *in_syn, *in_cid;
+    const uint32_t *in_lag;      // steps back from an epoch's first step to the oldest spike that can matter
+    const uint8_t *in_ports;
+    const double *in_w, *in_d;
+
+    // spike rings: the last H spikes of each cell, entry k of cell c at
+    // c * H + k mod H; spk_n counts the cell's spikes, spk_last holds the
+    // step of its last spike plus one (0 before the first)
+    SpikeRec *spk;
+    uint32_t *spk_n, *spk_last;
 
     // trains
     const uint32_t *tr_syn, *tr_cell;
@@ -121,49 +147,57 @@ struct DevNet {
     const uint32_t *pois_syn, *pois_cell;
     const uint8_t *pois_ports;
     const double *pois_w, *pois_rate;
-    double *pois_t;              // next arrival time
-    uint64_t *pois_j;            // its index
+    const uint32_t *pois_cap;    // most arrivals per port a source may bring into one epoch
+    double *pois_t;              // 2 per source (conductance, calcium stream): next arrival time
+    uint64_t *pois_j;            // and its index
 
     // clamps, sorted by (CV, id)
     const double *cl_t0, *cl_dur, *cl_amp;
 
-    // event rings
-    uint32_t *ev_n;              // n_cells * R
+    // per-epoch event queues: cell c's events of the epoch in
+    // q_ev[q_off[c] .. q_off[c + 1]) (room for the most its incoming
+    // connections and sources can bring in one epoch); per (cell, step of
+    // the epoch) slot its count and offset into the cell's queue
+    const uint64_t *q_off;       // n_cells + 1
+    Event *q_ev;
+    uint32_t *ev_n, *ev_off;     // n_cells * K each (plain form)
     uint64_t *blk_done;          // n_cells: per workgroup, grid barriers passed (multi-epoch kernel)
     uint32_t *bar_grp;           // grid barrier: 32 group counters, top counter, release word (128 bytes apart)
-    Event *ev;                   // n_cells * R * Q
 
-    // spikes
-    uint32_t *ep_gid, *ep_step;  // capacity K * n_cells
-    double *ep_t;
+    // spike history of the present advance
     uint32_t *hist_gid;          // capacity hist_cap
     uint64_t *hist_step;
     double *hist_t;
     uint64_t hist_cap;
     Counters *ctr;
 
-    // probes
+    // probes: probe k samples after every pr_stride[k]-th step into its
+    // own region of pr_buf starting at pr_off[k]
     const int32_t *pr_what;
     const uint64_t *pr_idx;      // internal index (sorted synapse, CV, cell)
-    double *pr_buf;              // samples x n_probes
+    const uint32_t *pr_stride;
+    const uint64_t *pr_off;
+    double *pr_buf;
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return a HIP error
 // code (0 on success).
 int launch_init(const DevNet &d, void *stream);
-// The epoch kernels (inject, fused epoch, expand, close) take the epoch's
-// first step from Counters::step on the device, so that a captured graph
-// of epochs can be replayed; the close kernel advances it.
-int launch_inject(const DevNet &d, uint32_t nsteps, void *stream);
-int launch_step_plain(const DevNet &d, uint64_t n, void *stream, void *ev_begin, void *ev_end);
-int launch_expand(const DevNet &d, uint32_t nsteps, void *stream);
-int launch_probe(const DevNet &d, uint64_t row, void *stream);
-// Fused epoch: workgroup b owns cells blk[b] .. blk[b+1]-1; the first
+// Plain form: the events of the epoch [n0, n0 + nsteps) into the per-cell
+// queues, then one step.
+int launch_gather(const DevNet &d, uint64_t n0, uint32_t nsteps, void *stream);
+int launch_step_plain(const DevNet &d, uint64_t n, uint64_t n0, void *stream, void *ev_begin, void *ev_end);
+// Samples the probes due after step n (those whose stride divides n);
+// `first` is the first step of the present drain interval.
+int launch_probe(const DevNet &d, uint64_t n, uint64_t first, void *stream);
+// Fused epochs: workgroup b owns cells blk[b] .. blk[b+1]-1; the first
 // solver_waves wavefronts of a multi-wavefront workgroup share its cable
-// solves.  n_epochs = 0: one epoch of nsteps steps (the spike exchange is a
-// separate kernel); n_epochs > 0: n_epochs whole epochs in one cooperative
-// launch, the workgroups exchanging spikes themselves between epochs.
-int launch_epoch_fused(const DevNet &d, uint32_t nsteps, uint32_t n_epochs, const uint32_t *blk, uint32_t n_blocks,
+// solves.  resident = 0: one epoch of nsteps <= K steps, its first step
+// read from Counters::step (so that a captured graph of epochs can be
+// replayed) and advanced by the last workgroup; resident = 1: nsteps steps
+// in epochs of K (the last one shorter) in one cooperative launch, the
+// workgroups waiting for each other between epochs.
+int launch_epoch_fused(const DevNet &d, uint32_t nsteps, uint32_t resident, const uint32_t *blk, uint32_t n_blocks,
                        size_t lds_bytes, uint32_t block_threads, uint32_t solver_waves, void *stream);
 // Workgroups of the fused kernel that can be resident at once (0 if the
 // device does not support cooperative launches).
@@ -172,5 +206,9 @@ uint32_t epoch_fused_capacity(bool mixed, uint32_t block_threads, size_t lds_byt
 // written from the host).
 int launch_carried_sums(const DevNet &d, void *stream);
 int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream);
+// Copies n elements of a state array (words 64-bit words each, or FP32
+// widened to FP64) to dst, element q to position perm[q] (perm may be null).
+int launch_state_out(const void *src, uint32_t words, bool narrow, const uint32_t *perm, uint64_t n, void *dst,
+                     void *stream);
 
 }  // namespace pa

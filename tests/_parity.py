@@ -23,9 +23,13 @@ def run_pair(net, n_steps, chunks=1, **kw):
 
 
 def assert_raster_equal(o, s, t_rtol=1e-9):
+    """Equal rasters: both sides deliver them in (t*, gid) order; equal
+    counts, cells and crossing steps, t* within t_rtol."""
     og, ost, ot = o.spikes()
     sg, sst, stt = s.spikes()
     assert og.size == sg.size, f"spike count oracle {og.size} vs gpu {sg.size}"
+    if stt.size > 1:
+        assert np.all((np.diff(stt) > 0) | ((np.diff(stt) == 0) & (np.diff(sg) > 0))), "not in (t*, gid) order"
     np.testing.assert_array_equal(sg, og)
     np.testing.assert_array_equal(sst, ost)
     if ot.size:

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_function():
 
 def _sim(**over):
     lib = B.load_library()
-    cfg = B.pa_config(dt_ms=0.2, threshold_mV=-10.0, seed=1, precision=0, mode=0, probe_stride=1)
+    cfg = B.pa_config(dt_ms=0.2, threshold_mV=-10.0, seed=1, precision=0, mode=0, flags=0)
     for k, v in over.items():
         setattr(cfg, k, v)
     stc = B.stc_params(netgen.STC_TABLE5)
@@ -51,10 +51,10 @@ def test_create_validates_configuration():
     lib.pa_sim_destroy(h)
     lib.pa_sim_destroy(None)  # NULL-safe
     for bad in (dict(dt_ms=0.0), dict(dt_ms=float("nan")), dict(precision=7), dict(mode=3),
-                dict(probe_stride=0)):
+                dict(flags=1)):
         _, st, _ = _sim(**bad)
         assert st == B.PA_EINVAL, bad
-    assert lib.pa_status_str(B.PA_EOVERFLOW) == b"event slot overflow"
+    assert lib.pa_status_str(B.PA_EOVERFLOW) == b"event queue or spike history overflow"
 
 
 def _add_cells(lib, h, parent, mech=None):
@@ -112,7 +112,16 @@ def test_build_phase_validation():
                              off.ctypes.data, times.ctypes.data) == B.PA_OK
     what = np.array([3], np.int32)  # h of an exp-syn
     idx = np.array([1], np.uint64)
-    assert lib.pa_probes_add(h, 1, what.ctypes.data, idx.ctypes.data, None) == B.PA_EINVAL
+    stride = np.array([1], np.uint32)
+    assert lib.pa_probes_add(h, 1, what.ctypes.data, idx.ctypes.data, stride.ctypes.data, None) == B.PA_EINVAL
+    what = np.array([0], np.int32)  # V of CV 0, stride 0
+    idx = np.array([0], np.uint64)
+    stride = np.array([0], np.uint32)
+    assert lib.pa_probes_add(h, 1, what.ctypes.data, idx.ctypes.data, stride.ctypes.data, None) == B.PA_EINVAL
+    stride = np.array([7], np.uint32)
+    first = C.c_uint32()
+    assert lib.pa_probes_add(h, 1, what.ctypes.data, idx.ctypes.data, stride.ctypes.data, C.byref(first)) == B.PA_OK
+    assert first.value == 0
     assert lib.pa_advance(h, 1.0) == B.PA_ESTATE  # before finalize
     out = np.zeros(4)
     assert lib.pa_state_read(h, 0, out.ctypes.data, 4) == B.PA_ESTATE

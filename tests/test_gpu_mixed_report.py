@@ -22,6 +22,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 REPORT = {}
 
 
+def _by_step(sp):
+    g, st, t = sp
+    o = np.lexsort((g, st))
+    return g[o], st[o], t[o]
+
+
 def _compare(name, net, n_steps, chunk):
     print(f"[case] mixed report {name} {n_steps} steps", flush=True)
     o = oracle.Oracle(net)
@@ -34,8 +40,10 @@ def _compare(name, net, n_steps, chunk):
         s.advance_steps(m)
         done += m
         dv_max = max(dv_max, float(np.abs(s.read("V") - o.read("V")).max()))
-    og, ost, ot = o.spikes()
-    sg, sst, stt = s.spikes()
+    # matched in (step, gid) order: a crossing-time shift inside one step
+    # must not count as a divergence
+    og, ost, ot = _by_step(o.spikes())
+    sg, sst, stt = _by_step(s.spikes())
     n = min(og.size, sg.size)
     same = (og[:n] == sg[:n]) & (ost[:n] == sst[:n])
     first_div = int(np.argmin(same)) if not same.all() else n
@@ -85,3 +93,38 @@ def test_mixed_report_uneven_trees():
     rep = _compare("trees 4096 30 ms", netgen.config3(t_end=60.0), 150, 150)
     assert rep["max_spike_time_shift_ms"] < 0.2
     assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) < 0.1 * rep["spikes_fp64_oracle"] + 10
+
+
+def test_mixed_report_long_dendrites_one_second():
+    """The 2000 x 101 network over 1 s (5,000 steps) against the oracle's
+    raster stored by tests/golden/make_fixtures.py."""
+    p = os.path.join(ROOT, "tests", "golden", "oracle_ei2000x101_1s.npz")
+    if not os.path.exists(p):
+        pytest.skip("fixture not written (tests/golden/make_fixtures.py)")
+    fx = np.load(p)
+    net = netgen.config4(t_end=1000.0)
+    print("[case] mixed report E/I 2000x101 1 s", flush=True)
+    s = Simulation(net, mode="batched", precision="mixed")
+    s.advance_steps(int(fx["steps"]))
+    o_sp = (fx["gid"].astype(np.int64), fx["step"].astype(np.int64), fx["t"])
+    og, ost, ot = _by_step(o_sp)
+    sg, sst, stt = _by_step(s.spikes())
+    n = min(og.size, sg.size)
+    same = (og[:n] == sg[:n]) & (ost[:n] == sst[:n])
+    first_div = int(np.argmin(same)) if not same.all() else n
+    shift = np.abs(stt[:first_div] - ot[:first_div])
+    vs = s.read("V")[::int(fx["v_stride"])]
+    rep = dict(steps=int(fx["steps"]), t_ms=int(fx["steps"]) * net["dt"],
+               max_abs_dV_mV_at_end=float(np.abs(vs - fx["V"]).max()),
+               spikes_fp64_oracle=int(og.size), spikes_mixed=int(sg.size),
+               first_divergence_index=first_div,
+               first_divergence_ms=float(min(ost[first_div], sst[first_div]) * net["dt"]) if first_div < n else None,
+               max_spike_time_shift_ms=float(shift.max()) if shift.size else 0.0,
+               mean_spike_time_shift_ms=float(shift.mean()) if shift.size else 0.0)
+    REPORT["E/I 2000x101 1 s"] = rep
+    print(json.dumps({"E/I 2000x101 1 s": rep}), flush=True)
+    d = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(d):
+        with open(os.path.join(d, "mixed_report.json"), "w") as f:
+            json.dump(REPORT, f, indent=1)
+    assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) < 0.05 * rep["spikes_fp64_oracle"] + 10

@@ -88,10 +88,10 @@ def test_uneven_trees_full_size_short_horizon(mode):
 def test_heavy_input_matches_oracle(mode):
     """Several events per cell and step (20 kHz of external arrivals per
     cell): the epoch's events exceed the fused kernel's LDS event buffer, so
-    part of them are delivered from the ring in global memory."""
+    the workgroup's events are gathered into its queue in global memory."""
     net = netgen.tiny(seed=12, n_cells=9, t_end=60.0, ext_rate=20000.0, w_ext=0.0005)
     _say(f"heavy input mode={mode}")
-    o, s = run_pair(net, 300, chunks=2, mode=mode, slot_capacity=64)
+    o, s = run_pair(net, 300, chunks=2, mode=mode)
     assert_raster_equal(o, s)
     assert_routing_equal(o, s)
     assert_state_close(o, s)
@@ -133,6 +133,30 @@ def test_probes_sample_the_oracle_trajectory():
     got = s.probes()
     assert got.shape == (100, 7)
     np.testing.assert_allclose(got, np.array(rows), rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_probes_with_their_own_strides(mode):
+    """Each probe samples after every stride-th step of its own (1, 4, 7,
+    10), across advances that end between samples."""
+    net = netgen.tiny(seed=5, n_cells=7, t_end=100.0)
+    strides = [1, 4, 7, 10]
+    probes = [("V", 0, 1), ("V", int(net["cv_off"][3]) + 1, 4), ("p", 2, 7), ("V", 5, 10)]
+    _say(f"probe strides mode={mode}")
+    s = Simulation(net, mode=mode, probes=probes)
+    o = oracle.Oracle(net)
+    want = [[] for _ in probes]
+    for n in range(1, 141):
+        o.run(1)
+        for k, (q, i, st) in enumerate(probes):
+            if n % st == 0:
+                want[k].append(o.read(q)[i])
+    for m in (13, 50, 1, 76):
+        s.advance_steps(m)
+    for k, st in enumerate(strides):
+        got = s.probe(k)
+        assert got.size == 140 // st
+        np.testing.assert_allclose(got, np.array(want[k]), rtol=1e-9, atol=1e-12)
 
 
 def test_noise_path_matches_bitwise_generator():
@@ -345,16 +369,21 @@ def test_advance_time_grid_and_errors():
     assert s.stats()["steps"] == 100
 
 
-def test_slot_overflow_is_reported():
-    net = netgen.tiny(seed=4, n_cells=9, t_end=100.0, ext_rate=2000.0)
-    _say("overflow tiny seed=4 slot_capacity=1")
-    s = Simulation(net, slot_capacity=1)
-    with pytest.raises(PAError) as e:
-        s.advance_steps(500)
-    assert e.value.status == B.PA_EOVERFLOW
-    with pytest.raises(PAError) as e:
-        s.advance_steps(1)      # refuses after a failure
-    assert e.value.status == B.PA_ESTATE
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_synchronous_burst_matches_oracle(mode):
+    """All 160 cells of an all-to-all network fire in the same step (one
+    suprathreshold clamp pulse on every soma), so each cell receives 159
+    conductance and 159 calcium events in one step, and again t_c,delay
+    later: far beyond a fixed per-step slot; the per-epoch queues hold them
+    and the deliveries match the oracle."""
+    net = netgen.burst_network(n_cells=160, t_end=60.0)
+    _say(f"synchronous burst mode={mode}")
+    o, s = run_pair(net, 300, chunks=2, mode=mode)
+    assert assert_raster_equal(o, s) >= 160
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+    cnt, _ = s.event_stats()
+    assert cnt.sum() >= 160 * 159 * 2
 
 
 def test_non_finite_voltage_is_reported():
@@ -392,3 +421,107 @@ def test_mixed_precision_stays_close_over_short_horizon():
         no, ns = o.spikes()[0].size, s.spikes()[0].size
         assert abs(ns - no) <= 0.25 * no + 2, (no, ns)
         assert np.all(np.isfinite(s.read("V")))
+
+
+# ------------------------------------------------- full-size plastic dynamics
+def _seed_plastic_state(net, sims, seed=9):
+    """The same non-trivial plastic state on every side: h over [h0 - 2.5,
+    h0 + 2.5] (tags of both signs), z over [-0.4, 0.9], p over [0, 8] and c
+    over [0, 5] (both calcium thresholds crossed) on every plastic synapse."""
+    rng = np.random.default_rng(seed)
+    kinds = net["syn_kind"] == 1
+    n, nc = len(kinds), int(net["n_cells"])
+    h0 = net["stc"]["h0"]
+    h = np.where(kinds, rng.uniform(h0 - 2.5, h0 + 2.5, n), h0)
+    z = np.where(kinds, rng.uniform(-0.4, 0.9, n), 0.0)
+    c = np.where(kinds, rng.uniform(0.0, 5.0, n), 0.0)
+    p = rng.uniform(0.0, 8.0, nc)
+    for x in sims:
+        x.write("h", h)
+        x.write("z", z)
+        x.write("c", c)
+        x.write("p", p)
+    return h, z
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_ei_network_learning_stimulus_full_size(mode):
+    """The 2000-cell E/I network with a learning stimulus on an assembly of
+    150 excitatory cells (a somatic current step from 2 ms) and a seeded
+    plastic state (tags of both signs, protein, calcium over both
+    thresholds), 120 ms at full size: the conductance-port weight of Eq. 16
+    with h != h0 and z != 0, the early phase (Eqs. 17-18) on both threshold
+    branches with its noise, the late phase (Eq. 20) and the protein (Eq.
+    21) all move, and match the oracle."""
+    net = netgen.config2(t_end=200.0, stim_n=150, stim_t0=2.0, stim_dur=150.0, stim_amp=0.4)
+    _say(f"config2 learning stimulus 600 steps mode={mode}")
+    o = oracle.Oracle(net)
+    s = Simulation(net, mode=mode)
+    h_init, z_init = _seed_plastic_state(net, (o, s))
+    for _ in range(3):
+        o.run(200)
+        s.advance_steps(200)
+    assert assert_raster_equal(o, s) > 1000
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+    kinds = net["syn_kind"] == 1
+    ho, zo, po = o.read("h"), o.read("z"), o.read("p")
+    assert np.abs(ho - h_init)[kinds].max() > 0.05      # h moved
+    assert np.abs(zo - z_init)[kinds].max() > 1e-6      # z moved
+    assert po.max() > 0.0
+
+
+@pytest.fixture(scope="module")
+def large_network_oracle():
+    """Config-5 network (1e5 trees of 10-60 CVs, 1e7 plastic synapses, device
+    Poisson drive), oracle over 60 steps; computed once for both forms."""
+    net = netgen.config5(t_end=20.0)
+    _say("config5 oracle 60 steps")
+    o = oracle.Oracle(net)
+    o.run(60)
+    return net, o
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_large_network_full_size_short_horizon(mode, large_network_oracle):
+    """1e5 random trees, in-degree 100 through both ports, delays 1-5 ms
+    (epochs of 4 steps), device-drawn Poisson input: 12 ms at full size,
+    through the start-up burst in which every cell fires."""
+    net, o = large_network_oracle
+    _say(f"config5 full size 60 steps mode={mode}")
+    s = Simulation(net, mode=mode)
+    s.advance_steps(25)
+    s.advance_steps(35)
+    assert assert_raster_equal(o, s) > 1000
+    assert_routing_equal(o, s)
+    assert_state_close(o, s)
+
+
+def _fixture(name):
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"oracle_{name}.npz")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not written (tests/golden/make_fixtures.py)")
+    return np.load(p)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_ei_network_full_horizon_raster(mode):
+    """The 2000-cell E/I network over its full 10 s (50,000 steps) against
+    the oracle's raster stored by tests/golden/make_fixtures.py: equal
+    spikes (count, cells, steps), t* within 1e-9, V and p at the end to the
+    FP64 bar, h of every 97th synapse."""
+    fx = _fixture("ei2000x21_10s")
+    net = netgen.config2(t_end=10000.0)
+    _say(f"config2 10 s mode={mode}")
+    s = Simulation(net, mode=mode)
+    for _ in range(5):
+        s.advance_steps(10000)
+    g, st, t = s.spikes()
+    assert g.size == fx["gid"].size, (g.size, fx["gid"].size)
+    np.testing.assert_array_equal(g, fx["gid"].astype(np.int64))
+    np.testing.assert_array_equal(st, fx["step"].astype(np.int64))
+    np.testing.assert_allclose(t, fx["t"], rtol=1e-9, atol=0)
+    assert_v_close(fx["V"], s.read("V")[::int(fx["v_stride"])])
+    np.testing.assert_allclose(s.read("p"), fx["p"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(s.read("h")[::int(fx["h_stride"])], fx["h"], rtol=1e-9, atol=1e-10)

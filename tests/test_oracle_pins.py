@@ -767,3 +767,16 @@ def test_hh_soma_rests_at_the_root_of_the_steady_state_current():
     o = oracle.Oracle(_net(b, dt=0.2))
     o.run(20000)  # 4 s
     assert abs(o.read("V")[0] - root) < 1e-6
+
+
+def test_threaded_oracle_build_gives_the_same_bits():
+    """The OpenMP build (timing on several host cores) computes every value
+    by the same expressions in the same order: identical raster and state."""
+    net = netgen.tiny(seed=3, n_cells=13, t_end=100.0)
+    a, b = oracle.Oracle(net), oracle.Oracle(net, threaded=True)
+    a.run(400)
+    b.run(400)
+    for x, y in zip(a.spikes(), b.spikes()):
+        np.testing.assert_array_equal(x, y)
+    for k in ("V", "m", "hh", "n", "g", "c", "h", "z", "p"):
+        np.testing.assert_array_equal(a.read(k), b.read(k), err_msg=k)
