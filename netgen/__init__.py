@@ -24,6 +24,9 @@ Network dictionary (all arrays are numpy, C-contiguous):
   poisson    pois_dst, pois_ports, pois_w, pois_rate[Hz]: sources whose
              arrivals are drawn by the simulator from the network's seed
   scalars    dt, theta (detector threshold mV), seed, t_end, name, stc{...}
+  diffusion  optional {d_sps, d_prp} (um^2/ms): the signal triggering
+             protein synthesis and the protein diffuse over each cell's CVs
+             instead of the per-cell sum of the plasticity rule
 
 Units: ms, mV, um, nA, uS, nF.  The seed recipe (one master seed, split into
 independent substreams for morphology, placement, connectivity, delays and
@@ -363,6 +366,96 @@ def _ei_network(name, n_dend, seed, t_end, n_e=1600, n_i=400, p=0.1, delay=3.0,
     stc.update(CA_INVIVO)
     net = b.finish(name, 0.2, t_end, seed, stc)
     net["ext_rate_hz"] = n_ext * ext_rate
+    return net
+
+
+def with_diffusion(net, d_sps=1e-2, d_prp=1e-2):
+    """The same network with SPS / PRP particle diffusion over every cell
+    (diffusivities in um^2/ms; 1e-11 m^2/s = 1e-2 um^2/ms)."""
+    out = dict(net)
+    out["diffusion"] = dict(d_sps=float(d_sps), d_prp=float(d_prp))
+    out["name"] = net["name"] + "-diffusion"
+    return out
+
+
+# Morphologies of the multi-compartment network (Table 6): compartments of
+# 1 um, one radius for soma and dendrites, the soma two cylinders with a
+# one-compartment middle (protein synthesis, detector), an apical dendrite
+# on one end and a basal dendrite on the other.
+TABLE6 = dict(small_cell=dict(r=6.0, l_soma=12.0), large_cell=dict(r=12.0, l_soma=24.0),
+              small_dendrites=dict(l_apical=12.5, l_basal=5.0),
+              large_dendrites=dict(l_apical=25.0, l_basal=10.0))
+
+
+def stc_neuron(cell="small", dendrites="small", dl=1.0):
+    """(parent, length, diam, mech, apical tip, basal tip) of one neuron:
+    CV 0 the middle soma compartment, then one soma half and the apical
+    dendrite, then the other half and the basal dendrite (depth-first,
+    parent < child); HH on the soma, passive dendrites.  Small cells with
+    small dendrites have 31 CVs, with large dendrites 48."""
+    c = TABLE6[f"{cell}_cell"]
+    d = TABLE6[f"{dendrites}_dendrites"]
+    half = int(round((c["l_soma"] / 2) / dl))
+    parent, length, mech = [-1], [dl], [MECH_HH]
+
+    def chain(start, n, L, m):
+        p = start
+        for _ in range(n):
+            parent.append(p)
+            length.append(L / n)
+            mech.append(m)
+            p = len(parent) - 1
+        return p
+
+    end_a = chain(0, half, half * dl, MECH_HH)
+    apical = chain(end_a, int(np.ceil(d["l_apical"] / dl)), d["l_apical"], MECH_PAS)
+    end_b = chain(0, half, half * dl, MECH_HH)
+    basal = chain(end_b, int(np.ceil(d["l_basal"] / dl)), d["l_basal"], MECH_PAS)
+    n = len(parent)
+    return (np.asarray(parent, np.int32), np.asarray(length), np.full(n, 2.0 * c["r"]),
+            np.asarray(mech, np.uint8), apical, basal)
+
+
+def stc_morpho_network(seed=6, t_end=10000.0, cell="small", dendrites="small", d_sps=1e-2, d_prp=1e-2,
+                       n_e=1600, n_i=400, p=0.1, delay=3.0, w_ee=0.0004, w_ei=0.0005, w_ie=0.02,
+                       w_ii=0.01, w_ext=0.0006, n_ext=25, ext_rate=5.0, stim_n=0, stim_rate=0.0,
+                       stim_t0=0.0, stim_dur=0.0):
+    """E/I network of the multi-compartment neurons of Table 6 (Sec. 3.6):
+    external input on the apical tip, recurrent excitation on the basal tip
+    (plastic E->E through both ports), inhibition on the soma; SPS / PRP
+    diffusion with the given diffusivities (um^2/ms)."""
+    rng_c, rng_t, rng_s = _streams(seed, 3)
+    n = n_e + n_i
+    parent, length, diam, mech, apical, basal = stc_neuron(cell, dendrites)
+    b = _Builder()
+    for _ in range(n):
+        b.add_cell(parent, length, diam, mech, detector=0)
+    ext_syn = [b.add_syn(c, apical, KIND_EXPSYN, 5.0, 0.0) for c in range(n)]
+    conn_src, conn_dst, conn_ports, conn_w = [], [], [], []
+    for tgt in range(n):
+        src = np.nonzero(rng_c.random(n) < p)[0]
+        src = src[src != tgt]
+        for s_ in src[src < n_e]:
+            plastic = tgt < n_e
+            sid = b.add_syn(tgt, basal, KIND_STC if plastic else KIND_EXPSYN, 5.0, 0.0)
+            conn_src.append(s_); conn_dst.append(sid)
+            conn_ports.append(PORT_G | PORT_CA if plastic else PORT_G)
+            conn_w.append(w_ee if plastic else w_ei)
+        for s_ in src[src >= n_e]:
+            sid = b.add_syn(tgt, 0, KIND_EXPSYN, 5.0, -80.0)
+            conn_src.append(s_); conn_dst.append(sid)
+            conn_ports.append(PORT_G); conn_w.append(w_ie if tgt < n_e else w_ii)
+    b.add_conns(conn_src, conn_dst, conn_ports, conn_w, delay)
+    for c in range(n):
+        times = _merge_trains(rng_t, n_ext, ext_rate, t_end)
+        if c < stim_n:
+            extra = stim_t0 + poisson_times(rng_s, stim_rate, min(stim_dur, t_end - stim_t0))
+            times = np.concatenate([times, extra])
+        b.add_train(ext_syn[c], PORT_G, w_ext, times)
+    stc = dict(STC_TABLE5)
+    stc.update(CA_INVIVO)
+    net = b.finish(f"ei-stc-morpho-{cell}-{dendrites}", 0.2, t_end, seed, stc)
+    net["diffusion"] = dict(d_sps=float(d_sps), d_prp=float(d_prp))
     return net
 
 

@@ -62,7 +62,8 @@ class _Net(C.Structure):
          ("train_off", _P), ("train_times", _P),
          ("n_clamps", _I64), ("clamp_cell", _P), ("clamp_cv", _P), ("clamp_t0", _P),
          ("clamp_dur", _P), ("clamp_amp", _P),
-         ("n_pois", _I64), ("pois_dst", _P), ("pois_ports", _P), ("pois_w", _P), ("pois_rate", _P)]
+         ("n_pois", _I64), ("pois_dst", _P), ("pois_ports", _P), ("pois_w", _P), ("pois_rate", _P),
+         ("prp_model", _I64), ("d_sps", _D), ("d_prp", _D)]
 
 
 _libs = {}
@@ -101,7 +102,7 @@ def _load(threaded: bool = False):
     return _libs[path]
 
 
-_READ = {"V": 0, "m": 1, "hh": 2, "n": 3, "g": 4, "c": 5, "h": 6, "z": 7, "p": 8}
+_READ = {"V": 0, "m": 1, "hh": 2, "n": 3, "g": 4, "c": 5, "h": 6, "z": 7, "p": 8, "sps": 11, "prp": 12}
 
 _ARRAYS = {
     "cv_off": np.int64, "parent": np.int32, "length": np.float64, "diam": np.float64,
@@ -142,6 +143,10 @@ class Oracle:
         s.n_trains = len(self._keep["train_dst"])
         s.n_clamps = len(self._keep["clamp_cell"])
         s.n_pois = len(self._keep["pois_dst"])
+        dif = net.get("diffusion")
+        s.prp_model = 1 if dif else 0
+        s.d_sps = float(dif["d_sps"]) if dif else 0.0
+        s.d_prp = float(dif["d_prp"]) if dif else 0.0
         self._s = s
         err = C.create_string_buffer(256)
         h = lib.orc_create(C.byref(s), err, 256)
@@ -182,8 +187,8 @@ class Oracle:
         return gid, step, t
 
     def _size(self, what):
-        return {0: self.n_cv, 1: self.n_hh, 2: self.n_hh, 3: self.n_hh, 8: self.n_cells}.get(
-            what, self.n_syn)
+        return {0: self.n_cv, 1: self.n_hh, 2: self.n_hh, 3: self.n_hh, 8: self.n_cells, 11: self.n_cv,
+                12: self.n_cv}.get(what, self.n_syn)
 
     def read(self, what: str) -> np.ndarray:
         code = _READ[what]

@@ -27,6 +27,13 @@
  *  6. plasticity (Eqs. 17, 18, 20, 21): per cell S = sum |h - h0| over its
  *     tagging synapses from step-start h; Euler-Maruyama step of h (Sec. 2.3)
  *     with Threefry-4x64-12 + Box-Muller noise; z; calcium decay; then p,
+ *     With particle diffusion switched on (prp_model 1, Sec. 2.4 Eq. 5 and
+ *     Sec. 3.6 Eq. 23) the per-cell sum and p are replaced by two species
+ *     diffusing over the cell's CVs: a signal triggering protein synthesis
+ *     (SPS), released at each synapse's CV by the change of |h - h0|, and
+ *     the protein (PRP), synthesised at the soma while the SPS
+ *     concentration there exceeds theta_pro / V_tot and decaying everywhere;
+ *     z then takes the PRP concentration of its synapse's CV.
  *  7. threshold detection V^n < theta <= V^{n+1}, linear interpolation of
  *     the crossing time, and one queued event per outgoing connection and
  *     port (delay d, calcium port a further t_c,delay later), delivered at
@@ -89,6 +96,11 @@ typedef struct {
     const int32_t *pois_dst;
     const uint8_t *pois_ports;
     const double *pois_w, *pois_rate;
+
+    /* protein model: 0 the per-cell sum of Eq. 21; 1 SPS / PRP diffusion
+       (Eq. 5) with diffusivities in um^2/ms */
+    int64_t prp_model;
+    double d_sps, d_prp;
 } orc_net;
 
 /* ------------------------------------------------------------ event heap */
@@ -246,6 +258,12 @@ typedef struct {
     double *p, *S;
     uint8_t *post;
     int64_t *out_off, *out_conn; /* outgoing connections per cell */
+    /* particle diffusion: CV volume (um^3), the geometric factor of the
+       flux between a CV and its parent (um), species concentrations, the
+       soma CV and total volume of each cell, per-synapse change of
+       |h - h0| in the step, per-CV release, elimination scratch */
+    double *vol, *dgeo, *sps, *prp, *dlt, *src, *Dx, *bx, *vtot;
+    int64_t *soma;
     /* Poisson sources: next arrival time and its index */
     double *pois_t;
     int64_t *pois_j;
@@ -285,6 +303,11 @@ orc *orc_create(const orc_net *net, char *err, int errlen) {
     o->cdt = xcalloc(ncv, 8); o->gpas = xcalloc(ncv, 8); o->gpas_e = xcalloc(ncv, 8);
     o->axial = xcalloc(ncv, 8); o->d0 = xcalloc(ncv, 8); o->scale = xcalloc(ncv, 8);
     o->gparent = xcalloc(ncv, 8); o->hh_of = xcalloc(ncv, 8); o->cv_cell = xcalloc(ncv, 8);
+    o->vol = xcalloc(ncv, 8); o->dgeo = xcalloc(ncv, 8); o->sps = xcalloc(ncv, 8); o->prp = xcalloc(ncv, 8);
+    o->src = xcalloc(ncv, 8); o->Dx = xcalloc(ncv, 8); o->bx = xcalloc(ncv, 8);
+    o->vtot = xcalloc(nc, 8); o->soma = xcalloc(nc, 8);
+    if (N->prp_model != 0 && N->prp_model != 1) FAIL("prp_model must be 0 or 1");
+    if (N->prp_model == 1 && !(N->d_sps >= 0 && N->d_prp >= 0)) FAIL("diffusivities must be >= 0");
     const double pi = 3.14159265358979323846;
     int64_t nhh = 0;
     for (int64_t c = 0; c < nc; c++) {
@@ -320,7 +343,16 @@ orc *orc_create(const orc_net *net, char *err, int errlen) {
             /* series resistance of the two half-cylinders between the nodes */
             double rsum = N->length[i] / (2.0 * pi * ri * ri) + N->length[k] / (2.0 * pi * rk * rk);
             o->axial[i] = 1e2 / (P[1] * rsum);                     /* uS */
+            /* the same half-cylinder series form for a diffusive flux:
+               cross-section over length, summed as resistances */
+            o->dgeo[i] = 1.0 / rsum;                                /* um */
         }
+        for (int64_t i = b0; i < b1; i++) {
+            double r = 0.5 * N->diam[i];
+            o->vol[i] = pi * r * r * N->length[i];                  /* um^3 */
+            o->vtot[c] += o->vol[i];
+        }
+        o->soma[c] = b0 + N->detector[c];
     }
     /* diagonal invariant: C/dt + g_pas + (own axial + children's axial) */
     double *axsum = xcalloc(ncv, 8);
@@ -342,7 +374,7 @@ orc *orc_create(const orc_net *net, char *err, int errlen) {
     /* synapses */
     int64_t ns = N->n_syn;
     o->g = xcalloc(ns, 8); o->c = xcalloc(ns, 8); o->h = xcalloc(ns, 8); o->z = xcalloc(ns, 8);
-    o->decay = xcalloc(ns, 8);
+    o->decay = xcalloc(ns, 8); o->dlt = xcalloc(ns, 8);
     o->ev_count = xcalloc(2 * ns, 8); o->ev_stepsum = xcalloc(2 * ns, 8);
     int64_t *pairs = xcalloc(2 * ns, 8);
     for (int64_t s = 0; s < ns; s++) {
@@ -468,6 +500,34 @@ static void currents(orc *o, double tn) {
     }
 }
 
+/* One backward-Euler step of the diffusion equation (Eq. 5) of one species
+ * over the CVs b0..b1-1 of a cell, in amounts: (V_i + dt sum_j a_ij) X_i -
+ * dt sum_j a_ij X_j = bx_i, a_ij = D x (cross-section / length) of the
+ * CV-parent pair, sealed ends; solved by the same elimination as the cable
+ * system.  bx holds the right-hand side on entry; X receives the
+ * concentrations. */
+static void diffuse_cell(orc *o, int64_t b0, int64_t b1, double dcoef, double *X) {
+    const double dt = o->net.dt;
+    for (int64_t i = b0; i < b1; i++) o->Dx[i] = o->vol[i];
+    for (int64_t i = b0 + 1; i < b1; i++) {
+        double a = dt * (dcoef * o->dgeo[i]);
+        o->Dx[i] += a;
+        o->Dx[o->gparent[i]] += a;
+    }
+    for (int64_t i = b1 - 1; i > b0; i--) {
+        int64_t p = o->gparent[i];
+        double u = -(dt * (dcoef * o->dgeo[i]));
+        double f = u / o->Dx[i];
+        o->Dx[p] -= f * u;
+        o->bx[p] -= f * o->bx[i];
+    }
+    X[b0] = o->bx[b0] / o->Dx[b0];
+    for (int64_t i = b0 + 1; i < b1; i++) {
+        double u = -(dt * (dcoef * o->dgeo[i]));
+        X[i] = (o->bx[i] - u * X[o->gparent[i]]) / o->Dx[i];
+    }
+}
+
 /* One step n -> n+1.  Returns 0, or -1 with a message. */
 static int orc_step(orc *o) {
     const orc_net *N = &o->net;
@@ -557,22 +617,33 @@ static int orc_step(orc *o) {
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N->n_syn; s++) o->g[s] *= o->decay[s];
 
-    /* 6. plasticity: S from step-start h; h, z from step-start h, z, p, c */
+    /* 6. plasticity: S from step-start h; h, z from step-start h, z, p, c.
+       With particle diffusion the trigger is the step-start SPS
+       concentration at the soma against theta_pro / V_tot (Eq. 23), and z
+       takes the step-start PRP concentration of its synapse's CV. */
+    const int diffuse = N->prp_model == 1;
+    if (!diffuse) {
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t cell = 0; cell < nc; cell++) {
-        double S = 0.0;
-        for (int64_t i = N->cv_off[cell]; i < N->cv_off[cell + 1]; i++)
-            for (int64_t q = o->cv_syn_off[i]; q < o->cv_syn_off[i + 1]; q++) {
-                int64_t s = o->syn_order[q];
-                if (N->syn_kind[s] == 1) S += fabs(o->h[s] - h0);
-            }
-        o->S[cell] = S;
+        for (int64_t cell = 0; cell < nc; cell++) {
+            double S = 0.0;
+            for (int64_t i = N->cv_off[cell]; i < N->cv_off[cell + 1]; i++)
+                for (int64_t q = o->cv_syn_off[i]; q < o->cv_syn_off[i + 1]; q++) {
+                    int64_t s = o->syn_order[q];
+                    if (N->syn_kind[s] == 1) S += fabs(o->h[s] - h0);
+                }
+            o->S[cell] = S;
+        }
+    } else {
+        for (int64_t cell = 0; cell < nc; cell++)
+            o->S[cell] = (o->sps[o->soma[cell]] - N->theta_pro / o->vtot[cell] > 0.0) ? 1.0 : 0.0;
     }
     const double ah = dt / N->tau_h, az = dt / N->tau_z;
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N->n_syn; s++) {
         if (N->syn_kind[s] != 1) continue;
-        double c = o->c[s], h = o->h[s], z = o->z[s], p = o->p[N->syn_cell[s]];
+        int32_t cell = N->syn_cell[s];
+        double c = o->c[s], h = o->h[s], z = o->z[s];
+        double p = diffuse ? o->prp[N->cv_off[cell] + N->syn_cv[s]] : o->p[cell];
         double thp = (c - N->theta_p > 0.0) ? 1.0 : 0.0;
         double thd = (c - N->theta_d > 0.0) ? 1.0 : 0.0;
         double drift = 0.1 * (h0 - h) + N->gamma_p * (10.0 - h) * thp - N->gamma_d * h * thd;
@@ -582,15 +653,43 @@ static int orc_step(orc *o) {
         double tagp = ((h - h0) - N->theta_tag > 0.0) ? 1.0 : 0.0;
         double tagd = ((h0 - h) - N->theta_tag > 0.0) ? 1.0 : 0.0;
         double zn = z + az * p * N->f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
+        o->dlt[s] = fabs(hn - h0) - fabs(h - h0);
         o->h[s] = hn;
         o->z[s] = zn;
         o->c[s] = c * o->r_c;
     }
     const double ap = dt / N->tau_p;
+    if (!diffuse) {
 #pragma omp parallel for schedule(static)
-    for (int64_t cell = 0; cell < nc; cell++) {
-        double trig = (o->S[cell] - N->theta_pro > 0.0) ? 1.0 : 0.0;
-        o->p[cell] = o->p[cell] + ap * (-o->p[cell] + N->p_max * trig);
+        for (int64_t cell = 0; cell < nc; cell++) {
+            double trig = (o->S[cell] - N->theta_pro > 0.0) ? 1.0 : 0.0;
+            o->p[cell] = o->p[cell] + ap * (-o->p[cell] + N->p_max * trig);
+        }
+    } else {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t cell = 0; cell < nc; cell++) {
+            int64_t b0 = N->cv_off[cell], b1 = N->cv_off[cell + 1];
+            /* SPS released in the step per CV: the change of |h - h0| of its
+               plastic synapses, in (CV, id) order */
+            for (int64_t i = b0; i < b1; i++) {
+                double r = 0.0;
+                for (int64_t q = o->cv_syn_off[i]; q < o->cv_syn_off[i + 1]; q++) {
+                    int64_t s = o->syn_order[q];
+                    if (N->syn_kind[s] == 1) r += o->dlt[s];
+                }
+                o->src[i] = r;
+            }
+            for (int64_t i = b0; i < b1; i++) o->bx[i] = o->vol[i] * o->sps[i] + o->src[i];
+            diffuse_cell(o, b0, b1, N->d_sps, o->sps);
+            /* PRP: decay in every CV; synthesis at the soma while triggered,
+               scaled so that the well-mixed cell follows Eq. 21 */
+            for (int64_t i = b0; i < b1; i++) {
+                double x = o->prp[i];
+                o->bx[i] = o->vol[i] * (x + ap * (-x));
+            }
+            o->bx[o->soma[cell]] += ap * (N->p_max * o->vtot[cell]) * o->S[cell];
+            diffuse_cell(o, b0, b1, N->d_prp, o->prp);
+        }
     }
 
     /* 7. threshold detection and event generation */
@@ -642,7 +741,8 @@ void orc_spikes(const orc *o, int64_t *gid, int64_t *step, double *t) {
 }
 
 /* what: 0 V, 1 m, 2 h(HH), 3 n, 4 g, 5 c, 6 h(weight), 7 z, 8 p,
- *       9 delivered-event counts (2 per synapse), 10 step sums (2 per synapse) */
+ *       9 delivered-event counts (2 per synapse), 10 step sums (2 per synapse),
+ *       11 SPS concentration, 12 PRP concentration (per CV) */
 int orc_read(const orc *o, int what, void *out) {
     const orc_net *N = &o->net;
     size_t nh = (size_t)o->n_hh, ns = (size_t)N->n_syn;
@@ -658,11 +758,13 @@ int orc_read(const orc *o, int what, void *out) {
     case 8: memcpy(out, o->p, (size_t)N->n_cells * 8); return 0;
     case 9: memcpy(out, o->ev_count, 2 * ns * 8); return 0;
     case 10: memcpy(out, o->ev_stepsum, 2 * ns * 8); return 0;
+    case 11: memcpy(out, o->sps, (size_t)o->n_cv * 8); return 0;
+    case 12: memcpy(out, o->prp, (size_t)o->n_cv * 8); return 0;
     default: return -1;
     }
 }
 
-/* Test hooks: overwrite a state array (same codes as orc_read, 0-8). */
+/* Test hooks: overwrite a state array (same codes as orc_read, 0-8, 11, 12). */
 int orc_write(orc *o, int what, const double *in) {
     const orc_net *N = &o->net;
     size_t nh = (size_t)o->n_hh, ns = (size_t)N->n_syn;
@@ -676,6 +778,8 @@ int orc_write(orc *o, int what, const double *in) {
     case 6: memcpy(o->h, in, ns * 8); return 0;
     case 7: memcpy(o->z, in, ns * 8); return 0;
     case 8: memcpy(o->p, in, (size_t)N->n_cells * 8); return 0;
+    case 11: memcpy(o->sps, in, (size_t)o->n_cv * 8); return 0;
+    case 12: memcpy(o->prp, in, (size_t)o->n_cv * 8); return 0;
     default: return -1;
     }
 }
@@ -713,7 +817,8 @@ void orc_destroy(orc *o) {
     void *ptrs[] = {o->V, o->Vold, o->I, o->G, o->D, o->b, o->cdt, o->gpas, o->gpas_e, o->axial,
                     o->d0, o->scale, o->gparent, o->hh_of, o->cv_cell, o->gm, o->gh, o->gn, o->g, o->c, o->h,
                     o->z, o->decay, o->syn_order, o->cv_syn_off, o->ev_count, o->ev_stepsum, o->p,
-                    o->S, o->post, o->out_off, o->out_conn, o->sp_gid, o->sp_step, o->sp_t, o->q.v,
+                    o->S, o->post, o->vol, o->dgeo, o->sps, o->prp, o->dlt, o->src, o->Dx, o->bx,
+                    o->vtot, o->soma, o->out_off, o->out_conn, o->sp_gid, o->sp_step, o->sp_t, o->q.v,
                     o->pois_t, o->pois_j};
     for (size_t k = 0; k < sizeof ptrs / sizeof ptrs[0]; k++) free(ptrs[k]);
     free(o);
