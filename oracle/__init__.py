@@ -79,6 +79,8 @@ def _load(threaded: bool = False):
         lib.orc_create.argtypes = [C.POINTER(_Net), C.c_char_p, C.c_int]
         lib.orc_run.restype = C.c_int
         lib.orc_run.argtypes = [_P, _I64]
+        lib.orc_fast_forward.restype = C.c_int
+        lib.orc_fast_forward.argtypes = [_P, _I64, _D]
         lib.orc_error.restype = C.c_char_p
         lib.orc_error.argtypes = [_P]
         for f in ("orc_step_count", "orc_n_cv", "orc_n_hh", "orc_spike_count"):
@@ -172,6 +174,12 @@ class Oracle:
 
     def run(self, n_steps: int) -> None:
         if self._lib.orc_run(self._h, int(n_steps)) != 0:
+            raise OracleError(self._lib.orc_error(self._h).decode())
+
+    def fast_forward(self, n_long: int, dt_long: float) -> None:
+        """n_long long steps of the slow plasticity variables only (spiking
+        and calcium off); time moves by n_long * dt_long."""
+        if self._lib.orc_fast_forward(self._h, int(n_long), float(dt_long)) != 0:
             raise OracleError(self._lib.orc_error(self._h).decode())
 
     def spikes(self):

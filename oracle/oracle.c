@@ -724,6 +724,92 @@ static int orc_step(orc *o) {
     return 0;
 }
 
+/* Fast-forward (Sec. 3.5, the phases of slow network dynamics in the 8-h
+ * paradigm): n_long steps of length dt_long (a whole multiple of dt) that
+ * advance only the slow plasticity variables, with spiking and calcium
+ * dynamics off.  Per long step, from step-start values and with the
+ * calcium thresholds not crossed (no early-phase drive, no noise):
+ *   h <- h + (dt_long / tau_h) 0.1 (h0 - h)                     (Eq. 17)
+ *   z <- z + (dt_long / tau_z) p f_int [(1 - z) tag+ - (z + 0.5) tag-]  (Eq. 20)
+ *   p <- p + (dt_long / tau_p) (-p + p_max [S - theta_pro > 0])       (Eq. 21)
+ * with S = sum |h - h0| over the cell's plastic synapses (step-start h);
+ * calcium and synaptic conductances decay exactly over each long step;
+ * membrane voltages and gates stay as they are.  Everything in flight is
+ * dropped: spikes before the new time cause no events, post-synaptic flags
+ * clear, explicit train arrivals before the new time are skipped, and a
+ * Poisson source whose next arrival falls before it draws that arrival
+ * again (index + 1) as the new time plus an interval (the process is
+ * memoryless).  Time moves to t + n_long dt_long.  The per-cell protein
+ * model only.  Returns 0, or -1 with a message. */
+int orc_fast_forward(orc *o, int64_t n_long, double dt_long) {
+    const orc_net *N = &o->net;
+    const int64_t nc = N->n_cells;
+    const double dt = N->dt, h0 = N->h0;
+    if (N->prp_model != 0) { snprintf(o->err, sizeof o->err, "fast-forward needs the per-cell protein model"); return -1; }
+    double q = dt_long / dt;
+    int64_t ratio = (int64_t)floor(q + 0.5);
+    if (n_long < 0 || ratio < 1 || fabs((double)ratio * dt - dt_long) > 1e-9 * dt_long) {
+        snprintf(o->err, sizeof o->err, "dt_long must be a positive whole multiple of dt"); return -1;
+    }
+    const double ah = dt_long / N->tau_h, az = dt_long / N->tau_z, ap = dt_long / N->tau_p;
+    const double rc = exp(-dt_long / N->tau_c);
+    for (int64_t k = 0; k < n_long; k++) {
+        for (int64_t cell = 0; cell < nc; cell++) {
+            double S = 0.0;
+            for (int64_t i = N->cv_off[cell]; i < N->cv_off[cell + 1]; i++)
+                for (int64_t qq = o->cv_syn_off[i]; qq < o->cv_syn_off[i + 1]; qq++) {
+                    int64_t s = o->syn_order[qq];
+                    if (N->syn_kind[s] == 1) S += fabs(o->h[s] - h0);
+                }
+            o->S[cell] = S;
+        }
+        for (int64_t s = 0; s < N->n_syn; s++) {
+            o->g[s] *= exp(-dt_long / N->syn_tau[s]);
+            if (N->syn_kind[s] != 1) continue;
+            double h = o->h[s], z = o->z[s], p = o->p[N->syn_cell[s]];
+            double tagp = ((h - h0) - N->theta_tag > 0.0) ? 1.0 : 0.0;
+            double tagd = ((h0 - h) - N->theta_tag > 0.0) ? 1.0 : 0.0;
+            o->h[s] = h + ah * (0.1 * (h0 - h));
+            o->z[s] = z + az * p * N->f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
+            o->c[s] *= rc;
+        }
+        for (int64_t cell = 0; cell < nc; cell++) {
+            double trig = (o->S[cell] - N->theta_pro > 0.0) ? 1.0 : 0.0;
+            o->p[cell] = o->p[cell] + ap * (-o->p[cell] + N->p_max * trig);
+        }
+    }
+    const int64_t n_new = o->step + n_long * ratio;
+    const double t_new = (double)n_new * dt;
+    memset(o->post, 0, (size_t)nc);
+    /* drop every queued event, then queue the train arrivals from the new
+       time on again */
+    o->q.n = 0;
+    for (int64_t tr = 0; tr < N->n_trains; tr++) {
+        for (int64_t j = N->train_off[tr]; j < N->train_off[tr + 1]; j++) {
+            double t = N->train_times[j];
+            if (floor(t / dt) < (double)n_new) continue;
+            orc_event e = {0};
+            e.src = nc + tr; e.conn = 0; e.syn = N->train_dst[tr]; e.w = N->train_w[tr];
+            if (N->train_ports[tr] & 1) {
+                e.t = t; e.step = (int64_t)floor(e.t / dt); e.port = 1;
+                if (heap_push(&o->q, e)) { snprintf(o->err, sizeof o->err, "out of memory"); return -1; }
+            }
+            if (N->train_ports[tr] & 2) {
+                e.t = t + N->t_cd; e.step = (int64_t)floor(e.t / dt); e.port = 2;
+                if (heap_push(&o->q, e)) { snprintf(o->err, sizeof o->err, "out of memory"); return -1; }
+            }
+        }
+    }
+    for (int64_t k = 0; k < N->n_pois; k++) {
+        if (N->pois_rate[k] > 0 && floor(o->pois_t[k] / dt) < (double)n_new) {
+            o->pois_j[k] += 1;
+            o->pois_t[k] = t_new + orc_poisson_isi(N->seed, (uint64_t)k, (uint64_t)o->pois_j[k], N->pois_rate[k]);
+        }
+    }
+    o->step = n_new;
+    return 0;
+}
+
 int orc_run(orc *o, int64_t n_steps) {
     for (int64_t k = 0; k < n_steps; k++)
         if (orc_step(o)) return -1;
