@@ -63,7 +63,8 @@ class _Net(C.Structure):
          ("n_clamps", _I64), ("clamp_cell", _P), ("clamp_cv", _P), ("clamp_t0", _P),
          ("clamp_dur", _P), ("clamp_amp", _P),
          ("n_pois", _I64), ("pois_dst", _P), ("pois_ports", _P), ("pois_w", _P), ("pois_rate", _P),
-         ("prp_model", _I64), ("d_sps", _D), ("d_prp", _D)]
+         ("prp_model", _I64), ("d_sps", _D), ("d_prp", _D),
+         ("tau_pre", _D), ("tau_post", _D), ("a_pre_amp", _D), ("a_post_amp", _D), ("w0", _D), ("w_max", _D)]
 
 
 _libs = {}
@@ -149,6 +150,10 @@ class Oracle:
         s.prp_model = 1 if dif else 0
         s.d_sps = float(dif["d_sps"]) if dif else 0.0
         s.d_prp = float(dif["d_prp"]) if dif else 0.0
+        sp = net.get("stdp") or {}
+        s.tau_pre, s.tau_post = float(sp.get("tau_pre", 1.0)), float(sp.get("tau_post", 1.0))
+        s.a_pre_amp, s.a_post_amp = float(sp.get("a_pre", 0.0)), float(sp.get("a_post", 0.0))
+        s.w0, s.w_max = float(sp.get("w0", 0.0)), float(sp.get("w_max", 0.0))
         self._s = s
         err = C.create_string_buffer(256)
         h = lib.orc_create(C.byref(s), err, 256)

@@ -34,6 +34,10 @@
  *     the protein (PRP), synthesised at the soma while the SPS
  *     concentration there exceeds theta_pro / V_tot and decaying everywhere;
  *     z then takes the PRP concentration of its synapse's CV.
+ *     Pair-based STDP synapses (kind 2, Eqs. 6-8): a conductance-port event
+ *     adds w_conn x clip(w, 0, w_max) to g, then a_pre += A_pre and
+ *     w += a_post; the post-synaptic hook adds A_post to a_post and a_pre
+ *     to w; both traces decay exactly in step 6.
  *  7. threshold detection V^n < theta <= V^{n+1}, linear interpolation of
  *     the crossing time, and one queued event per outgoing connection and
  *     port (delay d, calcium port a further t_c,delay later), delivered at
@@ -101,6 +105,10 @@ typedef struct {
        (Eq. 5) with diffusivities in um^2/ms */
     int64_t prp_model;
     double d_sps, d_prp;
+
+    /* pair-based STDP synapses (kind 2; Eqs. 6-8, Table 1): trace time
+       constants (ms), trace amplitudes and weights (uS) */
+    double tau_pre, tau_post, a_pre_amp, a_post_amp, w0, w_max;
 } orc_net;
 
 /* ------------------------------------------------------------ event heap */
@@ -272,7 +280,7 @@ typedef struct {
     int64_t *sp_gid, *sp_step;
     double *sp_t;
     heap q;
-    double r_c;
+    double r_c, r_pre, r_post;
 } orc;
 
 static void *xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
@@ -308,6 +316,9 @@ orc *orc_create(const orc_net *net, char *err, int errlen) {
     o->vtot = xcalloc(nc, 8); o->soma = xcalloc(nc, 8);
     if (N->prp_model != 0 && N->prp_model != 1) FAIL("prp_model must be 0 or 1");
     if (N->prp_model == 1 && !(N->d_sps >= 0 && N->d_prp >= 0)) FAIL("diffusivities must be >= 0");
+    int has_stdp = 0;
+    for (int64_t s = 0; s < N->n_syn; s++) has_stdp |= N->syn_kind[s] == 2;
+    if (has_stdp && !(N->tau_pre > 0 && N->tau_post > 0 && N->w_max >= 0)) FAIL("STDP time constants must be positive");
     const double pi = 3.14159265358979323846;
     int64_t nhh = 0;
     for (int64_t c = 0; c < nc; c++) {
@@ -382,9 +393,12 @@ orc *orc_create(const orc_net *net, char *err, int errlen) {
         if (cell < 0 || cell >= nc) FAIL("synapse %lld: bad cell", (long long)s);
         if (N->syn_cv[s] < 0 || N->syn_cv[s] >= N->cv_off[cell + 1] - N->cv_off[cell]) FAIL("synapse %lld: bad CV", (long long)s);
         if (!(N->syn_tau[s] > 0)) FAIL("synapse %lld: tau must be positive", (long long)s);
-        if (N->syn_kind[s] > 1) FAIL("synapse %lld: bad kind", (long long)s);
+        if (N->syn_kind[s] > 2) FAIL("synapse %lld: bad kind", (long long)s);
         o->decay[s] = exp(-N->dt / N->syn_tau[s]);
-        o->h[s] = (N->syn_kind[s] == 1) ? N->h0 : 0.0;
+        /* h holds the early-phase weight of a tagging-and-capture synapse
+           and the weight w of an STDP synapse (whose traces a_pre, a_post
+           live in c and z) */
+        o->h[s] = (N->syn_kind[s] == 1) ? N->h0 : ((N->syn_kind[s] == 2) ? N->w0 : 0.0);
         pairs[2 * s] = N->cv_off[cell] + N->syn_cv[s];
         pairs[2 * s + 1] = s;
     }
@@ -413,6 +427,8 @@ orc *orc_create(const orc_net *net, char *err, int errlen) {
     }
     free(fill);
     o->r_c = exp(-N->dt / N->tau_c);
+    o->r_pre = has_stdp ? exp(-N->dt / N->tau_pre) : 1.0;
+    o->r_post = has_stdp ? exp(-N->dt / N->tau_post) : 1.0;
     /* explicit presynaptic trains enter the queue up front */
     for (int64_t tr = 0; tr < N->n_trains; tr++) {
         int32_t s = N->train_dst[tr];
@@ -560,8 +576,19 @@ static int orc_step(orc *o) {
         if (e.step < n) { snprintf(o->err, sizeof o->err, "event for step %lld found at step %lld", (long long)e.step, (long long)n); return -1; }
         int32_t s = e.syn;
         if (e.port == 1) {
-            if (N->syn_kind[s] == 1) o->g[s] += e.w * ((o->h[s] + h0 * o->z[s]) / h0);
-            else o->g[s] += e.w;
+            if (N->syn_kind[s] == 1) {
+                o->g[s] += e.w * ((o->h[s] + h0 * o->z[s]) / h0);
+            } else if (N->syn_kind[s] == 2) {
+                /* STDP (Eqs. 6-8): the spike transmits the present weight,
+                   clipped to [0, w_max]; then a_pre += A_pre, w += a_post */
+                double w = o->h[s];
+                double wc = w < 0.0 ? 0.0 : (w > N->w_max ? N->w_max : w);
+                o->g[s] += e.w * wc;
+                o->c[s] += N->a_pre_amp;
+                o->h[s] = w + o->z[s];
+            } else {
+                o->g[s] += e.w;
+            }
         } else {
             o->c[s] += N->c_pre;
         }
@@ -569,8 +596,16 @@ static int orc_step(orc *o) {
         o->ev_stepsum[2 * s + e.port - 1] += (uint64_t)n;
     }
 #pragma omp parallel for schedule(static)
-    for (int64_t s = 0; s < N->n_syn; s++)
-        if (N->syn_kind[s] == 1 && o->post[N->syn_cell[s]]) o->c[s] += N->c_post;
+    for (int64_t s = 0; s < N->n_syn; s++) {
+        if (!o->post[N->syn_cell[s]]) continue;
+        if (N->syn_kind[s] == 1) {
+            o->c[s] += N->c_post;
+        } else if (N->syn_kind[s] == 2) {
+            /* STDP post-synaptic spike: a_post += A_post, w += a_pre */
+            o->z[s] += N->a_post_amp;
+            o->h[s] += o->c[s];
+        }
+    }
     memset(o->post, 0, (size_t)nc);
 
     /* 2. currents and conductances at V^n */
@@ -640,6 +675,12 @@ static int orc_step(orc *o) {
     const double ah = dt / N->tau_h, az = dt / N->tau_z;
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N->n_syn; s++) {
+        if (N->syn_kind[s] == 2) {
+            /* STDP traces decay exactly over the step (Eqs. 6, 7) */
+            o->c[s] *= o->r_pre;
+            o->z[s] *= o->r_post;
+            continue;
+        }
         if (N->syn_kind[s] != 1) continue;
         int32_t cell = N->syn_cell[s];
         double c = o->c[s], h = o->h[s], z = o->z[s];
