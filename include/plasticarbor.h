@@ -324,6 +324,42 @@ pa_status pa_stats_get(const pa_sim *sim, pa_stats *out);
 pa_status pa_kernel_timing(pa_sim *sim, int32_t enable);
 pa_status pa_kernel_time(pa_sim *sim, double *total_ms, uint64_t *launches, const char **name);
 
+/* Batched Hines solve (Hines 1989) of caller-given tree systems on the
+ * device, outside any simulation: the linear system of one implicit step
+ * of the cable equation (Eq. 4, Sec. 2.4) for n_cells cells at once.  All
+ * array arguments are device pointers owned by the caller:
+ *   cv_off  int64[n_cells+1]: cell k owns rows cv_off[k] .. cv_off[k+1]-1,
+ *           0 <= cv_off[k] <= cv_off[k+1] <= n_cv;
+ *   parent  int32[n_cv]: cell-local parent row, -1 for a cell's first row,
+ *           else 0 <= parent[i] < i;
+ *   diag    double[n_cv]: diagonal entries;
+ *   off     double[n_cv]: off[i] is the symmetric entry coupling row i to
+ *           its parent (ignored for a cell's first row);
+ *   rhs     double[n_cv]: right-hand side;
+ *   x       double[n_cv]: the solution (written).
+ * diag, off and rhs are not modified.  The elimination runs from a cell's
+ * last row towards its root, then substitution from the root, in the
+ * sequential algorithm's order (IEEE FP64, no fused multiply-add).  A cell
+ * whose range or parents break the rules above gets NaN in its rows of x.
+ * Work is enqueued on hip_stream (NULL: the null stream); the call returns
+ * after it has completed.  The elimination workspace (16 bytes per row) is
+ * allocated with hipMalloc for the call.  Errors: PA_EINVAL (NULL array
+ * with n_cells > 0), PA_ENOMEM, PA_EDEVICE. */
+pa_status pa_tree_solve(uint32_t n_cells, uint64_t n_cv, const int64_t *cv_off, const int32_t *parent,
+                        const double *diag, const double *off, const double *rhs, double *x,
+                        void *hip_stream);
+
+/* The same solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops): it allocates nothing, takes its
+ * workspace from a fixed per-device array of the library (16 MiB, so
+ * n_cv <= 1048576), does not synchronise and returns once the work is
+ * enqueued.  Calls that overlap on one device share that workspace and
+ * race: order them on one stream.  Errors: PA_EINVAL, PA_ERANGE
+ * (n_cv > 1048576), PA_EDEVICE. */
+pa_status pa_tree_solve_noalloc(uint32_t n_cells, uint64_t n_cv, const int64_t *cv_off,
+                                const int32_t *parent, const double *diag, const double *off,
+                                const double *rhs, double *x, void *hip_stream);
+
 const char *pa_last_error(const pa_sim *sim);
 const char *pa_status_str(pa_status status);
 

@@ -36,7 +36,8 @@ EXPORTS = [
     "pa_finalize", "pa_advance", "pa_advance_steps", "pa_spikes_count", "pa_spikes_read",
     "pa_probe_count", "pa_probe_read", "pa_state_read", "pa_state_read_device", "pa_state_write",
     "pa_stats_get",
-    "pa_kernel_timing", "pa_kernel_time", "pa_last_error", "pa_status_str",
+    "pa_kernel_timing", "pa_kernel_time", "pa_tree_solve", "pa_tree_solve_noalloc", "pa_last_error",
+    "pa_status_str",
 ]
 
 
@@ -134,6 +135,8 @@ def load_library(path: str = None):
         "pa_kernel_timing": (st, [_P, C.c_int32]),
         "pa_kernel_time": (st, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
                                 C.POINTER(C.c_char_p)]),
+        "pa_tree_solve": (st, [C.c_uint32, C.c_uint64, _P, _P, _P, _P, _P, _P, _P]),
+        "pa_tree_solve_noalloc": (st, [C.c_uint32, C.c_uint64, _P, _P, _P, _P, _P, _P, _P]),
         "pa_last_error": (C.c_char_p, [_P]),
         "pa_status_str": (C.c_char_p, [C.c_int32]),
     }
