@@ -939,6 +939,58 @@ void orc_hines(int64_t n, const int64_t *parent, const double *U, double *D, dou
     for (int64_t i = 1; i < n; i++) x[i] = (b[i] - U[i] * x[parent[i]]) / D[i];
 }
 
+/* ------------------------------------------------------------ Graupner-Brunel */
+/* The calcium-based rule of Graupner and Brunel (Sec. 3.3, Eqs. 10-12,
+ * Table 3) on independent single synapses under the pairing protocol of
+ * the DP curve: n_pairs presynaptic spikes, one every period_ms from t0_ms;
+ * each adds c_pre to the calcium t_cd later (delivered at the step
+ * floor(t / dt)), and a postsynaptic spike delay_ms[i] after it adds c_post
+ * (the postsynaptic spikes are imposed, as in the protocol).  Per step n,
+ * after that step's jumps (presynaptic first): with Theta_p = [c > theta_p]
+ * and Theta_d = [c > theta_d] from the step-start calcium, the
+ * Euler-Maruyama step of Eq. 10,
+ *   w <- w + (dt / tau_w) (-w (1 - w) (w_* - w) + gamma_p (1 - w) Theta_p
+ *                          - gamma_d w Theta_d)
+ *          + sigma sqrt((Theta_p + Theta_d) dt / tau_w) N_n   (Eq. 11),
+ * N_n the standard normal of trial i at step n (the generator of the
+ * early-phase noise keyed by the trial), then c <- c exp(-dt / tau_c)
+ * (Eq. 12).  The run covers the steps of n_pairs periods from t0.  Writes
+ * the final weight and calcium of every trial. */
+typedef struct {
+    double tau_w, w_star, gamma_p, gamma_d, theta_p, theta_d, sigma, tau_c, c_pre, c_post, t_cd;
+} orc_gb;
+
+int orc_gb_trials(const orc_gb *P, double dt, int64_t n_trials, const double *delay_ms, const double *w0,
+                  int64_t n_pairs, double period_ms, double t0_ms, uint64_t seed, double *w_out, double *c_out) {
+    if (!(dt > 0) || !(P->tau_w > 0) || !(P->tau_c > 0) || n_pairs < 0) return -1;
+    const int64_t n_end = (int64_t)floor((t0_ms + (double)n_pairs * period_ms) / dt);
+    const double ah = dt / P->tau_w, rc = exp(-dt / P->tau_c);
+    for (int64_t i = 0; i < n_trials; i++) {
+        double w = w0[i], c = 0.0;
+        int64_t kp = 0, kq = 0;
+        for (int64_t n = 0; n < n_end; n++) {
+            while (kp < n_pairs && floor((t0_ms + (double)kp * period_ms + P->t_cd) / dt) <= (double)n) {
+                c += P->c_pre;
+                kp++;
+            }
+            while (kq < n_pairs && floor((t0_ms + (double)kq * period_ms + delay_ms[i]) / dt) <= (double)n) {
+                c += P->c_post;
+                kq++;
+            }
+            double thp = (c - P->theta_p > 0.0) ? 1.0 : 0.0;
+            double thd = (c - P->theta_d > 0.0) ? 1.0 : 0.0;
+            double drift = -w * (1.0 - w) * (P->w_star - w) + P->gamma_p * (1.0 - w) * thp - P->gamma_d * w * thd;
+            double wn = w + ah * drift;
+            if (thp + thd > 0.0) wn += P->sigma * sqrt((thp + thd) * ah) * orc_normal(seed, (uint64_t)i, (uint64_t)n);
+            w = wn;
+            c = c * rc;
+        }
+        w_out[i] = w;
+        if (c_out) c_out[i] = c;
+    }
+    return 0;
+}
+
 void orc_destroy(orc *o) {
     if (!o) return;
     void *ptrs[] = {o->V, o->Vold, o->I, o->G, o->D, o->b, o->cdt, o->gpas, o->gpas_e, o->axial,
