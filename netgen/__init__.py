@@ -459,6 +459,81 @@ def stc_morpho_network(seed=6, t_end=10000.0, cell="small", dendrites="small", d
     return net
 
 
+# Graupner-Brunel calcium-based rule (Table 3): time constants in ms,
+# weights without unit.
+GB_TABLE3 = dict(tau_w=150000.0, w_star=0.5, gamma_p=321.808, gamma_d=200.0, theta_p=1.3, theta_d=1.0,
+                 sigma=2.8248, tau_c=20.0, c_pre=1.0, c_post=2.0, t_cd=13.7)
+
+# STDP synapse parameters (Table 1: the classical-window set; Table 7: the
+# busyring set), trace amplitudes and weights in uS, time constants in ms.
+STDP_TABLE1 = dict(tau_pre=20.0, tau_post=20.0, a_pre=0.01, a_post=-0.0105, w0=1.0, w_max=10.0)
+STDP_TABLE7 = dict(tau_pre=10.0, tau_post=10.0, a_pre=0.01, a_post=-0.01, w0=1.0, w_max=10.0)
+KIND_STDP = 2
+
+
+def simple_branchy(rng, depth, soma_diam=20.0, p_split=0.75, cvs=(6, 12), cv_len=10.0, d_rng=(0.5, 1.5)):
+    """HH soma and a random passive tree of at most `depth` branch levels
+    below the first dendritic branch: every branch above the deepest level
+    splits into two children with probability p_split; a branch has a
+    uniform number of 10-um CVs in [cvs] and one diameter.  Depth-first,
+    parent < child; depth 0 is the soma alone.  Mean sizes: 1, ~44 and
+    ~1500 CVs for depths 0, 2 and 10."""
+    parent, length, diam = [-1], [soma_diam], [soma_diam]
+    if depth > 0:
+        def grow(pcv, level):
+            n = int(rng.integers(cvs[0], cvs[1] + 1))
+            d = float(rng.uniform(*d_rng))
+            for _ in range(n):
+                parent.append(pcv)
+                length.append(cv_len)
+                diam.append(d)
+                pcv = len(parent) - 1
+            if level < depth and rng.random() < p_split:
+                grow(pcv, level + 1)
+                grow(pcv, level + 1)
+        grow(0, 0)
+    mech = np.zeros(len(parent), np.uint8)
+    mech[0] = MECH_HH
+    return np.asarray(parent, np.int32), np.asarray(length), np.asarray(diam), mech
+
+
+def busyring(n_cells=1024, depth=2, stdp=False, seed=8, ring=4, fanout=1000, delay=5.0, t_end=200.0,
+             w_ring=0.05, dt=0.025):
+    """The busyring benchmark (Sec. 3.8, Table 7): rings of `ring` cells in
+    which each cell excites the next (exp-syn on the soma, tau 2 ms, delay
+    5 ms) so that one spike circulates; the first cell of every ring gets a
+    single external arrival at t = 0; every cell also makes `fanout`
+    connections of weight 0 to synapses of its own on uniformly random
+    cells (on a random CV), which load spike transmission and delivery
+    without effect -- pair-based STDP synapses in the plasticity variant."""
+    rng_m, rng_c = _streams(seed, 2)
+    b = _Builder()
+    for _ in range(n_cells):
+        parent, length, diam, mech = simple_branchy(rng_m, depth)
+        b.add_cell(parent, length, diam, mech)
+    ring_syn = b.add_syns(np.arange(n_cells), np.zeros(n_cells, np.int32), KIND_EXPSYN, 2.0, 0.0)
+    n_ring = n_cells // ring
+    src = np.arange(n_ring * ring)
+    dst = (src // ring) * ring + (src % ring + 1) % ring
+    b.add_conns(src, ring_syn[dst], PORT_G, w_ring, delay)
+    # the random zero-weight connections: targets uniform over the cells,
+    # each onto a synapse of its own at a uniformly random CV of the target
+    tgt = rng_c.integers(0, n_cells, n_cells * fanout)
+    ncv = np.diff(np.asarray(b.cv_off))
+    cv = (rng_c.random(n_cells * fanout) * ncv[tgt]).astype(np.int32)
+    order = np.argsort(tgt, kind="stable")
+    sids = b.add_syns(tgt[order], cv[order], KIND_STDP if stdp else KIND_EXPSYN, 2.0, 0.0)
+    syn_of = np.empty(n_cells * fanout, np.int64)
+    syn_of[order] = sids
+    b.add_conns(np.repeat(np.arange(n_cells), fanout), syn_of, PORT_G, 0.0, delay)
+    for r in range(n_ring):
+        b.add_train(int(ring_syn[r * ring]), PORT_G, 10.0 * w_ring, [0.0])
+    net = b.finish(f"busyring-{n_cells}-d{depth}{'-stdp' if stdp else ''}", dt, t_end, seed, STC_TABLE5)
+    if stdp:
+        net["stdp"] = dict(STDP_TABLE7)
+    return net
+
+
 def config2(seed=2, t_end=10000.0, **kw):
     """2000 ball-and-stick cells (1 soma + 20 dendrite CVs), 1600 E / 400 I,
     p = 0.1, delay 3 ms, E->E plastic, 25 x 5 Hz external Poisson per cell."""
