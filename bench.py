@@ -105,21 +105,96 @@ def run_form(net, form, steps, warmup, settle=0, time_kernel=True, plan=None):
     return out
 
 
-def cpu_baseline(net, n_steps):
+def _oracle_rate(net, budget_s, threaded, min_steps=1):
+    """Steps the oracle from the network's start in chunks until budget_s of
+    CPU time has passed; returns (CV-steps/s, steps, seconds, spikes)."""
     import oracle
-    o = oracle.Oracle(net)
-    t0 = time.perf_counter()
-    o.run(n_steps)
-    el = time.perf_counter() - t0
-    spikes = int(o.spikes()[0].size)
-    return dict(value=o.n_cv * n_steps / el, unit="CV-steps/s", cores=1, kind="oracle",
-                sample=f"first {n_steps} steps ({n_steps * net['dt']:.0f} ms, {spikes} spikes) of the same "
-                       f"network with its inputs, single-threaded plain FP64 C oracle, {el:.1f} s")
+    o = oracle.Oracle(net, threaded=threaded)
+    done, el, chunk = 0, 0.0, 1
+    while el < budget_s or done < min_steps:
+        t0 = time.perf_counter()
+        o.run(chunk)
+        el += time.perf_counter() - t0
+        done += chunk
+        if el < 0.25 * budget_s:
+            chunk *= 2
+    return o.n_cv * done / el, done, el, int(o.spikes()[0].size)
+
+
+def cpu_baseline(net, budget_s):
+    """The plain FP64 oracle on the host: single-threaded (the oracle as it
+    stands) and, as a second figure, its OpenMP build on every host core
+    (same expressions and order per value)."""
+    rate, steps, el, spikes = _oracle_rate(net, budget_s, threaded=False)
+    cores = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    rate_n, steps_n, el_n, _ = _oracle_rate(net, budget_s / 2, threaded=True)
+    return dict(value=rate, unit="CV-steps/s", cores=1, kind="oracle",
+                sample=f"first {steps} steps ({steps * net['dt']:.1f} ms, {spikes} spikes) of the same network "
+                       f"with its inputs, single-threaded plain FP64 C oracle, {el:.1f} s",
+                multi_core=dict(value=rate_n, unit="CV-steps/s", cores=cores, kind="oracle (OpenMP build)",
+                                sample=f"first {steps_n} steps, {el_n:.1f} s"))
 
 
 # workloads: name in the JSON line, network builder
 WORKLOADS = {"ei2000x21": ("ei-ball-and-stick-2000x21cv", "config2"),
-             "ei2000x101": ("ei-ball-and-stick-2000x101cv", "config4")}
+             "ei2000x101": ("ei-ball-and-stick-2000x101cv", "config4"),
+             "trees4096": ("uneven-trees-4096x10-300cv", "config3"),
+             "large1e5": ("random-trees-1e5x10-60cv-1e7-plastic", "config5"),
+             "morpho2000": ("ei-table6-neurons-2000x31cv-sps-prp-diffusion", "stc_morpho_network"),
+             "busyring": ("busyring", "busyring"),
+             "dpcurve": ("graupner-brunel-dp-curve-41x4000-trials", None)}
+
+# The paper's own propagation times of the busyring benchmark over 200 ms
+# (Table 9, one NVIDIA T1000 GPU; context only, other hardware), seconds:
+# (cells, depth) -> (exponential synapses, STDP synapses)
+BUSYRING_T1000_S = {(1024, 0): (0.30, 0.78), (1024, 2): (0.41, 1.00), (1024, 10): (2.99, 3.50),
+                    (16384, 0): (2.81, 10.44), (16384, 2): (4.15, 12.04), (16384, 10): (40.45, 49.05),
+                    (32768, 0): (5.30, 20.47), (32768, 2): (7.78, 23.71), (32768, 10): (80.44, 97.75)}
+
+
+def dp_curve_bench(args):
+    """The Graupner-Brunel DP-curve batch (41 delays x 4000 trials, 60 pairs
+    at 1 Hz, dt 0.5 ms) as one launch of pa_gb_trials: synapse-steps/s, and
+    the oracle on a sample of trials for the CPU baseline."""
+    import numpy as np
+    import torch
+
+    import netgen
+    from paper_2411_16445_amd import binding as B
+    delays = np.repeat(np.linspace(-100.0, 100.0, 41), 4000)
+    w0 = np.tile(np.r_[np.zeros(2000), np.ones(2000)], 41)
+    d = torch.tensor(delays, dtype=torch.float64, device="cuda")
+    w = torch.tensor(w0, dtype=torch.float64, device="cuda")
+    steps = int(np.floor((100.0 + 60 * 1000.0) / 0.5))
+    for _ in range(max(1, args.warmup and 1)):
+        B.gb_trials(netgen.GB_TABLE3, 0.5, d, w, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(1, args.steps // 1000)
+    for k in range(reps):
+        wf, _ = B.gb_trials(netgen.GB_TABLE3, 0.5, d, w, seed=1 + k)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    rate = delays.size * steps / el
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        n = 40
+        t1 = time.perf_counter()
+        oracle.gb_trials(netgen.GB_TABLE3, 0.5, delays[:n], w0[:n], seed=1)
+        el_c = time.perf_counter() - t1
+        cpu = dict(value=n * steps / el_c, unit="synapse-steps/s", cores=1, kind="oracle",
+                   sample=f"{n} of the batch's trials, single-threaded plain FP64 C oracle, {el_c:.1f} s")
+    m = wf.cpu().numpy().reshape(41, 4000).mean(1)
+    line = {"metric": "Graupner-Brunel DP-curve batch throughput", "value": rate, "unit": "synapse-steps/s",
+            "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": el * 1e3 / steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (pairing protocol)",
+            "config": {"workload": "graupner-brunel-dp-curve-41x4000-trials", "trials": int(delays.size),
+                       "pairs": 60, "dt_ms": 0.5, "parallelism": "single-gpu"},
+            "seconds_per_batch": el, "dp_curve_mean_w": [round(float(x), 4) for x in m],
+            "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -132,13 +207,18 @@ def main():
     ap.add_argument("--form", default=os.environ.get("PA_BENCH_FORM", "batched-mixed"),
                     choices=["plain-fp64", "plain-mixed", "batched-fp64", "batched-mixed"])
     ap.add_argument("--no-compare", action="store_true", help="skip the plain and batched FP64 runs")
-    ap.add_argument("--cpu-steps", type=int, default=1500)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU time of the single-threaded oracle sample (the OpenMP sample takes half)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plan", default="",
                     help="fix the batched form's plan instead of autotuning it: "
                          "CELLS_PER_BLOCK,BLOCK_THREADS,SOLVER_WAVES,EXCHANGE (kernel|resident)")
     ap.add_argument("--workload", default="ei2000x101", choices=sorted(WORKLOADS),
-                    help="ei2000x101: the headline network (100-CV dendrites); ei2000x21: 20-CV dendrites")
+                    help="ei2000x101: the headline network (100-CV dendrites); ei2000x21: 20-CV dendrites; "
+                         "trees4096: 4096 random trees of 10-300 CVs; large1e5: 1e5 random trees of 10-60 CVs")
+    ap.add_argument("--ring-cells", type=int, default=16384, help="busyring: cells (rings of 4)")
+    ap.add_argument("--ring-depth", type=int, default=2, help="busyring: dendritic tree depth")
+    ap.add_argument("--ring-stdp", action="store_true", help="busyring: STDP synapses on the random connections")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the runs, copy this many MiB device to device (a plain copy kernel of known "
                          "size that scales rocprofv3's FETCH_SIZE / WRITE_SIZE)")
@@ -147,12 +227,20 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "dpcurve":
+        dp_curve_bench(args)
+        return
     import netgen
     # inputs over everything that runs: settle, warmup, timed steps and the
     # oracle's sample
-    t_end = (max(args.settle + args.warmup + args.steps, args.cpu_steps) + 100) * 0.2
+    t_end = (args.settle + args.warmup + args.steps + 5000) * 0.2
     wname, make = WORKLOADS[args.workload]
-    net = getattr(netgen, make)(t_end=t_end)
+    if args.workload == "busyring":
+        net = netgen.busyring(n_cells=args.ring_cells, depth=args.ring_depth, stdp=args.ring_stdp,
+                              t_end=(args.settle + args.warmup + args.steps + 100) * 0.025)
+        wname = net["name"]
+    else:
+        net = getattr(netgen, make)(t_end=t_end)
     print(f"[bench] network {netgen.summary(net)}", file=sys.stderr, flush=True)
     plan = None
     if args.plan:
@@ -172,7 +260,7 @@ def main():
               file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(net, args.cpu_steps)
+        cpu = cpu_baseline(net, args.cpu_seconds)
         print(f"[bench] cpu oracle: {cpu['value']:.3e} CV-steps/s", file=sys.stderr, flush=True)
     if args.copy_probe_mib:
         import torch
@@ -196,11 +284,14 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32" if args.form.endswith("mixed") else "f64",
-        "data": "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network; "
-                f"{args.settle} untimed settling steps from rest)",
+        "data": (f"synthetic (seeded busyring of {args.ring_cells} cells, tree depth {args.ring_depth}, "
+                 f"{'STDP' if args.ring_stdp else 'exponential'} synapses on 1000 zero-weight connections per cell)"
+                 if args.workload == "busyring" else
+                 "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network; "
+                 f"{args.settle} untimed settling steps from rest)"),
         "config": {"workload": wname, "cells": head["stats"]["n_cells"],
                    "cvs": head["stats"]["n_cv"], "synapses": head["stats"]["n_syn"],
-                   "stc_synapses": head["stats"]["n_stc"], "dt_ms": 0.2, "form": args.form,
+                   "stc_synapses": head["stats"]["n_stc"], "dt_ms": net["dt"], "form": args.form,
                    "epoch_steps": head["epoch_steps"], "cells_per_block": head["cells_per_block"],
                    "block_threads": head["block_threads"], "solver_waves": head["solver_waves"],
                    "exchange": head["exchange"], "settle_steps": args.settle, "parallelism": "single-gpu"},
@@ -230,6 +321,12 @@ def main():
     if bfp is not None:
         line["batched_fp64"] = {"cv_steps_per_s": bfp["cv_steps_per_s"], "ms_per_step": bfp["ms_per_step"],
                                 "spikes": bfp["spikes"]}
+    if args.workload == "busyring":
+        # the benchmark's own measure: propagation of 200 ms (8000 steps of 0.025 ms)
+        prop = head["ms_per_step"] * 8000 / 1000.0
+        paper = BUSYRING_T1000_S.get((args.ring_cells, args.ring_depth))
+        line["busyring_200ms_propagation_s"] = prop
+        line["paper_t1000_propagation_s"] = None if paper is None else paper[1 if args.ring_stdp else 0]
     print(json.dumps(line), flush=True)
 
 

@@ -83,6 +83,8 @@ typedef int32_t pa_status;
 #define PA_SYN_EXP 0  /* conductance-based exponential synapse */
 #define PA_SYN_STC 1  /* exponential synapse with calcium-based early phase and
                          tagging-and-capture late phase (Sec. 3.5) */
+#define PA_SYN_STDP 2 /* exponential synapse with pair-based STDP (Sec. 3.1,
+                         Eqs. 6-8): weight w, traces a_pre, a_post */
 
 typedef struct {
     double dt_ms;            /* time step, > 0 */
@@ -124,6 +126,15 @@ typedef struct {
     double h0, theta_pro, theta_tag;     /* mV */
     double c_pre, c_post;                /* calcium jumps */
 } pa_stc_params;
+
+/* Pair-based STDP (Eqs. 6-8, Table 1): trace time constants (ms), trace
+ * amplitudes A_pre > 0, A_post < 0 and weights (uS). */
+typedef struct {
+    double tau_pre, tau_post;
+    double a_pre, a_post;
+    double w0;      /* initial weight */
+    double w_max;   /* the weight's contribution to the conductance is clipped to [0, w_max] */
+} pa_stdp_params;
 
 /* Membrane and channel constants of one cell. */
 typedef struct {
@@ -236,10 +247,42 @@ pa_status pa_clamps_add(pa_sim *sim, uint32_t n, const uint32_t *gid, const uint
 
 #define PA_PROBE_V 0   /* index: global CV (cv_off of the cell + local CV) */
 #define PA_PROBE_G 1   /* index: synapse id */
-#define PA_PROBE_CA 2  /* index: synapse id (PA_SYN_STC) */
-#define PA_PROBE_H 3   /* index: synapse id (PA_SYN_STC) */
-#define PA_PROBE_Z 4   /* index: synapse id (PA_SYN_STC) */
+#define PA_PROBE_CA 2  /* index: synapse id (PA_SYN_STC; a_pre of PA_SYN_STDP) */
+#define PA_PROBE_H 3   /* index: synapse id (PA_SYN_STC; w of PA_SYN_STDP) */
+#define PA_PROBE_Z 4   /* index: synapse id (PA_SYN_STC; a_post of PA_SYN_STDP) */
 #define PA_PROBE_P 5   /* index: cell id */
+#define PA_PROBE_SPS 6 /* index: global CV (needs pa_set_diffusion) */
+#define PA_PROBE_PRP 7 /* index: global CV (needs pa_set_diffusion) */
+
+/* Switches the protein model from the per-cell sum of Eq. 21 to particle
+ * diffusion over each cell's CVs (Eq. 5, Sec. 2.4; the multi-compartment
+ * formulation of Sec. 3.6 with the threshold of Eq. 23).  Two species
+ * diffuse by backward Euler on the finite-volume tree of the cell (sealed
+ * ends; between a CV and its parent a flux D (X_j - X_i) over the two
+ * half-cylinders' length / cross-section in series; CV volume pi r^2 l):
+ *   SPS, released at each plastic synapse's CV by the step's change of
+ *     |h - h0| (so that a cell's SPS amount is the sum of Eq. 21);
+ *   PRP, decaying at rate 1 / tau_p everywhere and synthesised in the
+ *     detector CV (the soma) at p_max V_tot / tau_p (amount per time) while
+ *     the SPS concentration there exceeds theta_pro / V_tot (Eq. 23), so
+ *     that a well-mixed cell follows Eq. 21.
+ * z (Eq. 20) then takes the step-start PRP concentration of its synapse's
+ * CV; the per-cell p is no longer updated.  Diffusivities in um^2/ms
+ * (1e-11 m^2/s = 1e-2 um^2/ms), >= 0.  Both start at zero concentration.
+ * Allowed before pa_finalize only.  Errors: PA_EINVAL, PA_ESTATE. */
+pa_status pa_set_diffusion(pa_sim *sim, double d_sps_um2_per_ms, double d_prp_um2_per_ms);
+
+/* Parameters of the PA_SYN_STDP synapses (Eqs. 6-8): a conductance-port
+ * event of connection weight w_conn adds w_conn clip(w, 0, w_max) to g
+ * (the weight before this spike's change), then a_pre += A_pre and
+ * w += a_post; a post-synaptic spike (the hook of Sec. 2.1, at the start of
+ * the step after its detection, after that step's events) adds A_post to
+ * a_post and a_pre to w; both traces decay by exp(-dt/tau) every step.  The
+ * state arrays and probes report w as H, a_pre as CA and a_post as Z.
+ * Fast-forward leaves STDP synapses as they are (apart from their
+ * conductance).  Required before pa_finalize when PA_SYN_STDP synapses
+ * exist.  Errors: PA_EINVAL (time constants not positive), PA_ESTATE. */
+pa_status pa_set_stdp(pa_sim *sim, const pa_stdp_params *params);
 
 /* Adds n probes (the recorded traces of the paper's figures): probe k
  * samples quantity what[k] of element index[k] after every
@@ -296,6 +339,8 @@ pa_status pa_probe_read(const pa_sim *sim, uint32_t probe_id, double *out, uint6
 #define PA_STATE_P 8        /* n_cells doubles */
 #define PA_STATE_EVCOUNT 9  /* 2 uint64 per synapse: delivered events per port */
 #define PA_STATE_EVSTEPSUM 10 /* 2 uint64 per synapse: sum of delivery steps */
+#define PA_STATE_SPS 11     /* n_cv doubles: SPS concentration (needs pa_set_diffusion) */
+#define PA_STATE_PRP 12     /* n_cv doubles: PRP concentration (needs pa_set_diffusion) */
 
 /* Copies a state array to a host buffer of n elements (count must match).
  * FP32 state of the mixed form is widened.  READY state only. */
@@ -312,6 +357,37 @@ pa_status pa_state_read_device(pa_sim *sim, int32_t what, void *dev_out, uint64_
 /* Overwrites a state array (codes 0-8) from a host buffer; for setting up
  * test states.  READY state only. */
 pa_status pa_state_write(pa_sim *sim, int32_t what, const void *in, uint64_t n);
+
+/* Fast-forward (the long steps of slow network dynamics of the 8-h
+ * paradigm, Sec. 3.5): n_long steps of length dt_long_ms (a whole multiple
+ * of dt) that advance only h, z and p, with spiking and calcium off: per
+ * long step, from step-start values, h += (dt_long/tau_h) 0.1 (h0 - h)
+ * (Eq. 17 without calcium), z by Eq. 20 and p by Eq. 21 with S = sum
+ * |h - h0|; synaptic conductances and calcium decay exactly over each long
+ * step; membrane voltages and gates stay as they are.  Everything in
+ * flight is dropped: spikes before the new time cause no events, the
+ * post-synaptic flags clear, explicit train arrivals before the new time
+ * are skipped, and a Poisson source whose next arrival falls before it
+ * draws that arrival again (index + 1) as the new time plus an interval.
+ * Time moves to t + n_long dt_long.  Needs the per-cell protein model.
+ * Errors: PA_EINVAL (dt_long not a whole positive multiple of dt, particle
+ * diffusion on), PA_ESTATE, PA_ERANGE, PA_ENOMEM, PA_EDEVICE. */
+pa_status pa_fast_forward(pa_sim *sim, uint64_t n_long, double dt_long_ms);
+
+/* Device state dump (the state saving of Sec. 3.5, without a host round
+ * trip): every mutable array of the simulation (voltages, gates,
+ * conductances, calcium, h, z, p, species, post flags, spike rings,
+ * delivery statistics, train cursors, Poisson streams) and the step, in
+ * one buffer of pa_state_size bytes.  buf may be a device pointer (e.g. a
+ * framework tensor's storage) or host memory.  pa_state_load restores a
+ * dump into a simulation of the same network, precision and protein model
+ * (checked against the dump's header) and sets its time to the dump's;
+ * spikes and probe samples already read out are not part of the state.
+ * Errors: PA_EINVAL (buffer too small, dump of another shape), PA_ESTATE,
+ * PA_EDEVICE. */
+pa_status pa_state_size(pa_sim *sim, uint64_t *bytes);
+pa_status pa_state_save(pa_sim *sim, void *buf, uint64_t bytes);
+pa_status pa_state_load(pa_sim *sim, const void *buf, uint64_t bytes);
 
 /* Sizes and counters. */
 pa_status pa_stats_get(const pa_sim *sim, pa_stats *out);
@@ -359,6 +435,35 @@ pa_status pa_tree_solve(uint32_t n_cells, uint64_t n_cv, const int64_t *cv_off, 
 pa_status pa_tree_solve_noalloc(uint32_t n_cells, uint64_t n_cv, const int64_t *cv_off,
                                 const int32_t *parent, const double *diag, const double *off,
                                 const double *rhs, double *x, void *hip_stream);
+
+/* Parameters of the calcium-based rule of Graupner and Brunel (Sec. 3.3,
+ * Eqs. 10-12, Table 3): time constants and the calcium delay in ms, the
+ * weight without unit. */
+typedef struct {
+    double tau_w, w_star, gamma_p, gamma_d, theta_p, theta_d, sigma;
+    double tau_c, c_pre, c_post, t_cd;
+} pa_gb_params;
+
+/* Batched single-synapse trials of that rule under the pairing protocol of
+ * its DP curve (Sec. 3.3, Fig. 2f/j): n_pairs presynaptic spikes, one every
+ * period_ms from t0_ms, each adding c_pre to the calcium t_cd later
+ * (delivered at the step floor(t / dt)); postsynaptic spikes imposed
+ * delay_ms[i] after each presynaptic one, adding c_post.  Per step, after
+ * that step's jumps (presynaptic first), the Euler-Maruyama step of Eq. 10
+ * from the step-start calcium,
+ *   w += (dt/tau_w)(-w(1-w)(w_* - w) + gamma_p (1-w) Th_p - gamma_d w Th_d)
+ *        + sigma sqrt((Th_p + Th_d) dt / tau_w) N,
+ * Th_x = [c > theta_x], N the standard normal of trial i at step n (the
+ * counter-based generator of the early-phase noise keyed by (seed, i)), then
+ * c *= exp(-dt / tau_c) (Eq. 12).  The run covers floor((t0 + n_pairs
+ * period) / dt) steps.  delay_ms, w0 (inputs) and w_final, c_final (the
+ * weight and calcium at the end; c_final may be NULL) are device arrays of
+ * n_trials doubles owned by the caller.  Work runs on hip_stream (NULL: the
+ * null stream); the call returns after it has completed.  Errors:
+ * PA_EINVAL, PA_ERANGE, PA_EDEVICE. */
+pa_status pa_gb_trials(const pa_gb_params *params, double dt_ms, uint64_t n_trials, const double *delay_ms,
+                       const double *w0, uint32_t n_pairs, double period_ms, double t0_ms, uint64_t seed,
+                       double *w_final, double *c_final, void *hip_stream);
 
 const char *pa_last_error(const pa_sim *sim);
 const char *pa_status_str(pa_status status);

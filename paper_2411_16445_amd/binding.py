@@ -26,17 +26,17 @@ PA_OK, PA_EINVAL, PA_ESTATE, PA_ENOMEM, PA_EDEVICE, PA_ERANGE, PA_EOVERFLOW, PA_
 PA_FP64, PA_MIXED = 0, 1
 PA_PLAIN, PA_BATCHED = 0, 1
 PA_PORT_G, PA_PORT_CA = 1, 2
-PA_PROBE = {"V": 0, "g": 1, "c": 2, "h": 3, "z": 4, "p": 5}
+PA_PROBE = {"V": 0, "g": 1, "c": 2, "h": 3, "z": 4, "p": 5, "sps": 6, "prp": 7}
 PA_STATE = {"V": 0, "m": 1, "hh": 2, "n": 3, "g": 4, "c": 5, "h": 6, "z": 7, "p": 8,
-            "evcount": 9, "evstepsum": 10}
+            "evcount": 9, "evstepsum": 10, "sps": 11, "prp": 12}
 
 EXPORTS = [
-    "pa_sim_create", "pa_sim_destroy", "pa_set_stream", "pa_set_allocator", "pa_cells_add",
+    "pa_sim_create", "pa_sim_destroy", "pa_set_stream", "pa_set_allocator", "pa_set_diffusion", "pa_set_stdp", "pa_cells_add",
     "pa_synapses_add", "pa_connect", "pa_trains_add", "pa_poisson_add", "pa_clamps_add", "pa_probes_add",
     "pa_finalize", "pa_advance", "pa_advance_steps", "pa_spikes_count", "pa_spikes_read",
     "pa_probe_count", "pa_probe_read", "pa_state_read", "pa_state_read_device", "pa_state_write",
-    "pa_stats_get",
-    "pa_kernel_timing", "pa_kernel_time", "pa_tree_solve", "pa_tree_solve_noalloc", "pa_last_error",
+    "pa_stats_get", "pa_fast_forward", "pa_state_size", "pa_state_save", "pa_state_load",
+    "pa_kernel_timing", "pa_kernel_time", "pa_tree_solve", "pa_tree_solve_noalloc", "pa_gb_trials", "pa_last_error",
     "pa_status_str",
 ]
 
@@ -55,6 +55,15 @@ STC_FIELDS = ["tau_c", "tau_h", "tau_p", "tau_z", "gamma_p", "gamma_d", "theta_p
 
 class pa_stc_params(C.Structure):
     _fields_ = [(k, C.c_double) for k in STC_FIELDS]
+
+
+class pa_stdp_params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("tau_pre", "tau_post", "a_pre", "a_post", "w0", "w_max")]
+
+
+class pa_gb_params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("tau_w", "w_star", "gamma_p", "gamma_d", "theta_p", "theta_d", "sigma",
+                                          "tau_c", "c_pre", "c_post", "t_cd")]
 
 
 class pa_cell_params(C.Structure):
@@ -91,13 +100,13 @@ _P = C.c_void_p
 
 
 def load_library(path: str = None):
-    """Loads libplasticarbor.so (the in-tree build, or the file named by the
-    PA_LIBRARY environment variable); raises ImportError if it is not built."""
+    """Loads the in-tree libplasticarbor.so; raises ImportError if it is not
+    built."""
     global _lib
     if _lib is not None:
         return _lib
     if path is None:
-        path = os.environ.get("PA_LIBRARY") or LIB_PATH
+        path = LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2411_16445_amd.build`")
     # PyTorch ships its own HIP runtime under the same soname; importing it
@@ -114,6 +123,8 @@ def load_library(path: str = None):
         "pa_sim_destroy": (None, [_P]),
         "pa_set_stream": (st, [_P, _P]),
         "pa_set_allocator": (st, [_P, ALLOC_FN, FREE_FN, _P]),
+        "pa_set_diffusion": (st, [_P, C.c_double, C.c_double]),
+        "pa_set_stdp": (st, [_P, C.POINTER(pa_stdp_params)]),
         "pa_cells_add": (st, [_P, C.c_uint32, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_uint32)]),
         "pa_synapses_add": (st, [_P, C.c_uint32, _P, _P, _P, _P, _P, C.POINTER(C.c_uint32)]),
         "pa_connect": (st, [_P, C.c_uint64, _P, _P, _P, _P, _P]),
@@ -132,11 +143,17 @@ def load_library(path: str = None):
         "pa_state_read_device": (st, [_P, C.c_int32, _P, C.c_uint64]),
         "pa_state_write": (st, [_P, C.c_int32, _P, C.c_uint64]),
         "pa_stats_get": (st, [_P, C.POINTER(pa_stats)]),
+        "pa_fast_forward": (st, [_P, C.c_uint64, C.c_double]),
+        "pa_state_size": (st, [_P, C.POINTER(C.c_uint64)]),
+        "pa_state_save": (st, [_P, _P, C.c_uint64]),
+        "pa_state_load": (st, [_P, _P, C.c_uint64]),
         "pa_kernel_timing": (st, [_P, C.c_int32]),
         "pa_kernel_time": (st, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
                                 C.POINTER(C.c_char_p)]),
         "pa_tree_solve": (st, [C.c_uint32, C.c_uint64, _P, _P, _P, _P, _P, _P, _P]),
         "pa_tree_solve_noalloc": (st, [C.c_uint32, C.c_uint64, _P, _P, _P, _P, _P, _P, _P]),
+        "pa_gb_trials": (st, [C.POINTER(pa_gb_params), C.c_double, C.c_uint64, _P, _P, C.c_uint32, C.c_double,
+                              C.c_double, C.c_uint64, _P, _P, _P]),
         "pa_last_error": (C.c_char_p, [_P]),
         "pa_status_str": (C.c_char_p, [C.c_int32]),
     }
@@ -146,6 +163,25 @@ def load_library(path: str = None):
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def gb_trials(params: dict, dt, delays, w0, n_pairs=60, period=1000.0, t0=100.0, seed=1):
+    """Graupner-Brunel trials on the device (pa_gb_trials): delays and w0
+    are float64 device tensors (or arrays, copied to the device); returns
+    the final weights and calcium as device tensors."""
+    import torch
+    lib = load_library()
+    d = torch.as_tensor(delays, dtype=torch.float64, device="cuda").contiguous()
+    w = torch.as_tensor(w0, dtype=torch.float64, device="cuda").contiguous()
+    out = torch.empty_like(d)
+    cout = torch.empty_like(d)
+    prm = pa_gb_params(*[float(params[k]) for k, _ in pa_gb_params._fields_])
+    st = lib.pa_gb_trials(C.byref(prm), float(dt), d.numel(), C.c_void_p(d.data_ptr()), C.c_void_p(w.data_ptr()),
+                          int(n_pairs), float(period), float(t0), int(seed), C.c_void_p(out.data_ptr()),
+                          C.c_void_p(cout.data_ptr()), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != PA_OK:
+        raise PAError(st, lib.pa_status_str(st).decode())
+    return out, cout
 
 
 class PAError(RuntimeError):
@@ -170,8 +206,9 @@ class Simulation:
 
     precision: "fp64" | "mixed"; mode: "plain" | "batched".
     probes: list of (quantity, index) or (quantity, index, stride_steps) with
-    quantity in V, g, c, h, z, p; probe_stride is the stride of those
-    without one.
+    quantity in V, g, c, h, z, p (and sps, prp per CV with particle
+    diffusion, net["diffusion"] = {d_sps, d_prp} in um^2/ms); probe_stride
+    is the stride of those without one.
     """
 
     def __init__(self, net: dict, precision="fp64", mode="plain", probes=(), probe_stride=1,
@@ -201,7 +238,14 @@ class Simulation:
         self._torch_cb = None
         if use_torch:
             self._attach_torch()
+        sp = net.get("stdp")
+        if sp:
+            prm = pa_stdp_params(*[float(sp[k]) for k in ("tau_pre", "tau_post", "a_pre", "a_post", "w0", "w_max")])
+            self._check(lib.pa_set_stdp(h, C.byref(prm)))
         self._add_network(net)
+        dif = net.get("diffusion")
+        if dif:
+            self._check(lib.pa_set_diffusion(h, float(dif["d_sps"]), float(dif["d_prp"])))
         if probes:
             what = np.array([PA_PROBE[p[0]] for p in probes], np.int32)
             idx = np.array([int(p[1]) for p in probes], np.uint64)
@@ -311,6 +355,31 @@ class Simulation:
     def advance_steps(self, n: int):
         self._check(self._lib.pa_advance_steps(self._h, int(n)))
 
+    def fast_forward(self, n_long: int, dt_long: float):
+        """n_long long steps of the slow plasticity variables only (spiking
+        and calcium off); time moves by n_long * dt_long ms."""
+        self._check(self._lib.pa_fast_forward(self._h, int(n_long), float(dt_long)))
+
+    def state_size(self) -> int:
+        n = C.c_uint64()
+        self._check(self._lib.pa_state_size(self._h, C.byref(n)))
+        return n.value
+
+    def save_state(self, buf=None):
+        """Dumps the whole mutable state into `buf` (a uint8 device tensor or
+        numpy array of state_size() bytes; a new numpy array if None)."""
+        if buf is None:
+            buf = np.zeros(self.state_size(), np.uint8)
+        ptr = buf.data_ptr() if hasattr(buf, "data_ptr") else buf.ctypes.data
+        nbytes = buf.numel() * buf.element_size() if hasattr(buf, "data_ptr") else buf.nbytes
+        self._check(self._lib.pa_state_save(self._h, C.c_void_p(ptr), int(nbytes)))
+        return buf
+
+    def load_state(self, buf):
+        ptr = buf.data_ptr() if hasattr(buf, "data_ptr") else buf.ctypes.data
+        nbytes = buf.numel() * buf.element_size() if hasattr(buf, "data_ptr") else buf.nbytes
+        self._check(self._lib.pa_state_load(self._h, C.c_void_p(ptr), int(nbytes)))
+
     def spikes(self):
         """The raster, (gid, step, t*) arrays in (t*, gid) order."""
         n = C.c_uint64()
@@ -339,7 +408,7 @@ class Simulation:
 
     def _size(self, what):
         return {"V": self.n_cv, "m": self.n_hh, "hh": self.n_hh, "n": self.n_hh,
-                "p": self.n_cells}.get(what, self.n_syn)
+                "p": self.n_cells, "sps": self.n_cv, "prp": self.n_cv}.get(what, self.n_syn)
 
     def read(self, what: str) -> np.ndarray:
         if what in ("evcount", "evstepsum"):

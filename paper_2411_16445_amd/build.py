@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplasticarbor.so")
-SOURCES = ["api.cpp", "kernels.hip", "kernels_fused.hip", "tree_solve.hip"]
+SOURCES = ["api.cpp", "kernels.hip", "kernels_fused.hip", "tree_solve.hip", "gb_trials.hip"]
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: no FMA contraction, so FP64 arithmetic is that of the

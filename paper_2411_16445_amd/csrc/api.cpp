@@ -24,6 +24,7 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 constexpr uint64_t HIST_CAP = 1ull << 24;   // spikes held on the device per chunk
 constexpr uint64_t SP_STAGE = 1ull << 16;   // spikes copied to the host per transfer
+constexpr double QUEUE_BUDGET = 12.0 * (1ull << 30);  // bytes of per-epoch event queues the epoch length aims at
 
 struct Alloc {
     void *p;
@@ -76,6 +77,11 @@ struct pa_sim {
     std::vector<int32_t> pr_what;
     std::vector<uint64_t> pr_index;
     std::vector<uint32_t> pr_stride;
+    double *ff_gdec = nullptr;    // per sorted synapse: conductance decay over a fast-forward step
+    pa_stdp_params stdp{};        // STDP synapses
+    bool stdp_set = false;
+    bool dif_on = false;          // SPS / PRP diffusion model
+    double dif_sps = 0.0, dif_prp = 0.0;
 
     // derived
     std::vector<uint32_t> syn_perm;   // sorted position -> synapse id
@@ -317,7 +323,7 @@ pa_status pa_synapses_add(pa_sim *s, uint32_t n, const uint32_t *gid, const uint
     for (uint32_t k = 0; k < n; ++k) {
         if (gid[k] >= ncell) return fail(s, PA_EINVAL, "synapse %u: unknown cell %u", k, gid[k]);
         if ((int64_t)cv[k] >= s->cv_off[gid[k] + 1] - s->cv_off[gid[k]]) return fail(s, PA_EINVAL, "synapse %u: CV out of range", k);
-        if (kind[k] > 1) return fail(s, PA_EINVAL, "synapse %u: unknown kind", k);
+        if (kind[k] > 2) return fail(s, PA_EINVAL, "synapse %u: unknown kind", k);
         if (!finite_pos(tau[k]) || !std::isfinite(erev[k])) return fail(s, PA_EINVAL, "synapse %u: invalid tau or reversal", k);
     }
     if (first_sid) *first_sid = (uint32_t)s->syn_cell.size();
@@ -428,6 +434,29 @@ pa_status pa_clamps_add(pa_sim *s, uint32_t n, const uint32_t *gid, const uint32
     return PA_OK;
 }
 
+pa_status pa_set_stdp(pa_sim *s, const pa_stdp_params *p) {
+    if (!s || !p) return PA_EINVAL;
+    if (s->state != 0) return fail(s, PA_ESTATE, "STDP parameters are set before pa_finalize");
+    if (!(p->tau_pre > 0.0) || !(p->tau_post > 0.0) || !std::isfinite(p->tau_pre) || !std::isfinite(p->tau_post) ||
+        !std::isfinite(p->a_pre) || !std::isfinite(p->a_post) || !std::isfinite(p->w0) || !(p->w_max >= 0.0) ||
+        !std::isfinite(p->w_max))
+        return fail(s, PA_EINVAL, "STDP time constants must be positive and every parameter finite");
+    s->stdp = *p;
+    s->stdp_set = true;
+    return PA_OK;
+}
+
+pa_status pa_set_diffusion(pa_sim *s, double d_sps, double d_prp) {
+    if (!s) return PA_EINVAL;
+    if (s->state != 0) return fail(s, PA_ESTATE, "the protein model is set before pa_finalize");
+    if (!(d_sps >= 0.0) || !(d_prp >= 0.0) || !std::isfinite(d_sps) || !std::isfinite(d_prp))
+        return fail(s, PA_EINVAL, "diffusivities must be finite and >= 0");
+    s->dif_on = true;
+    s->dif_sps = d_sps;
+    s->dif_prp = d_prp;
+    return PA_OK;
+}
+
 pa_status pa_probes_add(pa_sim *s, uint32_t n, const int32_t *what, const uint64_t *index,
                         const uint32_t *stride_steps, uint32_t *first) {
     if (!s) return PA_EINVAL;
@@ -438,13 +467,16 @@ pa_status pa_probes_add(pa_sim *s, uint32_t n, const int32_t *what, const uint64
         if (stride_steps[k] == 0) return fail(s, PA_EINVAL, "probe %u: stride must be >= 1", k);
         switch (what[k]) {
         case PA_PROBE_V:
+        case PA_PROBE_SPS:
+        case PA_PROBE_PRP:
             if (i >= (uint64_t)s->cv_off.back()) return fail(s, PA_EINVAL, "probe %u: CV out of range", k);
             break;
         case PA_PROBE_G:
             if (i >= s->syn_cell.size()) return fail(s, PA_EINVAL, "probe %u: synapse out of range", k);
             break;
         case PA_PROBE_CA: case PA_PROBE_H: case PA_PROBE_Z:
-            if (i >= s->syn_cell.size() || s->syn_kind[i] != PA_SYN_STC) return fail(s, PA_EINVAL, "probe %u: needs a PA_SYN_STC synapse", k);
+            if (i >= s->syn_cell.size() || s->syn_kind[i] == PA_SYN_EXP)
+                return fail(s, PA_EINVAL, "probe %u: needs a PA_SYN_STC or PA_SYN_STDP synapse", k);
             break;
         case PA_PROBE_P:
             if (i >= s->cv_off.size() - 1) return fail(s, PA_EINVAL, "probe %u: cell out of range", k);
@@ -486,6 +518,11 @@ pa_status build(pa_sim *s) {
                 P.sigma_pl, P.p_max, P.f_int, P.t_cd, P.h0, P.theta_pro, P.theta_tag, P.c_pre, P.c_post};
     d.r_c = std::exp(-dt / P.tau_c);
     d.r_c_f = (float)d.r_c;
+    if (s->stdp_set) {
+        const pa_stdp_params &Q = s->stdp;
+        d.stdp = StdpK{Q.a_pre, Q.a_post, Q.w_max, std::exp(-dt / Q.tau_pre), std::exp(-dt / Q.tau_post), 0.f};
+        d.stdp.r_pre_f = (float)d.stdp.r_pre;
+    }
 
     // ---- epoch length: spikes of an epoch may only be delivered after it
     double dmin = INFINITY, dmax = 0.0;
@@ -496,6 +533,14 @@ pa_status build(pa_sim *s) {
         double q = dmin / dt;
         long k = (long)std::ceil(q - 1e-9) - 1;
         K = (uint32_t)std::max<long>(1, std::min<long>(k, 256));
+        // The per-epoch queues hold, per incoming connection and port, the
+        // most spikes a source can make in an epoch's window (K / 2 + 2);
+        // with thousands of inputs per cell and long epochs that bound alone
+        // would take tens of GB, so the epoch is shortened until it fits
+        // QUEUE_BUDGET (any K up to the delay bound is exact).
+        uint64_t ports = 0;
+        for (uint8_t pr : s->conn_ports) ports += ((pr & 1) ? 1 : 0) + ((pr & 2) ? 1 : 0);
+        while (K > 1 && 32.0 * (double)ports * (double)(K / 2 + 2) > QUEUE_BUDGET) K = std::max<uint32_t>(1, K * 3 / 4);
     }
     const double tcd = P.t_cd;
     d.K = K;
@@ -526,6 +571,7 @@ pa_status build(pa_sim *s) {
     // ---- per-CV invariants of the cable system
     std::vector<int32_t> gparent(ncv);
     std::vector<double> cdt(ncv), gpas(ncv), gpas_e(ncv), axial(ncv, 0.0), d0(ncv);
+    std::vector<double> dgeo(ncv, 0.0);  // cross-section / length of the CV-parent pair (diffusion)
     std::vector<int32_t> hh_of(ncv, -1);
     std::vector<uint32_t> hh_cv;
     std::vector<double> hh_scale, hh_par;
@@ -560,6 +606,7 @@ pa_status build(pa_sim *s) {
             const double ri = 0.5 * s->diam[i], rk = 0.5 * s->diam[k];
             const double rsum = s->length[i] / (2.0 * PI * ri * ri) + s->length[k] / (2.0 * PI * rk * rk);
             axial[i] = 1e2 / (C.ra * rsum);  // uS between the two CV centres
+            dgeo[i] = 1.0 / rsum;            // um: the same series form for a diffusive flux
         }
     }
     cvoff[nc] = ncv;
@@ -572,6 +619,51 @@ pa_status build(pa_sim *s) {
     }
     d.n_hh = (uint32_t)hh_cv.size();
     s->hh_cv = hh_cv;
+
+    // ---- particle diffusion: CV volumes, per cell V_tot, and both species'
+    // constant tree systems (V_i + dt sum a) X_i - dt sum a X_j eliminated
+    // in the order of the Hines sweep
+    std::vector<double> dvol, sps_u, sps_f, sps_dp, prp_u, prp_f, prp_dp, dif_thr, dif_pv;
+    if (s->dif_on) {
+        dvol.resize(ncv);
+        dif_thr.resize(nc);
+        dif_pv.resize(nc);
+        for (uint32_t c = 0; c < nc; ++c) {
+            double vt = 0.0;
+            for (uint32_t i = cvoff[c]; i < cvoff[c + 1]; ++i) {
+                const double r = 0.5 * s->diam[i];
+                dvol[i] = PI * r * r * s->length[i];
+                vt += dvol[i];
+            }
+            dif_thr[c] = P.theta_pro / vt;
+            dif_pv[c] = P.p_max * vt;
+        }
+        auto factor = [&](double dc, std::vector<double> &U, std::vector<double> &F, std::vector<double> &Dp) {
+            U.assign(ncv, 0.0);
+            F.assign(ncv, 0.0);
+            Dp = dvol;
+            for (uint32_t c = 0; c < nc; ++c) {
+                const uint32_t b0 = cvoff[c], b1 = cvoff[c + 1];
+                for (uint32_t i = b0 + 1; i < b1; ++i) {
+                    const double a = dt * (dc * dgeo[i]);
+                    Dp[i] += a;
+                    Dp[gparent[i]] += a;
+                }
+                for (uint32_t i = b1 - 1; i > b0; --i) {
+                    const double u = -(dt * (dc * dgeo[i]));
+                    const double f = u / Dp[i];
+                    Dp[gparent[i]] -= f * u;
+                    U[i] = u;
+                    F[i] = f;
+                }
+            }
+        };
+        factor(s->dif_sps, sps_u, sps_f, sps_dp);
+        factor(s->dif_prp, prp_u, prp_f, prp_dp);
+    }
+    for (int32_t w : s->pr_what)
+        if ((w == PA_PROBE_SPS || w == PA_PROBE_PRP) && !s->dif_on)
+            return fail(s, PA_EINVAL, "SPS / PRP probes need pa_set_diffusion");
 
     // ---- synapses in sorted order
     std::vector<uint32_t> ssid(ns), scell(ns), scv(ns), syn_off(nc + 1, 0), cv_syn_off(ncv + 1, 0);
@@ -588,7 +680,8 @@ pa_status build(pa_sim *s) {
         serev[q] = s->syn_erev[k];
         sdecay[q] = std::exp(-dt / s->syn_tau[k]);
         sdecay_f[q] = (float)sdecay[q];
-        h[q] = skind[q] == PA_SYN_STC ? P.h0 : 0.0;
+        h[q] = skind[q] == PA_SYN_STC ? P.h0 : (skind[q] == PA_SYN_STDP ? s->stdp.w0 : 0.0);
+        if (skind[q] == PA_SYN_STDP && !s->stdp_set) return fail(s, PA_EINVAL, "PA_SYN_STDP synapses need pa_set_stdp");
         s->n_stc += skind[q] == PA_SYN_STC;
         cv_syn_off[gcv[k] + 1]++;
         syn_off[scell[q] + 1]++;
@@ -849,6 +942,21 @@ pa_status build(pa_sim *s) {
     d.cl_dur = upload(s, cldur, ok);
     d.cl_amp = upload(s, clamp, ok);
     d.q_off = upload(s, q_off, ok);
+    if (s->dif_on) {
+        d.dif = 1;
+        d.dvol = upload(s, dvol, ok);
+        d.sps_u = upload(s, sps_u, ok);
+        d.sps_f = upload(s, sps_f, ok);
+        d.sps_dp = upload(s, sps_dp, ok);
+        d.prp_u = upload(s, prp_u, ok);
+        d.prp_f = upload(s, prp_f, ok);
+        d.prp_dp = upload(s, prp_dp, ok);
+        d.dif_thr = upload(s, dif_thr, ok);
+        d.dif_pv = upload(s, dif_pv, ok);
+        d.sps = zeros<double>(s, ncv, ok);
+        d.prp = zeros<double>(s, ncv, ok);
+        d.dlt = zeros<double>(s, ns, ok);
+    }
     if (ok) {
         d.q_ev = (Event *)dev_alloc(s, std::max<uint64_t>(1, q_off[nc]) * sizeof(Event));
         if (!d.q_ev) ok = false;
@@ -1117,6 +1225,158 @@ extern "C" pa_status pa_advance(pa_sim *s, double t_until) {
 }
 
 // ----------------------------------------------------------------------
+// Fast-forward and the device state dump.
+extern "C" pa_status pa_fast_forward(pa_sim *s, uint64_t n_long, double dt_long) {
+    if (!s) return PA_EINVAL;
+    if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
+    if (s->state == 2) return fail(s, PA_ESTATE, "simulation failed earlier: %s", s->err.c_str());
+    if (s->dif_on) return fail(s, PA_EINVAL, "fast-forward needs the per-cell protein model");
+    const double dt = s->cfg.dt_ms;
+    if (!std::isfinite(dt_long) || !(dt_long > 0.0)) return fail(s, PA_EINVAL, "dt_long must be positive");
+    const double ratio_f = std::floor(dt_long / dt + 0.5);
+    if (ratio_f < 1.0 || std::fabs(ratio_f * dt - dt_long) > 1e-9 * dt_long)
+        return fail(s, PA_EINVAL, "dt_long must be a whole multiple of dt");
+    const uint64_t ratio = (uint64_t)ratio_f;
+    if (n_long == 0) return PA_OK;
+    if (n_long > (0xffffffffull - s->step) / ratio) return fail(s, PA_ERANGE, "step counts beyond 2^32 - 1 are not supported");
+    const uint64_t n_new = s->step + n_long * ratio;
+    DevNet &d = s->d;
+    const uint32_t ns = d.n_syn;
+    if (!s->ff_gdec && ns) {
+        s->ff_gdec = (double *)dev_alloc(s, (size_t)ns * 8);
+        if (!s->ff_gdec) return fail(s, PA_ENOMEM, "fast-forward factors");
+    }
+    if (ns) {
+        std::vector<double> gd(ns);
+        for (uint32_t q = 0; q < ns; ++q) gd[q] = std::exp(-dt_long / s->syn_tau[s->syn_perm[q]]);
+        HIPCHECK(s, hipMemcpyAsync(s->ff_gdec, gd.data(), (size_t)ns * 8, hipMemcpyHostToDevice, s->stream), "factors");
+        HIPCHECK(s, hipStreamSynchronize(s->stream), "factors");
+    }
+    const double rc = std::exp(-dt_long / s->stc.tau_c);
+    if (launch_fast_forward(d, n_long, dt_long, s->ff_gdec, rc, n_new, s->stream))
+        return hip_fail(s, hipGetLastError(), "fast-forward");
+    // train cursors: both ports at the first arrival from the new time on
+    const uint32_t ntr = d.n_trains;
+    if (ntr) {
+        std::vector<uint64_t> cur(2 * (size_t)ntr);
+        for (uint32_t k = 0; k < ntr; ++k) {
+            uint64_t j = s->tr_off[k];
+            while (j < s->tr_off[k + 1] && std::floor(s->tr_t[j] / dt) < (double)n_new) ++j;
+            cur[2 * k] = cur[2 * k + 1] = j;
+        }
+        HIPCHECK(s, hipMemcpyAsync((void *)d.tr_cur, cur.data(), cur.size() * 8, hipMemcpyHostToDevice, s->stream), "cursors");
+        HIPCHECK(s, hipStreamSynchronize(s->stream), "cursors");
+    }
+    // new conductances: their carried per-CV sums follow
+    if (d.gsum && launch_carried_sums(d, s->stream) != 0) return fail(s, PA_EDEVICE, "carried sums");
+    // the epoch counter the kernels start from
+    Counters c{};
+    HIPCHECK(s, hipMemcpyAsync(&c, d.ctr, sizeof c, hipMemcpyDeviceToHost, s->stream), "counters");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "counters");
+    c.step = n_new;
+    HIPCHECK(s, hipMemcpyAsync(d.ctr, &c, sizeof c, hipMemcpyHostToDevice, s->stream), "counters");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "fast-forward");
+    s->step = n_new;
+    s->drained_to = n_new;
+    return PA_OK;
+}
+
+namespace {
+
+struct StateHeader {
+    uint64_t magic, version, n_cells, n_cv, n_syn, n_pois, n_trains, step, mixed, dif, bytes;
+};
+constexpr uint64_t STATE_MAGIC = 0x5041535441544531ull;  // "PASTATE1"
+
+// The mutable device arrays of a simulation (the same list the autotuning
+// snapshot saves), each padded to 256 bytes in the dump.
+struct Span { void *p; size_t n; };
+std::vector<Span> mutable_spans(pa_sim *s) {
+    DevNet &d = s->d;
+    const size_t t = d.mixed ? 4 : 8;
+    return {
+        {d.V, (size_t)d.n_cv * 8}, {d.gm, (size_t)d.n_hh * t}, {d.gh, (size_t)d.n_hh * t},
+        {d.gn, (size_t)d.n_hh * t}, {d.g, (size_t)d.n_syn * t}, {d.c, (size_t)d.n_syn * t},
+        {d.h, (size_t)d.n_syn * 8}, {d.z, (size_t)d.n_syn * 8}, {d.p, (size_t)d.n_cells * 8},
+        {d.S, (size_t)d.n_cells * 8}, {d.vdet_old, (size_t)d.n_cells * 8}, {d.post, (size_t)d.n_cells},
+        {d.ev_cnt, (size_t)d.n_syn * 16}, {d.ev_sum, (size_t)d.n_syn * 16},
+        {d.gsum, d.gsum ? (size_t)d.n_cv * 8 : 0}, {d.gesum, d.gesum ? (size_t)d.n_cv * 8 : 0},
+        {d.spk, (size_t)d.n_cells * d.H * sizeof(SpikeRec)}, {d.spk_n, (size_t)d.n_cells * 4},
+        {d.spk_last, (size_t)d.n_cells * 4},
+        {d.tr_cur, (size_t)d.n_trains * 16},
+        {d.pois_t, (size_t)d.n_pois * 16}, {d.pois_j, (size_t)d.n_pois * 16},
+        {d.sps, d.sps ? (size_t)d.n_cv * 8 : 0}, {d.prp, d.prp ? (size_t)d.n_cv * 8 : 0}};
+}
+
+uint64_t dump_bytes(pa_sim *s) {
+    uint64_t total = 256;  // header
+    for (const Span &x : mutable_spans(s)) total += (x.n + 255) & ~size_t(255);
+    return total;
+}
+
+StateHeader header_of(pa_sim *s) {
+    const DevNet &d = s->d;
+    return StateHeader{STATE_MAGIC, 1, d.n_cells, d.n_cv, d.n_syn, d.n_pois, d.n_trains, s->step,
+                       d.mixed, d.dif, dump_bytes(s)};
+}
+
+}  // namespace
+
+extern "C" pa_status pa_state_size(pa_sim *s, uint64_t *bytes) {
+    if (!s || !bytes) return PA_EINVAL;
+    if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
+    *bytes = dump_bytes(s);
+    return PA_OK;
+}
+
+extern "C" pa_status pa_state_save(pa_sim *s, void *buf, uint64_t bytes) {
+    if (!s || !buf) return PA_EINVAL;
+    if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
+    const StateHeader H = header_of(s);
+    if (bytes < H.bytes) return fail(s, PA_EINVAL, "state dump needs %llu bytes", (unsigned long long)H.bytes);
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "sync");
+    HIPCHECK(s, hipMemcpyAsync(buf, &H, sizeof H, hipMemcpyDefault, s->stream), "state save");
+    uint64_t off = 256;
+    for (const Span &x : mutable_spans(s)) {
+        if (x.n) HIPCHECK(s, hipMemcpyAsync((uint8_t *)buf + off, x.p, x.n, hipMemcpyDefault, s->stream), "state save");
+        off += (x.n + 255) & ~size_t(255);
+    }
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "state save");
+    return PA_OK;
+}
+
+extern "C" pa_status pa_state_load(pa_sim *s, const void *buf, uint64_t bytes) {
+    if (!s || !buf) return PA_EINVAL;
+    if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
+    StateHeader H{}, want = header_of(s);
+    if (bytes < sizeof H) return fail(s, PA_EINVAL, "state dump too short");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "sync");
+    HIPCHECK(s, hipMemcpyAsync(&H, buf, sizeof H, hipMemcpyDefault, s->stream), "state load");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "state load");
+    if (H.magic != STATE_MAGIC || H.version != want.version || H.n_cells != want.n_cells || H.n_cv != want.n_cv ||
+        H.n_syn != want.n_syn || H.n_pois != want.n_pois || H.n_trains != want.n_trains || H.mixed != want.mixed ||
+        H.dif != want.dif || H.bytes != want.bytes || bytes < H.bytes)
+        return fail(s, PA_EINVAL, "state dump does not belong to a network of this shape and form");
+    if (H.step >= 0xffffffffull) return fail(s, PA_EINVAL, "state dump step out of range");
+    uint64_t off = 256;
+    for (const Span &x : mutable_spans(s)) {
+        if (x.n) HIPCHECK(s, hipMemcpyAsync(x.p, (const uint8_t *)buf + off, x.n, hipMemcpyDefault, s->stream), "state load");
+        off += (x.n + 255) & ~size_t(255);
+    }
+    Counters c{};
+    HIPCHECK(s, hipMemcpyAsync(&c, s->d.ctr, sizeof c, hipMemcpyDeviceToHost, s->stream), "counters");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "counters");
+    c.step = H.step;
+    c.flags = 0;
+    HIPCHECK(s, hipMemcpyAsync(s->d.ctr, &c, sizeof c, hipMemcpyHostToDevice, s->stream), "counters");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "state load");
+    s->step = H.step;
+    s->drained_to = H.step;
+    if (s->state == 2) s->state = 1;
+    return PA_OK;
+}
+
+// ----------------------------------------------------------------------
 extern "C" pa_status pa_spikes_count(const pa_sim *s, uint64_t *n) {
     if (!s || !n) return PA_EINVAL;
     *n = s->sp_gid.size();
@@ -1198,6 +1458,8 @@ bool view_of(pa_sim *s, int32_t what, View &v) {
     case PA_STATE_P: v = {d.p, 8, d.n_cells, 0, false}; return true;
     case PA_STATE_EVCOUNT: v = {d.ev_cnt, 16, d.n_syn, 1, false}; return true;
     case PA_STATE_EVSTEPSUM: v = {d.ev_sum, 16, d.n_syn, 1, false}; return true;
+    case PA_STATE_SPS: v = {d.sps, 8, d.n_cv, 0, false}; return d.dif != 0;
+    case PA_STATE_PRP: v = {d.prp, 8, d.n_cv, 0, false}; return d.dif != 0;
     default: return false;
     }
 }
@@ -1209,7 +1471,7 @@ extern "C" pa_status pa_state_read(pa_sim *s, int32_t what, void *out, uint64_t 
     if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
     View v;
     if (!view_of(s, what, v)) return fail(s, PA_EINVAL, "unknown state array %d", what);
-    const uint64_t count = (what >= PA_STATE_EVCOUNT) ? 2 * v.n : v.n;
+    const uint64_t count = (what == PA_STATE_EVCOUNT || what == PA_STATE_EVSTEPSUM) ? 2 * v.n : v.n;
     if (n != count) return fail(s, PA_EINVAL, "state array %d has %llu elements", what, (unsigned long long)count);
     std::vector<uint8_t> buf(v.n * v.esize);
     HIPCHECK(s, hipStreamSynchronize(s->stream), "sync");
@@ -1233,7 +1495,7 @@ extern "C" pa_status pa_state_read_device(pa_sim *s, int32_t what, void *out, ui
     if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
     View v;
     if (!view_of(s, what, v)) return fail(s, PA_EINVAL, "unknown state array %d", what);
-    const uint64_t count = (what >= PA_STATE_EVCOUNT) ? 2 * v.n : v.n;
+    const uint64_t count = (what == PA_STATE_EVCOUNT || what == PA_STATE_EVSTEPSUM) ? 2 * v.n : v.n;
     if (n != count) return fail(s, PA_EINVAL, "state array %d has %llu elements", what, (unsigned long long)count);
     const uint32_t words = v.narrow ? 1u : (uint32_t)(v.esize / 8);
     if (launch_state_out(v.p, words, v.narrow, v.perm == 1 ? s->d.syn_sid : nullptr, v.n, out, s->stream))
@@ -1245,7 +1507,8 @@ extern "C" pa_status pa_state_read_device(pa_sim *s, int32_t what, void *out, ui
 extern "C" pa_status pa_state_write(pa_sim *s, int32_t what, const void *in, uint64_t n) {
     if (!s || !in) return PA_EINVAL;
     if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
-    if (what > PA_STATE_P) return fail(s, PA_EINVAL, "state array %d is read-only", what);
+    if (what == PA_STATE_EVCOUNT || what == PA_STATE_EVSTEPSUM)
+        return fail(s, PA_EINVAL, "state array %d is read-only", what);
     View v;
     if (!view_of(s, what, v)) return fail(s, PA_EINVAL, "unknown state array %d", what);
     if (n != v.n) return fail(s, PA_EINVAL, "state array %d has %llu elements", what, (unsigned long long)v.n);
@@ -1329,21 +1592,10 @@ BatchedPlan *&pa_plan(pa_sim *s) { return s->plan; }
 // so that autotuning trials leave the simulation at its initial state.
 pa_status pa_snapshot(pa_sim *s, int restore) {
     DevNet &d = s->d;
-    const size_t t = d.mixed ? 4 : 8;
-    struct Span { void *p; size_t n; };
-    const Span spans[] = {
-        {d.V, (size_t)d.n_cv * 8}, {d.gm, (size_t)d.n_hh * t}, {d.gh, (size_t)d.n_hh * t},
-        {d.gn, (size_t)d.n_hh * t}, {d.g, (size_t)d.n_syn * t}, {d.c, (size_t)d.n_syn * t},
-        {d.h, (size_t)d.n_syn * 8}, {d.z, (size_t)d.n_syn * 8}, {d.p, (size_t)d.n_cells * 8},
-        {d.S, (size_t)d.n_cells * 8}, {d.vdet_old, (size_t)d.n_cells * 8}, {d.post, (size_t)d.n_cells},
-        {d.ev_cnt, (size_t)d.n_syn * 16}, {d.ev_sum, (size_t)d.n_syn * 16},
-        {d.gsum, d.gsum ? (size_t)d.n_cv * 8 : 0}, {d.gesum, d.gesum ? (size_t)d.n_cv * 8 : 0},
-        {d.spk, (size_t)d.n_cells * d.H * sizeof(SpikeRec)}, {d.spk_n, (size_t)d.n_cells * 4},
-        {d.spk_last, (size_t)d.n_cells * 4},
-        {d.blk_done, (size_t)d.n_cells * 8}, {d.bar_grp, 34 * 32 * 4},
-        {d.tr_cur, (size_t)d.n_trains * 16},
-        {d.pois_t, (size_t)d.n_pois * 16}, {d.pois_j, (size_t)d.n_pois * 16},
-        {d.ctr, sizeof(Counters)}};
+    std::vector<Span> spans = mutable_spans(s);
+    spans.push_back({d.blk_done, (size_t)d.n_cells * 8});
+    spans.push_back({d.bar_grp, 34 * 32 * 4});
+    spans.push_back({d.ctr, sizeof(Counters)});
     size_t total = 0;
     for (const Span &x : spans) total += (x.n + 255) & ~size_t(255);
     if (!s->snap) {

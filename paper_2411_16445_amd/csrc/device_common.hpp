@@ -230,9 +230,18 @@ __device__ __forceinline__ T apply_event(const DevNet &d, uint32_t s, uint32_t p
     const uint32_t j = s - sv.base;
     if (port == 1) {
         T dg;
-        if (sc.kind[s - sc.base] == 1) {
+        const uint8_t kind = sc.kind[s - sc.base];
+        if (kind == 1) {
             const double h0 = d.stc.h0;
             dg = (T)(w * ((sv.h[j] + h0 * sv.z[j]) / h0));
+        } else if (kind == 2) {
+            // STDP: the present weight clipped to [0, w_max], then the pre
+            // trace jumps and the weight takes the post trace
+            const double wt = sv.h[j];
+            const double wc = wt < 0.0 ? 0.0 : (wt > d.stdp.w_max ? d.stdp.w_max : wt);
+            dg = (T)(w * wc);
+            sv.c[j] = sv.c[j] + (T)d.stdp.a_pre;
+            sv.h[j] = wt + sv.z[j];
         } else {
             dg = (T)w;
         }
@@ -286,13 +295,21 @@ __device__ inline void record_spike(const DevNet &d, uint32_t cell, uint64_t n, 
 // (step >= n0) and ring entries not yet holding the spike looked for are
 // skipped.  The ring holds every spike that can still be due (sized on the
 // host from the longest delay, a cell fires at most every second step).
-template <class F>
+// COH: the rings were written within the running launch (resident form), so
+// they are read with device-coherent loads; otherwise an earlier launch
+// wrote them and ordinary (cached) loads see them.
+template <bool COH, class U>
+__device__ __forceinline__ U ld_ring(const U *p) {
+    if constexpr (COH) return ld_coh(p);
+    else return *p;
+}
+template <bool COH, class F>
 __device__ __forceinline__ void conn_events(const DevNet &d, uint64_t q, uint64_t n0, uint32_t nst, F &&emit) {
     const uint32_t src = d.in_src[q];
-    const uint32_t last = ld_coh(d.spk_last + src);
+    const uint32_t last = ld_ring<COH>(d.spk_last + src);
     const int64_t lo = (int64_t)n0 - (int64_t)d.in_lag[q];
     if (last == 0 || (int64_t)last - 1 < lo) return;
-    const uint32_t cnt = ld_coh(d.spk_n + src);
+    const uint32_t cnt = ld_ring<COH>(d.spk_n + src);
     const uint32_t stop = cnt > d.H ? cnt - d.H : 0u;
     const uint8_t ports = d.in_ports[q];
     const double dly = d.in_d[q];
@@ -304,12 +321,12 @@ __device__ __forceinline__ void conn_events(const DevNet &d, uint64_t q, uint64_
     const uint64_t n1 = n0 + nst;
     for (uint32_t k = cnt; k-- > stop;) {
         const uint64_t *r = (const uint64_t *)(d.spk + (uint64_t)src * d.H + (k & (d.H - 1)));
-        const uint64_t w1 = ld_coh(r + 1);
+        const uint64_t w1 = ld_ring<COH>(r + 1);
         if ((uint32_t)(w1 >> 32) != k) continue;
         const uint64_t ns = (uint32_t)w1;
         if (ns >= n0) continue;
         if ((int64_t)ns < lo) break;
-        const double ts = __longlong_as_double((long long)ld_coh(r));
+        const double ts = __longlong_as_double((long long)ld_ring<COH>(r));
         const double te = ts + dly;
         if (ports & 1) {
             const uint64_t s = (uint64_t)floor(te / d.dt);
@@ -711,6 +728,19 @@ __device__ inline bool seg_forward(const double *D, const double *B, double *V, 
 // first (after this step's events, as in the sequential definition).  The
 // decayed conductance goes to gout (sv.g itself, or the other half of a
 // double buffer).  Returns |h - h0| of step start (0 for plain synapses).
+// One backward-Euler step of a diffusing species over the CVs b0..b1-1 of
+// a cell whose constant tree system was eliminated beforehand: per CV the
+// coupling u to the parent, the factor f = u / D' and the eliminated
+// diagonal D'.  bx holds the right-hand side (amounts) and is swept in
+// place; X receives the concentrations.  The operations and their order are
+// those of the full elimination.
+__device__ inline void species_sweep(double *bx, double *X, const int32_t *par, const double *f, const double *u,
+                                     const double *dp, uint32_t b0, uint32_t b1) {
+    for (uint32_t i = b1 - 1; i > b0; --i) bx[par[i]] -= f[i] * bx[i];
+    X[b0] = bx[b0] / dp[b0];
+    for (uint32_t i = b0 + 1; i < b1; ++i) X[i] = (bx[i] - u[i] * X[par[i]]) / dp[i];
+}
+
 template <class T>
 struct SynIn {
     T g, dec, c;
@@ -756,10 +786,24 @@ __device__ __forceinline__ void syn_noise(const DevNet &d, uint32_t s, uint64_t 
     if (o.th > 0.0) o.h += noise_increment(d.seed, d.syn_sid[s], n, d.stc.sigma_pl, o.th, d.dt / d.stc.tau_h);
 }
 
+// The STDP synapse's step in place of the tagging-and-capture outputs: the
+// post-synaptic hook (a_post += A_post, w += a_pre), then both traces decay.
 template <class T>
-__device__ __forceinline__ double syn_store(const SynView<T> &sv, uint32_t j, bool stc, const SynOut<T> &o, T *gout) {
+__device__ __forceinline__ void stdp_compute(const DevNet &d, bool post, const SynIn<T> &x, SynOut<T> &o) {
+    const StdpK &P = d.stdp;
+    o.h = post ? x.h + (double)x.c : x.h;
+    const double ap = post ? x.z + P.a_post : x.z;
+    o.z = ap * P.r_post;
+    if constexpr (sizeof(T) == 8) o.c = x.c * (T)P.r_pre;
+    else o.c = x.c * P.r_pre_f;
+    o.absdh = 0.0;
+}
+
+template <class T>
+__device__ __forceinline__ double syn_store(const SynView<T> &sv, uint32_t j, bool plastic, const SynOut<T> &o,
+                                            T *gout) {
     gout[j] = o.g;
-    if (!stc) return 0.0;
+    if (!plastic) return 0.0;
     sv.h[j] = o.h;
     sv.z[j] = o.z;
     sv.c[j] = o.c;
@@ -771,10 +815,11 @@ __device__ inline double syn_update(const DevNet &d, uint32_t s, uint64_t n, dou
                                     const SynView<T> &sv, const SynConst<T> &sc, T *gout) {
     const uint32_t j = s - sv.base, jc = s - sc.base;
     const SynIn<T> x{sv.g[j], sc.decay[jc], sv.c[j], sv.h[j], sv.z[j]};
-    const bool stc = sc.kind[jc] == 1;
+    const uint8_t kind = sc.kind[jc];
     SynOut<T> o = syn_compute<T>(d, p, post, x);
-    if (stc) syn_noise<T>(d, s, n, o);
-    return syn_store<T>(sv, j, stc, o, gout);
+    if (kind == 1) syn_noise<T>(d, s, n, o);
+    if (kind == 2) stdp_compute<T>(d, post, x, o);
+    return syn_store<T>(sv, j, kind != 0, o, gout);
 }
 
 // --------------------------------------------------------------- cells

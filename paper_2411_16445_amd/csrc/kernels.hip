@@ -62,7 +62,7 @@ __global__ void k_gather(DevNet d, uint64_t n0, uint32_t nst) {
     const uint32_t ta = d.tr_cell_off[cell], tb = d.tr_cell_off[cell + 1];
     const uint32_t pa = d.po_cell_off[cell], pb = d.po_cell_off[cell + 1];
     auto count = [&](uint32_t st, const Event &) { atomicAdd(&cnt[st], 1u); };
-    for (uint64_t q = qa + lane; q < qb; q += 64) conn_events(d, q, n0, nst, count);
+    for (uint64_t q = qa + lane; q < qb; q += 64) conn_events<false>(d, q, n0, nst, count);
     for (uint32_t x = ta + lane; x < tb; x += 64) train_events(d, d.tr_by_cell[x], n0, nst, false, count);
     for (uint32_t x = pa + lane; x < pb; x += 64) poisson_events(d, d.po_by_cell[x], n0, nst, false, count);
     wave_sync();
@@ -83,7 +83,7 @@ __global__ void k_gather(DevNet d, uint64_t n0, uint32_t nst) {
         const uint32_t pos = atomicAdd(&cur[st], 1u);
         if (pos < room) Q[pos] = e;
     };
-    for (uint64_t q = qa + lane; q < qb; q += 64) conn_events(d, q, n0, nst, place);
+    for (uint64_t q = qa + lane; q < qb; q += 64) conn_events<false>(d, q, n0, nst, place);
     for (uint32_t x = ta + lane; x < tb; x += 64) train_events(d, d.tr_by_cell[x], n0, nst, true, place);
     for (uint32_t x = pa + lane; x < pb; x += 64) poisson_events(d, d.po_by_cell[x], n0, nst, true, place);
     wave_sync();
@@ -194,20 +194,54 @@ __global__ void k_cellpre(DevNet d) {
 }
 
 // ----------------------------------------------------------------- synapses
+// With particle diffusion, z takes the protein concentration of the
+// synapse's CV, and the step's change of |h - h0| is kept for the release
+// of the synthesis-triggering signal.
 template <class T>
 __global__ void k_syn(DevNet d, uint64_t n) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.n_syn) return;
     const uint32_t cell = d.syn_cell[s];
     const SynView<T> sv = global_syn<T>(d);
-    (void)syn_update<T>(d, s, n, d.p[cell], d.post[cell] != 0, sv, global_const<T>(d), sv.g);
+    const double p = d.dif ? d.prp[d.syn_cv[s]] : d.p[cell];
+    const double a0 = syn_update<T>(d, s, n, p, d.post[cell] != 0, sv, global_const<T>(d), sv.g);
+    if (d.dif) d.dlt[s] = d.syn_kind[s] == 1 ? fabs(d.h[s] - d.stc.h0) - a0 : 0.0;
+}
+
+// ----------------------------------------------------------------- species
+// One lane per cell: the step of both diffusing species (synthesis trigger
+// from the step-start SPS concentration at the soma; SPS with the step's
+// release per CV, the sum over the CV's plastic synapses in (CV, id)
+// order; PRP with decay and synthesis).  d.b serves as the right-hand
+// side (the cable solve is done with it).
+__global__ void k_species(DevNet d) {
+    uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= d.n_cells) return;
+    const uint32_t b0 = d.cv_off[cell], b1 = d.cv_off[cell + 1];
+    const uint32_t soma = d.det_cv[cell];
+    const double trig = (d.sps[soma] - d.dif_thr[cell] > 0.0) ? 1.0 : 0.0;
+    double *bx = d.b;
+    for (uint32_t i = b0; i < b1; ++i) {
+        double r = 0.0;
+        for (uint32_t q = d.cv_syn_off[i]; q < d.cv_syn_off[i + 1]; ++q)
+            if (d.syn_kind[q] == 1) r += d.dlt[q];
+        bx[i] = d.dvol[i] * d.sps[i] + r;
+    }
+    species_sweep(bx, d.sps, d.parent, d.sps_f, d.sps_u, d.sps_dp, b0, b1);
+    const double ap = d.dt / d.stc.tau_p;
+    for (uint32_t i = b0; i < b1; ++i) {
+        const double x = d.prp[i];
+        bx[i] = d.dvol[i] * (x + ap * (-x));
+    }
+    bx[soma] += ap * d.dif_pv[cell] * trig;
+    species_sweep(bx, d.prp, d.parent, d.prp_f, d.prp_u, d.prp_dp, b0, b1);
 }
 
 // ----------------------------------------------------------------- cells
 __global__ void k_cellpost(DevNet d, uint64_t n) {
     uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= d.n_cells) return;
-    d.p[cell] = prp_next(d, d.p[cell], d.S[cell]);
+    if (!d.dif) d.p[cell] = prp_next(d, d.p[cell], d.S[cell]);
     const double v0 = d.vdet_old[cell], v1 = d.V[d.det_cv[cell]];
     const bool fired = crossed(d, v0, v1);
     if (fired) record_spike(d, cell, n, spike_time(d, n, v0, v1));
@@ -232,6 +266,8 @@ __global__ void k_probe(DevNet d, uint64_t n, uint64_t first) {
     case 2: v = (double)((const T *)d.c)[i]; break;
     case 3: v = d.h[i]; break;
     case 4: v = d.z[i]; break;
+    case 6: v = d.sps[i]; break;
+    case 7: v = d.prp[i]; break;
     default: v = d.p[i]; break;
     }
     d.pr_buf[d.pr_off[k] + n / str - first / str - 1] = v;
@@ -254,6 +290,67 @@ __global__ void k_state_out(const void *src, uint32_t words, uint32_t narrow, co
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// ----------------------------------------------------------------- fast-forward
+// n_long long steps of the slow plasticity variables, one wavefront per
+// cell (the cell's S couples its synapses): per step S over the cell's
+// plastic synapses from step-start h (lane l takes synapses l, l+64, ...,
+// then the fixed lane-shift tree), h relaxing to h0 and z from step-start
+// h, z, p (Eqs. 17 and 20 without calcium), conductance and calcium decay
+// by their factors over a long step (gdec per synapse, rc), then p (Eq.
+// 21).  Membrane state is not touched.
+template <class T>
+__global__ void k_fast_forward(DevNet d, uint64_t n_long, double ah, double az, double ap, const double *gdec,
+                               double rc) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t cell = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (cell >= d.n_cells) return;
+    const uint32_t a = d.syn_off[cell], e = d.syn_off[cell + 1];
+    const Stc &P = d.stc;
+    const double h0 = P.h0;
+    T *g = (T *)d.g, *c = (T *)d.c;
+    double p = d.p[cell];
+    for (uint64_t k = 0; k < n_long; ++k) {
+        double S = 0.0;
+        for (uint32_t s = a + lane; s < e; s += 64) S += d.syn_kind[s] == 1 ? fabs(d.h[s] - h0) : 0.0;
+        S = wave_sum(S);
+        for (uint32_t s = a + lane; s < e; s += 64) {
+            g[s] = g[s] * (T)gdec[s];
+            if (d.syn_kind[s] != 1) continue;
+            const double h = d.h[s], z = d.z[s];
+            const double tagp = ((h - h0) - P.theta_tag > 0.0) ? 1.0 : 0.0;
+            const double tagd = ((h0 - h) - P.theta_tag > 0.0) ? 1.0 : 0.0;
+            d.h[s] = h + ah * (0.1 * (h0 - h));
+            d.z[s] = z + az * p * P.f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
+            c[s] = c[s] * (T)rc;
+        }
+        const double trig = (S - P.theta_pro > 0.0) ? 1.0 : 0.0;
+        p = p + ap * (-p + P.p_max * trig);
+    }
+    if (lane == 0) {
+        d.p[cell] = p;
+        d.post[cell] = 0;
+        d.spk_n[cell] = 0;
+        d.spk_last[cell] = 0;
+    }
+}
+
+// After a jump to step n_new: a Poisson source whose next arrival falls
+// before it draws that arrival again (index + 1) from the new time; both
+// port streams continue from the conductance stream's arrival (everything
+// earlier, calcium events included, is dropped).
+__global__ void k_ff_poisson(DevNet d, uint64_t n_new) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n_pois) return;
+    double t = d.pois_t[2 * k];
+    uint64_t j = d.pois_j[2 * k];
+    if (d.pois_rate[k] > 0.0 && floor(t / d.dt) < (double)n_new) {
+        j += 1;
+        t = (double)n_new * d.dt + poisson_isi(d.seed, k, j, d.pois_rate[k]);
+    }
+    d.pois_t[2 * k] = d.pois_t[2 * k + 1] = t;
+    d.pois_j[2 * k] = d.pois_j[2 * k + 1] = j;
 }
 
 // ================================================================= launchers
@@ -288,6 +385,7 @@ static int step_plain(const DevNet &d, uint64_t n, uint64_t n0, hipStream_t s, h
     if (e0) (void)hipEventRecord(e0, s);
     if (d.n_syn) hipLaunchKernelGGL(k_syn<T>, grid_for(d.n_syn, 256), b, 0, s, d, n);
     if (e1) (void)hipEventRecord(e1, s);
+    if (d.dif) hipLaunchKernelGGL(k_species, grid_for(d.n_cells, 64), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_cellpost, grid_for(d.n_cells, 256), b, 0, s, d, n);
     return (int)hipGetLastError();
 }
@@ -312,6 +410,20 @@ int launch_state_out(const void *src, uint32_t words, bool narrow, const uint32_
     if (n == 0) return 0;
     hipLaunchKernelGGL(k_state_out, grid_for(n, 256), dim3(256), 0, (hipStream_t)stream, src, words,
                        narrow ? 1u : 0u, perm, n, dst);
+    return (int)hipGetLastError();
+}
+
+int launch_fast_forward(const DevNet &d, uint64_t n_long, double dt_long, const double *gdec, double rc,
+                        uint64_t n_new, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const double ah = dt_long / d.stc.tau_h, az = dt_long / d.stc.tau_z, ap = dt_long / d.stc.tau_p;
+    if (d.mixed)
+        hipLaunchKernelGGL(k_fast_forward<float>, grid_for((uint64_t)d.n_cells * 64, 256), dim3(256), 0, s, d, n_long,
+                           ah, az, ap, gdec, rc);
+    else
+        hipLaunchKernelGGL(k_fast_forward<double>, grid_for((uint64_t)d.n_cells * 64, 256), dim3(256), 0, s, d, n_long,
+                           ah, az, ap, gdec, rc);
+    if (d.n_pois) hipLaunchKernelGGL(k_ff_poisson, grid_for(d.n_pois, 256), dim3(256), 0, s, d, n_new);
     return (int)hipGetLastError();
 }
 

@@ -51,12 +51,19 @@ struct FusedLayout {
     uint32_t V, D, B, Ax, D0, Cdt, Gpe, DecCv, H, Z, Erev, P, Vold, Cu, Cb, HHp;
     // mixed form: per-CV conductance sums (two halves)
     uint32_t Gs, GsE;
+    // particle diffusion: per CV both species, the volume, both species'
+    // factors and a right-hand side; per synapse the change of |h - h0|;
+    // per cell the soma threshold and synthesis amount
+    uint32_t Sps, Prp, Dvol, SpsU, SpsF, SpsDp, PrpU, PrpF, PrpDp, Bx, Dlt, DThr, DPv;
     // T
     uint32_t G, C, Dec, M, HH, N;
     // 32-bit
     uint32_t Par, HHk, CvSyn, CvCl, Cb0, Cs0, Cg0, Ch0, Det, HHcv, EvN, EvOff, Scan;
     // events of the epoch, each slot's records sorted into delivery order
     uint32_t EvBuf, ev_cap;
+    // incoming connections whose source spiked recently enough to matter
+    // (offsets into the workgroup's connection range)
+    uint32_t Act, act_cap;
     // 16-bit, 8-bit
     uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, Kind, Post, SegLvl;
     uint32_t total;
@@ -67,7 +74,7 @@ struct FusedLayout {
     // per-CV synapse ranges stay in global memory
     bool lean, carried;
     __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
-                                    uint32_t tsize, uint32_t ng, bool carried_sums) {
+                                    uint32_t tsize, uint32_t ng, bool carried_sums, bool dif, uint32_t nq) {
         lean = tsize == 4 && ng == nc && nv <= 64 * CHAIN_ROWS;
         carried = tsize == 4 && carried_sums;
         const uint32_t nvd = lean ? 0 : nv, nse = carried ? 0 : ns;
@@ -86,16 +93,23 @@ struct FusedLayout {
         Cu = take(8 * ng, 8); Cb = take(8 * ng, 8); HHp = take(8 * 7 * nh, 8);
         const uint32_t nm = tsize == 4 ? nv : 0;
         Gs = take(16 * nm, 8); GsE = take(16 * nm, 8);
+        const uint32_t nvf = dif ? nv : 0, nsf = dif ? ns : 0, ncf = dif ? nc : 0;
+        Sps = take(8 * nvf, 8); Prp = take(8 * nvf, 8); Dvol = take(8 * nvf, 8);
+        SpsU = take(8 * nvf, 8); SpsF = take(8 * nvf, 8); SpsDp = take(8 * nvf, 8);
+        PrpU = take(8 * nvf, 8); PrpF = take(8 * nvf, 8); PrpDp = take(8 * nvf, 8);
+        Bx = take(8 * nvf, 8); Dlt = take(8 * nsf, 8); DThr = take(8 * ncf, 8); DPv = take(8 * ncf, 8);
         G = take((carried ? 1 : 2) * tsize * ns, 8); C = take(tsize * ns, 8); Dec = take(tsize * ns, 8);
         M = take(tsize * nh, 8); HH = take(tsize * nh, 8); N = take(tsize * nh, 8);
         Par = take(4 * nv, 4); HHk = take(4 * nv, 4); CvSyn = take(carried ? 0 : 4 * (nv + 1), 4);
         CvCl = take(4 * (nv + 1), 4); Cb0 = take(4 * (nc + 1), 4); Cs0 = take(4 * (nc + 1), 4);
         Cg0 = take(4 * (nc + 1), 4); Ch0 = take(4 * (nc + 1), 4);
         Det = take(4 * nc, 4); HHcv = take(4 * nh, 4); EvN = take(4 * nc * K, 4);
-        EvOff = take(4 * nc * K, 4); Scan = take(16, 4);
+        EvOff = take(4 * nc * K, 4); Scan = take(32, 4);
+        act_cap = nq < 2048u ? nq : 2048u;
+        Act = take(4 * act_cap, 4);
         ev_cap = 2 * nc * K + 32;
         EvBuf = take(32 * ev_cap, 16);
-        SynCv = take(2 * (tsize == 4 ? ns : 0), 2);
+        SynCv = take(2 * ((tsize == 4 || dif) ? ns : 0), 2);
         SegA = take(2 * ng, 2); SegB = take(2 * ng, 2); SegCell = take(2 * ng, 2);
         KidOff = take(2 * (ng + 1), 2); Kids = take(2 * ng, 2);
         Kind = take(ns, 1); Post = take(2 * nc, 1); SegLvl = take(ng, 1);
@@ -103,18 +117,6 @@ struct FusedLayout {
     }
 };
 
-#ifdef PA_STAGE_TIMING
-// Diagnostic build only: wall-clock ticks per stage, summed over the solver
-// wavefronts (entries 0-7) and the synapse wavefronts (8-15).
-__device__ unsigned long long pa_stage_ticks[24];
-#define STAGE_INIT() uint64_t st_prev_ = wall_clock64(); uint64_t st_acc_[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}
-#define STAGE_MARK(k_) do { if (lane == 0) { const uint64_t t_ = wall_clock64(); st_acc_[k_] += t_ - st_prev_; st_prev_ = t_; } } while (0)
-#define STAGE_FLUSH() do { if (lane == 0) for (int k_ = 0; k_ < 12; ++k_) atomicAdd(&pa_stage_ticks[k_ + (solver ? 0 : 12)], (unsigned long long)st_acc_[k_]); } while (0)
-#else
-#define STAGE_INIT() do {} while (0)
-#define STAGE_MARK(k_) do {} while (0)
-#define STAGE_FLUSH() do {} while (0)
-#endif
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
 #pragma unroll
@@ -346,11 +348,34 @@ __device__ bool grid_sync(const DevNet &d, uint32_t nblocks, uint32_t *ok_word) 
 // cells (V, gates, g, c, h, z, p, post flag), their constants and the
 // epoch's events live in LDS, so a step touches global memory only for
 // spikes, clamps and rare noise keys.
-#ifdef PA_MIN_WAVES_PER_EU
-#define PA_EPOCH_BOUNDS(BS_) __launch_bounds__(BS_, PA_MIN_WAVES_PER_EU)
-#else
 #define PA_EPOCH_BOUNDS(BS_) __launch_bounds__(BS_)
-#endif
+// The incoming connections in [qa, qb) whose source's last spike is recent
+// enough to bring events from step n0 on (its step at least n0 minus the
+// connection's lag) are appended to act (offsets from qa) through the
+// counter cnt; beyond cap only counted.  Each lane loads the operands of
+// four connections before it tests any of them.
+template <bool COH, uint32_t BS>
+__device__ __forceinline__ void screen_conns(const DevNet &d, uint64_t qa, uint64_t qb, uint64_t n0, uint32_t tid,
+                                             uint32_t *act, uint32_t cap, uint32_t *cnt) {
+    for (uint64_t q0 = qa + tid; q0 < qb; q0 += 4 * BS) {
+        uint32_t src[4], lag[4], last[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t q = q0 + (uint64_t)j * BS;
+            src[j] = q < qb ? d.in_src[q] : 0u;
+            lag[j] = q < qb ? d.in_lag[q] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) last[j] = (q0 + (uint64_t)j * BS < qb) ? ld_ring<COH>(d.spk_last + src[j]) : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (last[j] == 0 || (int64_t)last[j] - 1 < (int64_t)n0 - (int64_t)lag[j]) continue;
+            const uint32_t pos = atomicAdd(cnt, 1u);
+            if (pos < cap) act[pos] = (uint32_t)(q0 + (uint64_t)j * BS - qa);
+        }
+    }
+}
+
 template <class T, uint32_t BS>
 __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict__ blk, uint32_t nsteps,
                                               uint32_t resident, uint32_t solver_waves) {
@@ -375,7 +400,9 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     // are carried from step to step (decayed, plus each event's increment)
     // instead of being summed again
     const bool carry_sums = !EXACT && d.cv_dec_uniform != 0;
-    const FusedLayout lay(nv, ns, nhh, ncb, K, sizeof(T), ng, carry_sums);
+    const bool dif = d.dif != 0;
+    const uint32_t nq = (uint32_t)(d.in_off[c1] - d.in_off[c0]);
+    const FusedLayout lay(nv, ns, nhh, ncb, K, sizeof(T), ng, carry_sums, dif, nq);
     // offset of conductance half h (one buffer when the sums are carried)
     auto gofs = [&](uint32_t h) { return lay.carried ? 0u : h * ns; };
     double *sV = (double *)(L + lay.V), *sD = (double *)(L + lay.D), *sB = (double *)(L + lay.B);
@@ -395,12 +422,18 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     uint32_t *sDet = (uint32_t *)(L + lay.Det), *sHHcv = (uint32_t *)(L + lay.HHcv);
     uint32_t *sEvN = (uint32_t *)(L + lay.EvN), *sEvOff = (uint32_t *)(L + lay.EvOff);
     uint32_t *sScan = (uint32_t *)(L + lay.Scan);
+    uint32_t *sAct = (uint32_t *)(L + lay.Act);
     uint8_t *sKind = L + lay.Kind, *sPost = L + lay.Post, *sSegLvl = L + lay.SegLvl;
     double *sCu = (double *)(L + lay.Cu), *sCb = (double *)(L + lay.Cb), *sHHp = (double *)(L + lay.HHp);
     uint16_t *sSegA = (uint16_t *)(L + lay.SegA), *sSegB = (uint16_t *)(L + lay.SegB);
     uint16_t *sSegCell = (uint16_t *)(L + lay.SegCell), *sKidOff = (uint16_t *)(L + lay.KidOff);
     uint16_t *sKids = (uint16_t *)(L + lay.Kids);
     Event *sEv = (Event *)(L + lay.EvBuf);
+    double *sSps = (double *)(L + lay.Sps), *sPrp = (double *)(L + lay.Prp), *sDvol = (double *)(L + lay.Dvol);
+    double *sSpsU = (double *)(L + lay.SpsU), *sSpsF = (double *)(L + lay.SpsF), *sSpsDp = (double *)(L + lay.SpsDp);
+    double *sPrpU = (double *)(L + lay.PrpU), *sPrpF = (double *)(L + lay.PrpF), *sPrpDp = (double *)(L + lay.PrpDp);
+    double *sBx = (double *)(L + lay.Bx), *sDlt = (double *)(L + lay.Dlt);
+    double *sDThr = (double *)(L + lay.DThr), *sDPv = (double *)(L + lay.DPv);
     // blocks whose cells are all unbranched (one segment per cell)
     const bool chains = (ng == ncb);
     const SynConst<T> sc{sErev, sDec, sKind, s0};
@@ -414,7 +447,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     // workgroup's queue in global memory
     Event *gEv = d.q_ev + d.q_off[c0];
     const uint64_t groom = d.q_off[c1] - d.q_off[c0];
-    STAGE_INIT();
 
     // ---- stage in: state, constants, this epoch's events
     for (uint32_t i = tid; i < nv; i += BS) {
@@ -434,6 +466,17 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             sGs[i] = d.gsum[g];
             sGsE[i] = d.gesum[g];
         }
+        if (dif) {
+            sSps[i] = d.sps[g];
+            sPrp[i] = d.prp[g];
+            sDvol[i] = d.dvol[g];
+            sSpsU[i] = d.sps_u[g];
+            sSpsF[i] = d.sps_f[g];
+            sSpsDp[i] = d.sps_dp[g];
+            sPrpU[i] = d.prp_u[g];
+            sPrpF[i] = d.prp_f[g];
+            sPrpDp[i] = d.prp_dp[g];
+        }
         if (i == nv - 1) {
             if (!lay.carried) sCvSyn[nv] = d.cv_syn_off[g + 1];
             sCvCl[nv] = d.cv_cl_off[g + 1];
@@ -449,7 +492,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         if constexpr (EXACT) sDec[s] = (T)d.syn_decay[q];
         else sDec[s] = d.syn_decay_f[q];
         sKind[s] = d.syn_kind[q];
-        if constexpr (!EXACT) sSynCv[s] = (uint16_t)(d.syn_cv[q] - v0);
+        if (!EXACT || dif) sSynCv[s] = (uint16_t)(d.syn_cv[q] - v0);
     }
     for (uint32_t k = tid; k < nhh; k += BS) {
         sM[k] = ((const T *)d.gm)[k0 + k];
@@ -468,6 +511,10 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             sP[c] = d.p[c0 + c];
             sPost[c] = d.post[c0 + c];
             sDet[c] = d.det_cv[c0 + c] - v0;
+            if (dif) {
+                sDThr[c] = d.dif_thr[c0 + c];
+                sDPv[c] = d.dif_pv[c0 + c];
+            }
         }
     }
     for (uint32_t g = tid; g < ng; g += BS) {
@@ -550,7 +597,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         }
     };
 
-    STAGE_MARK(6);
     const uint32_t n_total = nsteps;
     for (uint32_t done = 0; done < n_total;) {
     n0 = nbase + done;
@@ -570,9 +616,27 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     const uint64_t qa = d.in_off[c0], qb = d.in_off[c1];
     const uint32_t ta = d.tr_cell_off[c0], tb = d.tr_cell_off[c1];
     const uint32_t pa = d.po_cell_off[c0], pb = d.po_cell_off[c1];
+    // screening: the incoming connections whose source spiked recently
+    // enough to matter, listed once (their loads issued four at a time), so
+    // that the counting and scatter passes visit only those
+    if (tid == 0) sScan[4] = 0;
+    __syncthreads();
+    if (multi) screen_conns<true, BS>(d, qa, qb, n0, tid, sAct, lay.act_cap, sScan + 4);
+    else screen_conns<false, BS>(d, qa, qb, n0, tid, sAct, lay.act_cap, sScan + 4);
+    __syncthreads();
+    const uint32_t nact = sScan[4];
+    const bool act_ok = nact <= lay.act_cap;
+    // visits fn(q) for every incoming connection that can bring an event
+    auto each_conn = [&](auto &&fn) {
+        if (act_ok)
+            for (uint32_t i = tid; i < nact; i += BS) fn(qa + sAct[i]);
+        else
+            for (uint64_t q = qa + tid; q < qb; q += BS) fn(q);
+    };
     {
         auto count = [&](uint32_t st, const Event &e) { atomicAdd(&sEvN[(d.syn_cell[e.syn] - c0) * K + st], 1u); };
-        for (uint64_t q = qa + tid; q < qb; q += BS) conn_events(d, q, n0, nst, count);
+        if (multi) each_conn([&](uint64_t q) { conn_events<true>(d, q, n0, nst, count); });
+        else each_conn([&](uint64_t q) { conn_events<false>(d, q, n0, nst, count); });
         for (uint32_t x = ta + tid; x < tb; x += BS) train_events(d, d.tr_by_cell[x], n0, nst, false, count);
         for (uint32_t x = pa + tid; x < pb; x += BS) poisson_events(d, d.po_by_cell[x], n0, nst, false, count);
     }
@@ -602,12 +666,12 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             const uint32_t pos = atomicAdd(&sEvOff[(d.syn_cell[e.syn] - c0) * K + st], 1u);
             if (pos < room) evb[pos] = e;
         };
-        for (uint64_t q = qa + tid; q < qb; q += BS) conn_events(d, q, n0, nst, place);
+        if (multi) each_conn([&](uint64_t q) { conn_events<true>(d, q, n0, nst, place); });
+        else each_conn([&](uint64_t q) { conn_events<false>(d, q, n0, nst, place); });
         for (uint32_t x = ta + tid; x < tb; x += BS) train_events(d, d.tr_by_cell[x], n0, nst, true, place);
         for (uint32_t x = pa + tid; x < pb; x += BS) poisson_events(d, d.po_by_cell[x], n0, nst, true, place);
     }
     __syncthreads();
-    STAGE_MARK(9);
     for (uint32_t x = tid; x < nslot; x += BS) {
         const uint32_t c = x / nst, st = x - c * nst;
         const uint32_t cnt = sEvN[c * K + st];
@@ -628,7 +692,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         }
     }
     __syncthreads();
-    STAGE_MARK(10);
 
     // the first step's events, and its conductance sums (carried sums
     // enter the epoch already decayed to this step)
@@ -643,7 +706,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         }
     }
     __syncthreads();
-    STAGE_MARK(11);
 
     // one step of each role (n = n0 + st); the roles run in separate loops
     // so that each loop keeps only its own role's values live
@@ -674,7 +736,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             for (uint32_t i = wva + lane; i < wvb; i += 64) row(i, sD[i], sB[i]);
         }
         wave_sync();
-        STAGE_MARK(0);
         // the cable solve of the share's cells
         if (wva == wvb) {
             // no cells of this share
@@ -721,7 +782,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             }
         }
         wave_sync();
-        STAGE_MARK(1);
         // HH gates at V^{n+1}, one lane per gate (the three gates of a
         // CV are independent), and threshold detection
         for (uint32_t t = lane; t < 3 * (whb - wha); t += 64) {
@@ -735,7 +795,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             if (fired) record_spike(d, c0 + c, n, spike_time(d, n, v0, v1));
             postn[c] = fired ? 1 : 0;
         }
-        STAGE_MARK(2);
         };
     auto synapse_step = [&](uint32_t st) {
         const uint64_t n = n0 + st;
@@ -757,18 +816,51 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
                 const uint32_t s2 = two ? s + 64 : s;
                 const SynIn<T> x1{gc[s], sDec[s], sC[s], sH[s], sZ[s]};
                 const SynIn<T> x2{gc[s2], sDec[s2], sC[s2], sH[s2], sZ[s2]};
-                const bool k1 = sKind[s] == 1, k2 = sKind[s2] == 1;
-                SynOut<T> o1 = syn_compute<T>(d, p, post, x1);
-                SynOut<T> o2 = syn_compute<T>(d, p, post, x2);
+                const uint8_t kd1 = sKind[s], kd2 = sKind[s2];
+                const bool k1 = kd1 == 1, k2 = kd2 == 1;
+                // with diffusion, z takes the protein of the synapse's CV
+                const double p1 = dif ? sPrp[sSynCv[s]] : p, p2 = dif ? sPrp[sSynCv[s2]] : p;
+                SynOut<T> o1 = syn_compute<T>(d, p1, post, x1);
+                SynOut<T> o2 = syn_compute<T>(d, p2, post, x2);
                 if (k1) syn_noise<T>(d, s0 + s, n, o1);
                 if (two && k2) syn_noise<T>(d, s0 + s2, n, o2);
-                S += syn_store<T>(svc, s, k1, o1, gn);
-                if (two) S += syn_store<T>(svc, s2, k2, o2, gn);
+                if (kd1 == 2) stdp_compute<T>(d, post, x1, o1);
+                if (kd2 == 2) stdp_compute<T>(d, post, x2, o2);
+                if (dif) {
+                    sDlt[s] = k1 ? fabs(o1.h - d.stc.h0) - o1.absdh : 0.0;
+                    if (two) sDlt[s2] = k2 ? fabs(o2.h - d.stc.h0) - o2.absdh : 0.0;
+                }
+                S += syn_store<T>(svc, s, kd1 != 0, o1, gn);
+                if (two) S += syn_store<T>(svc, s2, kd2 != 0, o2, gn);
             }
-            S = wave_sum(S);
-            if (lane == 0) sP[c] = prp_next(d, p, S);
+            if (!dif) {
+                S = wave_sum(S);
+                if (lane == 0) sP[c] = prp_next(d, p, S);
+            }
         }
-        STAGE_MARK(3);
+        if (dif) {
+            // both diffusing species of the share's cells, one lane per
+            // cell: the trigger from the step-start SPS at the soma, the
+            // release per CV (its plastic synapses in (CV, id) order), the
+            // SPS sweep, then the protein's decay, synthesis and sweep
+            wave_sync();
+            for (uint32_t c = uc0 + lane; c < uc1; c += 64) {
+                const uint32_t b0 = sCb0[c], b1 = sCb0[c + 1], soma = sDet[c];
+                const double trig = (sSps[soma] - sDThr[c] > 0.0) ? 1.0 : 0.0;
+                for (uint32_t i = b0; i < b1; ++i) sBx[i] = 0.0;
+                for (uint32_t q = sCs0[c]; q < sCs0[c + 1]; ++q)
+                    if (sKind[q] == 1) sBx[sSynCv[q]] += sDlt[q];
+                for (uint32_t i = b0; i < b1; ++i) sBx[i] = sDvol[i] * sSps[i] + sBx[i];
+                species_sweep(sBx, sSps, sPar, sSpsF, sSpsU, sSpsDp, b0, b1);
+                const double ap = d.dt / d.stc.tau_p;
+                for (uint32_t i = b0; i < b1; ++i) {
+                    const double x = sPrp[i];
+                    sBx[i] = sDvol[i] * (x + ap * (-x));
+                }
+                sBx[soma] += ap * sDPv[c] * trig;
+                species_sweep(sBx, sPrp, sPar, sPrpF, sPrpU, sPrpDp, b0, b1);
+            }
+        }
         // carried sums decay to the next step also after an epoch's last
         // step (the next epoch, or launch, starts from them)
         if (lay.carried) {
@@ -785,25 +877,21 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
                 cv_sums(gn, nxt);
             }
         }
-        STAGE_MARK(4);
     };
     // halves of the double buffers alternate over the steps of the launch
     if (NW == 1) {
         for (uint32_t st = 0; st < nst; ++st) {
-            STAGE_MARK(5);
             solver_step(st);
             synapse_step(st);
             __syncthreads();
         }
     } else if (solver) {
         for (uint32_t st = 0; st < nst; ++st) {
-            STAGE_MARK(5);
             solver_step(st);
             __syncthreads();
         }
     } else {
         for (uint32_t st = 0; st < nst; ++st) {
-            STAGE_MARK(5);
             synapse_step(st);
             __syncthreads();
         }
@@ -813,11 +901,9 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         // the epoch's spikes are in their cells' rings; every workgroup
         // waits for all the others before the next epoch gathers from them
         const bool ok = grid_sync(d, gridDim.x, sScan + 2);
-        STAGE_MARK(8);
         if (!ok) break;
     }
     }
-    STAGE_MARK(5);
     // ---- stage out
     const uint32_t hfin = n_total & 1u;
     const T *gfin = sG + gofs(hfin);
@@ -827,6 +913,10 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
         if (lay.carried) {
             d.gsum[v0 + i] = sGs[hfin * nv + i];
             d.gesum[v0 + i] = sGsE[hfin * nv + i];
+        }
+        if (dif) {
+            d.sps[v0 + i] = sSps[i];
+            d.prp[v0 + i] = sPrp[i];
         }
     }
     for (uint32_t s = tid; s < ns; s += BS) {
@@ -862,8 +952,6 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             }
         }
     }
-    STAGE_MARK(7);
-    STAGE_FLUSH();
 }
 
 // Carried per-CV sums from the conductances (mixed form), one lane per CV,
@@ -940,17 +1028,6 @@ uint32_t epoch_fused_capacity(bool mixed, uint32_t block_threads, size_t lds_byt
 
 }  // namespace pa
 
-#ifdef PA_STAGE_TIMING
-extern "C" int pa_debug_stage_ticks(unsigned long long *out, int reset) {
-    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(pa::pa_stage_ticks), 24 * sizeof(unsigned long long)) != hipSuccess)
-        return -1;
-    if (reset) {
-        unsigned long long z[24] = {};
-        if (hipMemcpyToSymbol(HIP_SYMBOL(pa::pa_stage_ticks), z, sizeof z) != hipSuccess) return -1;
-    }
-    return 0;
-}
-#endif
 
 // ======================================================================
 // Host side of the batched form.
@@ -984,8 +1061,10 @@ constexpr size_t LDS_MAX = 160 * 1024;
 
 struct Offsets {
     std::vector<uint32_t> cv, syn, hh, seg;
+    std::vector<uint64_t> in;  // incoming connections per cell (offsets)
     uint32_t tsize, K;
     bool carried;  // mixed form with carried per-CV sums
+    bool dif;      // particle diffusion
 };
 
 // Packs consecutive cells, at most cpb per workgroup, within an LDS budget
@@ -995,7 +1074,8 @@ bool pack(const Offsets &o, uint32_t cpb, uint32_t threads, std::vector<uint32_t
     const uint32_t nc = (uint32_t)o.cv.size() - 1;
     auto bytes = [&](uint32_t a, uint32_t e) {
         return (size_t)FusedLayout(o.cv[e] - o.cv[a], o.syn[e] - o.syn[a], o.hh[e] - o.hh[a], e - a, o.K,
-                                   o.tsize, o.seg[e] - o.seg[a], o.carried).total;
+                                   o.tsize, o.seg[e] - o.seg[a], o.carried, o.dif,
+                                   (uint32_t)(o.in[e] - o.in[a])).total;
     };
     blk.assign(1, 0);
     lds = 0;
@@ -1058,9 +1138,12 @@ pa_status batched_setup(pa_sim *s) {
     o.hh.resize(d.n_cells + 1);
     o.tsize = d.mixed ? 4 : 8;
     o.K = d.K;
+    o.dif = d.dif != 0;
     o.carried = d.mixed && d.cv_dec_uniform;
     o.seg.resize(d.n_cells + 1);
-    if (hipMemcpy(o.seg.data(), d.seg_off, o.seg.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+    o.in.resize(d.n_cells + 1);
+    if (hipMemcpy(o.in.data(), d.in_off, o.in.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(o.seg.data(), d.seg_off, o.seg.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(o.cv.data(), d.cv_off, o.cv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(o.syn.data(), d.syn_off, o.syn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(o.hh.data(), d.hh_off, o.hh.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
@@ -1152,10 +1235,6 @@ pa_status batched_setup(pa_sim *s) {
         (void)hipEventElapsedTime(&ms, a, b);
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
-        if (getenv("PA_AUTOTUNE_VERBOSE"))
-            fprintf(stderr,
-                    "[autotune] threads %u cells/block %u solver waves %u %s blocks %zu lds %zu: %.3f ms / 4 epochs\n",
-                    cd.threads, cd.cpb, cd.sw, tr.multi ? "resident" : "kernel-exchange", P.blk.size() - 1, P.lds, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = tr;

@@ -61,6 +61,13 @@ struct Stc {
     double sigma_pl, p_max, f_int, t_cd, h0, theta_pro, theta_tag, c_pre, c_post;
 };
 
+// Pair-based STDP (synapse kind 2): trace jumps, weight clip and the
+// traces' decay factors per step.
+struct StdpK {
+    double a_pre, a_post, w_max, r_pre, r_post;
+    float r_pre_f;
+};
+
 // Everything a kernel needs, passed by value.
 struct DevNet {
     uint32_t n_cells, n_cv, n_syn, n_hh, n_trains, n_probes;
@@ -70,6 +77,7 @@ struct DevNet {
     double dt, theta;
     uint64_t seed;
     Stc stc;
+    StdpK stdp;
     double r_c;          // exp(-dt / tau_c)
     float r_c_f;
 
@@ -171,6 +179,21 @@ struct DevNet {
     uint64_t hist_cap;
     Counters *ctr;
 
+    // particle diffusion (Eq. 5) of the signal triggering protein synthesis
+    // (SPS) and of the protein (PRP) over each cell's CVs, in place of the
+    // per-cell trigger sum and p (dif = 0: off).  Both species' tree
+    // systems are constant, so their elimination is done once on the host:
+    // per CV the coupling to the parent (u), the elimination factor
+    // u / D' and the eliminated diagonal D'; a step only sweeps the
+    // right-hand side.
+    uint32_t dif;
+    const double *dvol;                       // CV volume, um^3
+    const double *sps_u, *sps_f, *sps_dp;
+    const double *prp_u, *prp_f, *prp_dp;
+    const double *dif_thr, *dif_pv;           // per cell: theta_pro / V_tot, p_max V_tot
+    double *sps, *prp;                        // per CV concentrations (state)
+    double *dlt;                              // per synapse: change of |h - h0| in the step (plain form)
+
     // probes: probe k samples after every pr_stride[k]-th step into its
     // own region of pr_buf starting at pr_off[k]
     const int32_t *pr_what;
@@ -206,6 +229,12 @@ uint32_t epoch_fused_capacity(bool mixed, uint32_t block_threads, size_t lds_byt
 // written from the host).
 int launch_carried_sums(const DevNet &d, void *stream);
 int launch_fill_u32(uint32_t *p, uint32_t v, size_t n, void *stream);
+// Fast-forward: n_long long steps of the slow plasticity variables (gdec:
+// per sorted synapse the conductance decay over a long step, rc the
+// calcium's), clearing post flags and spike rings; Poisson sources restart
+// from step n_new.
+int launch_fast_forward(const DevNet &d, uint64_t n_long, double dt_long, const double *gdec, double rc,
+                        uint64_t n_new, void *stream);
 // Copies n elements of a state array (words 64-bit words each, or FP32
 // widened to FP64) to dst, element q to position perm[q] (perm may be null).
 int launch_state_out(const void *src, uint32_t words, bool narrow, const uint32_t *perm, uint64_t n, void *dst,

@@ -1,0 +1,163 @@
+"""GPU parity of the particle-diffusion protein model (Eq. 5; the SPS / PRP
+formulation of Sec. 3.6 with the threshold of Eq. 23) against the oracle,
+through the C ABI: rasters identical, voltages to the FP64 bar, h, z and
+both species' concentrations within 1e-9 relative, on tiny networks with
+several cells per CV tree, on the full-size E/I network of the Table 6
+neurons, in both forms and every batched launch shape."""
+import numpy as np
+import pytest
+
+import netgen
+import oracle
+from _parity import assert_raster_equal, assert_routing_equal, assert_state_close
+from paper_2411_16445_amd import PAError, Simulation
+from paper_2411_16445_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _seed(net, sims, seed=4):
+    """Non-trivial plastic and species state on both sides: h over both tag
+    signs, calcium over both thresholds (h moves, SPS is released), SPS
+    around the synthesis threshold (PRP is made in some cells), PRP
+    spread over the CVs."""
+    rng = np.random.default_rng(seed)
+    kinds = net["syn_kind"] == 1
+    n = len(kinds)
+    h0 = net["stc"]["h0"]
+    h = np.where(kinds, rng.uniform(h0 - 2.5, h0 + 2.5, n), h0)
+    z = np.where(kinds, rng.uniform(-0.4, 0.9, n), 0.0)
+    c = np.where(kinds, rng.uniform(0.0, 5.0, n), 0.0)
+    r = 0.5 * net["diam"]
+    vol = np.pi * r * r * net["length"]
+    vtot = np.add.reduceat(vol, net["cv_off"][:-1])
+    cell_of_cv = np.repeat(np.arange(net["n_cells"]), np.diff(net["cv_off"]))
+    thr = (net["stc"]["theta_pro"] / vtot)[cell_of_cv]
+    sps = thr * rng.uniform(0.0, 2.0, len(vol))
+    prp = rng.uniform(0.0, 6.0, len(vol))
+    for x in sims:
+        x.write("h", h)
+        x.write("z", z)
+        x.write("c", c)
+        x.write("sps", sps)
+        x.write("prp", prp)
+
+
+def _compare(o, s, rtol=1e-9):
+    assert_state_close(o, s)
+    for k in ("sps", "prp"):
+        want = o.read(k)
+        np.testing.assert_allclose(s.read(k), want, rtol=rtol, atol=1e-15 + rtol * np.abs(want).max(), err_msg=k)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+@pytest.mark.parametrize("seed", [3, 8])
+def test_tiny_networks_with_diffusion_match_oracle(seed, mode):
+    net = netgen.with_diffusion(netgen.tiny(seed=seed, n_cells=13, t_end=200.0), d_sps=4.0, d_prp=1.5)
+    _say(f"diffusion tiny seed={seed} mode={mode}")
+    o = oracle.Oracle(net)
+    s = Simulation(net, mode=mode)
+    _seed(net, (o, s))
+    prp0 = o.read("prp")
+    for m in (300, 350, 350):
+        o.run(m)
+        s.advance_steps(m)
+    assert assert_raster_equal(o, s) > 10
+    assert_routing_equal(o, s)
+    _compare(o, s)
+    assert np.abs(o.read("prp") - prp0).max() > 1e-6  # the protein moved
+
+
+def test_diffusion_in_every_launch_shape_is_bitwise_the_plain_form():
+    """The batched FP64 form with diffusion gives the plain form's bits in
+    every workgroup packing, wavefront split and exchange mode."""
+    net = netgen.with_diffusion(netgen.tiny(seed=8, n_cells=23, t_end=150.0), d_sps=4.0, d_prp=1.5)
+    ref = Simulation(net, mode="plain")
+    _seed(net, (ref,))
+    ref.advance_steps(700)
+    want = [ref.read(k) for k in ("V", "h", "z", "g", "c", "sps", "prp")]
+    shapes = [dict(exchange="kernel", cells_per_block=1, block_threads=64),
+              dict(exchange="kernel", cells_per_block=4, block_threads=256, solver_waves=2),
+              dict(exchange="resident", cells_per_block=4, block_threads=128, solver_waves=1)]
+    for shape in shapes:
+        _say(f"diffusion shape {shape}")
+        s = Simulation(net, mode="batched", **shape)
+        _seed(net, (s,))
+        s.advance_steps(350)
+        s.advance_steps(350)
+        for a, b in zip(ref.spikes(), s.spikes()):
+            np.testing.assert_array_equal(a, b)
+        for a, k in zip(want, ("V", "h", "z", "g", "c", "sps", "prp")):
+            np.testing.assert_array_equal(a, s.read(k), err_msg=k)
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_table6_network_with_diffusion_full_size(mode):
+    """2000 cells of the Table 6 morphology (31 CVs: a 13-CV soma with the
+    synthesis compartment in its middle, apical and basal dendrites), E->E
+    plastic on the basal tips, with a learning stimulus on 150 cells and a
+    seeded plastic state, 60 ms at full size."""
+    net = netgen.stc_morpho_network(t_end=200.0, d_sps=1.0, d_prp=0.5, stim_n=150, stim_rate=2000.0,
+                                    stim_t0=2.0, stim_dur=100.0)
+    _say(f"table6 network diffusion 300 steps mode={mode}")
+    o = oracle.Oracle(net)
+    s = Simulation(net, mode=mode)
+    _seed(net, (o, s))
+    for _ in range(2):
+        o.run(150)
+        s.advance_steps(150)
+    assert assert_raster_equal(o, s) > 100
+    assert_routing_equal(o, s)
+    _compare(o, s)
+
+
+def test_diffusion_probes_and_errors():
+    net = netgen.with_diffusion(netgen.tiny(seed=5, n_cells=7, t_end=100.0), d_sps=2.0, d_prp=2.0)
+    cv = int(net["cv_off"][3]) + 1
+    _say("diffusion probes")
+    s = Simulation(net, probes=[("sps", cv, 2), ("prp", 0, 5)])
+    o = oracle.Oracle(net)
+    _seed(net, (o, s))
+    want_s, want_p = [], []
+    for n in range(1, 101):
+        o.run(1)
+        if n % 2 == 0:
+            want_s.append(o.read("sps")[cv])
+        if n % 5 == 0:
+            want_p.append(o.read("prp")[0])
+    s.advance_steps(100)
+    np.testing.assert_allclose(s.probe(0), want_s, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(s.probe(1), want_p, rtol=1e-9, atol=1e-15)
+    # species probes and state need the diffusion model
+    plain = netgen.tiny(seed=5, n_cells=7, t_end=100.0)
+    with pytest.raises(PAError) as e:
+        Simulation(plain, probes=[("sps", 0)])
+    assert e.value.status == B.PA_EINVAL
+    s2 = Simulation(plain)
+    with pytest.raises(PAError):
+        s2.read("prp")
+
+
+def test_mixed_precision_with_diffusion_stays_close():
+    """The mixed form with diffusion (species and their solves in FP64):
+    until the first spike the voltages agree to FP32 rounding and the
+    species to 1e-6 relative."""
+    net = netgen.with_diffusion(netgen.tiny(seed=3, n_cells=13, t_end=60.0), d_sps=4.0, d_prp=1.5)
+    _say("diffusion mixed tiny seed=3")
+    for mode in ("plain", "batched"):
+        o = oracle.Oracle(net)
+        s = Simulation(net, precision="mixed", mode=mode)
+        _seed(net, (o, s))
+        for _ in range(20):
+            o.run(1)
+            s.advance_steps(1)
+            if o.spikes()[0].size:
+                break
+            assert np.abs(s.read("V") - o.read("V")).max() < 1e-2
+        for k in ("sps", "prp"):
+            w = o.read(k)
+            np.testing.assert_allclose(s.read(k), w, rtol=1e-6, atol=1e-12 * np.abs(w).max())
