@@ -267,19 +267,20 @@ class _GB(C.Structure):
                                    "tau_c", "c_pre", "c_post", "t_cd")]
 
 
-def gb_trials(params: dict, dt, delays, w0, n_pairs=60, period=1000.0, t0=100.0, seed=1):
+def gb_trials(params: dict, dt, delays, w0, n_pairs=60, period=1000.0, t0=100.0, seed=1, first_id=0):
     """Final weight and calcium of independent Graupner-Brunel synapses under
-    the pairing protocol (one trial per entry of delays / w0)."""
+    the pairing protocol (one trial per entry of delays / w0; trial k draws
+    the noise stream of trial id first_id + k)."""
     lib = _load()
     lib.orc_gb_trials.restype = C.c_int
-    lib.orc_gb_trials.argtypes = [C.POINTER(_GB), _D, _I64, _P, _P, _I64, _D, _D, C.c_uint64, _P, _P]
+    lib.orc_gb_trials.argtypes = [C.POINTER(_GB), _D, _I64, _P, _P, _I64, _D, _D, C.c_uint64, C.c_uint64, _P, _P]
     g = _GB(**{k: float(params[k]) for k, _ in _GB._fields_})
     d = np.ascontiguousarray(delays, np.float64)
     w = np.ascontiguousarray(w0, np.float64)
     out = np.zeros(len(d))
     cout = np.zeros(len(d))
     if lib.orc_gb_trials(C.byref(g), float(dt), len(d), d.ctypes.data, w.ctypes.data, int(n_pairs), float(period),
-                         float(t0), int(seed), out.ctypes.data, cout.ctypes.data) != 0:
+                         float(t0), int(seed), int(first_id), out.ctypes.data, cout.ctypes.data) != 0:
         raise OracleError("invalid Graupner-Brunel parameters")
     return out, cout
 

@@ -952,8 +952,8 @@ void orc_hines(int64_t n, const int64_t *parent, const double *U, double *D, dou
  *   w <- w + (dt / tau_w) (-w (1 - w) (w_* - w) + gamma_p (1 - w) Theta_p
  *                          - gamma_d w Theta_d)
  *          + sigma sqrt((Theta_p + Theta_d) dt / tau_w) N_n   (Eq. 11),
- * N_n the standard normal of trial i at step n (the generator of the
- * early-phase noise keyed by the trial), then c <- c exp(-dt / tau_c)
+ * N_n the standard normal of trial first_id + i at step n (the generator of
+ * the early-phase noise keyed by the trial), then c <- c exp(-dt / tau_c)
  * (Eq. 12).  The run covers the steps of n_pairs periods from t0.  Writes
  * the final weight and calcium of every trial. */
 typedef struct {
@@ -961,7 +961,8 @@ typedef struct {
 } orc_gb;
 
 int orc_gb_trials(const orc_gb *P, double dt, int64_t n_trials, const double *delay_ms, const double *w0,
-                  int64_t n_pairs, double period_ms, double t0_ms, uint64_t seed, double *w_out, double *c_out) {
+                  int64_t n_pairs, double period_ms, double t0_ms, uint64_t seed, uint64_t first_id,
+                  double *w_out, double *c_out) {
     if (!(dt > 0) || !(P->tau_w > 0) || !(P->tau_c > 0) || n_pairs < 0) return -1;
     const int64_t n_end = (int64_t)floor((t0_ms + (double)n_pairs * period_ms) / dt);
     const double ah = dt / P->tau_w, rc = exp(-dt / P->tau_c);
@@ -981,7 +982,8 @@ int orc_gb_trials(const orc_gb *P, double dt, int64_t n_trials, const double *de
             double thd = (c - P->theta_d > 0.0) ? 1.0 : 0.0;
             double drift = -w * (1.0 - w) * (P->w_star - w) + P->gamma_p * (1.0 - w) * thp - P->gamma_d * w * thd;
             double wn = w + ah * drift;
-            if (thp + thd > 0.0) wn += P->sigma * sqrt((thp + thd) * ah) * orc_normal(seed, (uint64_t)i, (uint64_t)n);
+            if (thp + thd > 0.0)
+                wn += P->sigma * sqrt((thp + thd) * ah) * orc_normal(seed, first_id + (uint64_t)i, (uint64_t)n);
             w = wn;
             c = c * rc;
         }
