@@ -754,9 +754,9 @@ struct SynOut {
 };
 
 // The arithmetic of one synapse's update from its loaded operands (no
-// memory access, no branch, so that several synapses of one lane can be
-// interleaved); the caller adds the noise where out.th > 0 and stores the
-// plastic state only for tagging-and-capture synapses.
+// memory access, so that several synapses of one lane can be interleaved);
+// the caller adds the noise where out.th > 0 and stores the plastic state
+// only for tagging-and-capture synapses.
 template <class T>
 __device__ __forceinline__ SynOut<T> syn_compute(const DevNet &d, double p, bool post, const SynIn<T> &x) {
     const Stc &P = d.stc;
@@ -767,13 +767,21 @@ __device__ __forceinline__ SynOut<T> syn_compute(const DevNet &d, double p, bool
     const double thp = (c - (T)P.theta_p > T(0)) ? 1.0 : 0.0;
     const double thd = (c - (T)P.theta_d > T(0)) ? 1.0 : 0.0;
     const double ah = d.dt / P.tau_h;
-    const double drift = 0.1 * (h0 - h) + P.gamma_p * (10.0 - h) * thp - P.gamma_d * h * thd;
+    // Below both calcium thresholds (most synapses, most steps) the drift's
+    // threshold terms are signed zeros and add nothing: the short form gives
+    // the same bits as the full expression, which a wavefront computes only
+    // when one of its lanes crossed a threshold.
+    double drift = 0.1 * (h0 - h);
+    if (__any(thp + thd > 0.0)) drift = drift + P.gamma_p * (10.0 - h) * thp - P.gamma_d * h * thd;
     o.h = h + ah * drift;
     o.th = thp + thd;
     const double tagp = ((h - h0) - P.theta_tag > 0.0) ? 1.0 : 0.0;
     const double tagd = ((h0 - h) - P.theta_tag > 0.0) ? 1.0 : 0.0;
     const double az = d.dt / P.tau_z;
-    o.z = z + az * p * P.f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
+    // likewise without a tag z keeps its value (z is never a negative zero:
+    // it starts at +0 and sums of non-negative-zero operands stay so)
+    o.z = z;
+    if (__any(tagp + tagd > 0.0)) o.z = z + az * p * P.f_int * ((1.0 - z) * tagp - (z + 0.5) * tagd);
     if constexpr (sizeof(T) == 8) o.c = c * (T)d.r_c;
     else o.c = c * d.r_c_f;
     o.absdh = fabs(h - h0);

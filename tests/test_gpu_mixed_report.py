@@ -28,10 +28,12 @@ def _by_step(sp):
     return g[o], st[o], t[o]
 
 
-def _compare(name, net, n_steps, chunk):
+def _compare(name, net, n_steps, chunk, prepare=None):
     print(f"[case] mixed report {name} {n_steps} steps", flush=True)
     o = oracle.Oracle(net)
     s = Simulation(net, mode="batched", precision="mixed")
+    if prepare is not None:
+        prepare(net, (o, s))
     dv_max = 0.0
     done = 0
     while done < n_steps:
@@ -91,6 +93,40 @@ def test_mixed_report_long_dendrites():
 
 def test_mixed_report_uneven_trees():
     rep = _compare("trees 4096 30 ms", netgen.config3(t_end=60.0), 150, 150)
+    assert rep["max_spike_time_shift_ms"] < 0.2
+    assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) < 0.1 * rep["spikes_fp64_oracle"] + 10
+
+
+def _plastic_state(net, sims, seed=9):
+    """h over both tag signs, z, calcium over both thresholds and protein on
+    every side, so that the early and late phase move."""
+    rng = np.random.default_rng(seed)
+    kinds = net["syn_kind"] == 1
+    n = len(kinds)
+    h0 = net["stc"]["h0"]
+    vals = dict(h=np.where(kinds, rng.uniform(h0 - 2.5, h0 + 2.5, n), h0),
+                z=np.where(kinds, rng.uniform(-0.4, 0.9, n), 0.0),
+                c=np.where(kinds, rng.uniform(0.0, 5.0, n), 0.0),
+                p=rng.uniform(0.0, 8.0, int(net["n_cells"])))
+    for x in sims:
+        for k, v in vals.items():
+            x.write(k, v)
+
+
+def test_mixed_report_learning_stimulus():
+    """The 2000 x 21 network with a learning stimulus on 150 cells and a
+    seeded plastic state, 120 ms: h and z move, so the report's max |dh|
+    and |dz| measure the FP32 calcium against the FP64 accumulators."""
+    net = netgen.config2(t_end=200.0, stim_n=150, stim_t0=2.0, stim_dur=150.0, stim_amp=0.4)
+    rep = _compare("E/I 2000x21 learning 120 ms", net, 600, 200, prepare=_plastic_state)
+    assert rep["max_abs_dh_mV"] > 0.0
+    assert rep["max_abs_dh_mV"] < 0.5 and rep["max_abs_dz"] < 0.05
+
+
+def test_mixed_report_large_network():
+    """The 1e5-cell network (random trees of 10-60 CVs, 1e7 plastic
+    synapses, device Poisson drive), 8 ms through its start-up burst."""
+    rep = _compare("trees 1e5 8 ms", netgen.config5(t_end=20.0), 40, 20)
     assert rep["max_spike_time_shift_ms"] < 0.2
     assert abs(rep["spikes_mixed"] - rep["spikes_fp64_oracle"]) < 0.1 * rep["spikes_fp64_oracle"] + 10
 
