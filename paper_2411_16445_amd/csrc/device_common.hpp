@@ -82,6 +82,26 @@ static __device__ __attribute__((noinline)) double noise_increment(uint64_t seed
     return sigma * sqrt(th * ah) * std_normal(seed, sid, n);
 }
 
+// The mixed form's normal: the same Threefry words, lane choice and
+// Box-Muller branch, with the uniforms' top 24 bits and the logarithm,
+// square root and sine or cosine in FP32 (the hardware's approximations);
+// it differs from the FP64 normal by FP32 rounding, far below the noise's
+// own scale in the FP64 early-phase weight.
+static __device__ __attribute__((noinline)) double noise_increment_f32(uint64_t seed, uint64_t sid, uint64_t n,
+                                                               double sigma, double th, double ah) {
+    uint64_t x[4];
+    threefry4x64_12(n >> 2, 0, 0, 0, seed, sid, NOISE_TAG, 0, x);
+    const uint32_t lane = (uint32_t)(n & 3);
+    const uint64_t xa = (lane & 2) ? x[2] : x[0];
+    const uint64_t xb = (lane & 2) ? x[3] : x[1];
+    const float ua = ((float)(uint32_t)(xa >> 40) + 0.5f) * 0x1.0p-24f;
+    const float ub = ((float)(uint32_t)(xb >> 40) + 0.5f) * 0x1.0p-24f;
+    const float r = __fsqrt_rn(-2.0f * __logf(ua));
+    const float ang = 6.28318530717958648f * ub;
+    const float nrm = (lane & 1) ? r * __sinf(ang) : r * __cosf(ang);
+    return sigma * sqrt(th * ah) * (double)nrm;
+}
+
 constexpr uint64_t POIS_TAG = 0x706f6973736f6e21ull;
 
 // Inter-arrival time (ms) number j of Poisson source k at rate (Hz):
@@ -678,13 +698,29 @@ __device__ inline void seg_backward(double *D, double *B, const double *ax, uint
         }
         i -= SEG_PRELOAD;
     }
-    for (; i > a; --i) {
-        const double u = -ax[i];
-        const double f = qdiv<EXACT>(u, dc);
-        D[i] = dc;
-        B[i] = bc;
-        dc = D[i - 1] - f * u;
-        bc = B[i - 1] - f * bc;
+    // the last nodes (fewer than SEG_PRELOAD): their operands are loaded
+    // before the chain too, so no LDS access sits inside it
+    const uint32_t r = i - a;
+    if (r) {
+        double U[SEG_PRELOAD], Dp[SEG_PRELOAD], Bp[SEG_PRELOAD];
+#pragma unroll
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
+            if (j < r) {
+                U[j] = -ax[i - j];
+                Dp[j] = D[i - j - 1];
+                Bp[j] = B[i - j - 1];
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
+            if (j < r) {
+                const double f = qdiv<EXACT>(U[j], dc);
+                D[i - j] = dc;
+                B[i - j] = bc;
+                dc = Dp[j] - f * U[j];
+                bc = Bp[j] - f * bc;
+            }
+        }
     }
     D[a] = dc;
     B[a] = bc;
@@ -713,10 +749,25 @@ __device__ inline bool seg_forward(const double *D, const double *B, double *V, 
         }
         i += SEG_PRELOAD;
     }
-    for (; i <= b; ++i) {
-        vp = qdiv<EXACT>(B[i] - (-ax[i]) * vp, D[i]);
-        V[i] = vp;
-        ok = ok && isfinite(vp);
+    const uint32_t r = b + 1 - i;
+    if (r) {
+        double U[SEG_PRELOAD], Dl[SEG_PRELOAD], Bl[SEG_PRELOAD];
+#pragma unroll
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
+            if (j < r) {
+                U[j] = -ax[i + j];
+                Dl[j] = D[i + j];
+                Bl[j] = B[i + j];
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < SEG_PRELOAD; ++j) {
+            if (j < r) {
+                vp = qdiv<EXACT>(Bl[j] - U[j] * vp, Dl[j]);
+                V[i + j] = vp;
+                ok = ok && isfinite(vp);
+            }
+        }
     }
     return ok;
 }
@@ -791,7 +842,12 @@ __device__ __forceinline__ SynOut<T> syn_compute(const DevNet &d, double p, bool
 // Noise increment of Eq. 18 added to the new h where a threshold is crossed.
 template <class T>
 __device__ __forceinline__ void syn_noise(const DevNet &d, uint32_t s, uint64_t n, SynOut<T> &o) {
-    if (o.th > 0.0) o.h += noise_increment(d.seed, d.syn_sid[s], n, d.stc.sigma_pl, o.th, d.dt / d.stc.tau_h);
+    if (o.th > 0.0) {
+        if constexpr (sizeof(T) == 8)
+            o.h += noise_increment(d.seed, d.syn_sid[s], n, d.stc.sigma_pl, o.th, d.dt / d.stc.tau_h);
+        else
+            o.h += noise_increment_f32(d.seed, d.syn_sid[s], n, d.stc.sigma_pl, o.th, d.dt / d.stc.tau_h);
+    }
 }
 
 // The STDP synapse's step in place of the tagging-and-capture outputs: the

@@ -145,7 +145,12 @@ def test_diffusion_probes_and_errors():
 def test_mixed_precision_with_diffusion_stays_close():
     """The mixed form with diffusion (species and their solves in FP64):
     until the first spike the voltages agree to FP32 rounding and the
-    species to 1e-6 relative."""
+    species to 1e-6 relative, plus 1e-5 of the largest species in absolute
+    terms: the mixed form draws the normal of the weight noise in FP32
+    (24-bit uniforms, the hardware's logarithm, square root and sine), an
+    error of order 1e-6 of each noise increment, and the species integrate
+    differences of |h - h0|, so a species that is small by cancellation
+    carries the error at the scale of the others."""
     net = netgen.with_diffusion(netgen.tiny(seed=3, n_cells=13, t_end=60.0), d_sps=4.0, d_prp=1.5)
     _say("diffusion mixed tiny seed=3")
     for mode in ("plain", "batched"):
@@ -160,4 +165,4 @@ def test_mixed_precision_with_diffusion_stays_close():
             assert np.abs(s.read("V") - o.read("V")).max() < 1e-2
         for k in ("sps", "prp"):
             w = o.read(k)
-            np.testing.assert_allclose(s.read(k), w, rtol=1e-6, atol=1e-12 * np.abs(w).max())
+            np.testing.assert_allclose(s.read(k), w, rtol=1e-6, atol=1e-5 * np.abs(w).max())
