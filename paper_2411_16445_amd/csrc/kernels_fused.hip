@@ -48,7 +48,7 @@ constexpr uint32_t CHAIN_ROWS = 4;
 // the arrays on the device.
 struct FusedLayout {
     // doubles
-    uint32_t V, D, B, Ax, D0, Cdt, Gpe, DecCv, H, Z, Erev, P, Vold, Cu, Cb, HHp;
+    uint32_t V, D, B, E, Ax, D0, Cdt, Gpe, DecCv, H, Z, Erev, P, Vold, Cu, Cb, HHp;
     // mixed form: per-CV conductance sums (two halves)
     uint32_t Gs, GsE;
     // particle diffusion: per CV both species, the volume, both species'
@@ -68,16 +68,20 @@ struct FusedLayout {
     uint32_t SynCv, SegA, SegB, SegCell, KidOff, Kids, Kind, Post, SegLvl;
     uint32_t total;
     // lean: mixed-form workgroup of unbranched cells solved by the lanes
-    // with the rows assembled in registers (no D, B); carried: mixed form
+    // with the rows assembled in registers (no D, B); chain: the same with
+    // more CVs than registers hold, a lane's chunk kept in D, B and E (each
+    // 256 doubles beyond the CVs, room for every solver wavefront's
+    // rounded-up share); carried: mixed form
     // with carried per-CV sums, so the synapse wavefronts alone read the
     // synapse conductances (one buffer), and the reversal potentials and
     // per-CV synapse ranges stay in global memory
-    bool lean, carried;
+    bool lean, chain, carried;
     __host__ __device__ FusedLayout(uint32_t nv, uint32_t ns, uint32_t nh, uint32_t nc, uint32_t K,
                                     uint32_t tsize, uint32_t ng, bool carried_sums, bool dif, uint32_t nq) {
         lean = tsize == 4 && ng == nc && nv <= 64 * CHAIN_ROWS;
+        chain = tsize == 4 && ng == nc && !lean;
         carried = tsize == 4 && carried_sums;
-        const uint32_t nvd = lean ? 0 : nv, nse = carried ? 0 : ns;
+        const uint32_t nvd = lean ? 0 : (chain ? nv + 256 : nv), nse = carried ? 0 : ns;
         uint32_t o = 0;
         auto take = [&](uint32_t bytes, uint32_t align) {
             o = (o + align - 1) / align * align;
@@ -85,7 +89,8 @@ struct FusedLayout {
             o += bytes;
             return r;
         };
-        V = take(8 * nv, 16); D = take(8 * nvd, 8); B = take(8 * nvd, 8); Ax = take(8 * nv, 8);
+        V = take(8 * nv, 16); D = take(8 * nvd, 8); B = take(8 * nvd, 8); E = take(8 * (chain ? nvd : 0), 8);
+        Ax = take(8 * nv, 8);
         D0 = take(8 * nv, 8); Cdt = take(8 * nv, 8); Gpe = take(8 * nv, 8);
         DecCv = take(8 * (tsize == 4 ? nv : 0), 8);
         H = take(8 * ns, 8); Z = take(8 * ns, 8); Erev = take(8 * nse, 8);
@@ -278,6 +283,130 @@ __device__ __forceinline__ bool part_cells(uint32_t va, uint32_t vb, uint32_t le
     return ok;
 }
 
+// The partition method of part_cells for shares of unbranched cells too long
+// for a lane's chunk to stay in registers: the same chunks and the same
+// arithmetic in the same order (so the same values as part_cells would give
+// for that chunking), with a chunk's rows kept in LDS scratch XA, XR, XI
+// (row j of lane l at j * 64 + l, so every access of a wavefront is
+// contiguous; each array holds 64 ceil(n / 64) doubles).  The rows are
+// assembled first (independent of one another, so their loads overlap),
+// then each pass over a chunk works through blocks of four rows whose
+// operands are loaded before the block's dependent arithmetic.  XR, XI
+// hold the assembled right-hand sides and diagonals, then the eliminated
+// rows; XA the couplings to the previous chunk's last CV.  Writes V = x
+// (after every row has read V).
+template <class Row>
+__device__ __forceinline__ bool part_chain(uint32_t va, uint32_t vb, uint32_t levels, uint32_t lane,
+                                           const int32_t *par, const double *ax, Row &&row, double *V, double *XA,
+                                           double *XR, double *XI) {
+    const uint32_t n = vb - va;
+    const uint32_t m = (n + 63) >> 6;
+    const uint32_t nact = (n + m - 1) / m;
+    const uint32_t s = va + lane * m;
+    const uint32_t cnt = lane < nact ? min(m, vb - s) : 0u;
+    // coupling of row i to its predecessor, and of row i to row i + 1
+    auto lower = [&](uint32_t i) { return par[i] >= 0 ? -ax[i] : 0.0; };
+    auto upper = [&](uint32_t i) { return i + 1 < vb && par[i + 1] == (int32_t)i ? -ax[i + 1] : 0.0; };
+#pragma unroll 4
+    for (uint32_t j = 0; j < cnt; ++j) {
+        double dj, rj;
+        row(s + j, dj, rj);
+        XI[j * 64 + lane] = dj;
+        XR[j * 64 + lane] = rj;
+    }
+    // lower couplings: row j becomes A x_prev + d x_j + C x_{j+1} = R with
+    // 1 / d kept in XI
+    double ap = 0.0, rp = 0.0, cp = 0.0, ivp = 0.0;
+    double ae = 0.0, re = 0.0, ce = 0.0, de = 1.0;
+    for (uint32_t j0 = 0; j0 < cnt; j0 += 4) {
+        double a4[4], c4[4], d4[4], r4[4];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            if (j0 + q < cnt) {
+                const uint32_t i = s + j0 + q;
+                a4[q] = lower(i);
+                c4[q] = upper(i);
+                d4[q] = XI[(j0 + q) * 64 + lane];
+                r4[q] = XR[(j0 + q) * 64 + lane];
+            }
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            if (j0 + q < cnt) {
+                const uint32_t j = j0 + q;
+                double aj = a4[q], dj = d4[q], rj = r4[q];
+                if (j > 0) {
+                    const double f = a4[q] * ivp;
+                    aj = -f * ap;
+                    dj = dj - f * cp;
+                    rj = rj - f * rp;
+                }
+                ivp = qdiv<false>(1.0, dj);
+                XA[j * 64 + lane] = aj;
+                XR[j * 64 + lane] = rj;
+                XI[j * 64 + lane] = ivp;
+                ap = aj;
+                rp = rj;
+                cp = c4[q];
+                ae = aj;
+                re = rj;
+                ce = c4[q];
+                de = dj;
+            }
+        }
+    }
+    // upper couplings, last row first: each row other than the chunk's
+    // last becomes x_j = R - A x_prev - C x_last (C kept in XI)
+    double rn = 0.0, an = 0.0, cn = -1.0;
+    for (int j0 = (int)cnt - 2; j0 >= 0; j0 -= 4) {
+        double c4[4], i4[4], r4[4], a4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 - q;
+            if (j >= 0) {
+                c4[q] = upper(s + (uint32_t)j);
+                i4[q] = XI[j * 64 + lane];
+                r4[q] = XR[j * 64 + lane];
+                a4[q] = XA[j * 64 + lane];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 - q;
+            if (j >= 0) {
+                rn = (r4[q] - c4[q] * rn) * i4[q];
+                an = (a4[q] - c4[q] * an) * i4[q];
+                cn = -(c4[q] * cn) * i4[q];
+                XR[j * 64 + lane] = rn;
+                XA[j * 64 + lane] = an;
+                XI[j * 64 + lane] = cn;
+            }
+        }
+    }
+    const double rn1 = __shfl_down(rn, 1), an1 = __shfl_down(an, 1), cn1 = __shfl_down(cn, 1);
+    const bool act = cnt > 0;
+    double ra = act ? ae : 0.0;
+    double rc = act ? -(ce * cn1) : 0.0;
+    double rd = act ? de - ce * an1 : 1.0;
+    double rr = act ? re - ce * rn1 : 0.0;
+    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, nact, sft, ra, rd, rc, rr);
+    const double xe = qdiv<false>(rr, rd);
+    const double xp0 = __shfl_up(xe, 1);
+    const double xp = lane > 0 ? xp0 : 0.0;
+    bool ok = !act || isfinite(xe);
+#pragma unroll 4
+    for (uint32_t j = 0; j < cnt; ++j) {
+        if (j + 1 < cnt) {
+            const double v = XR[j * 64 + lane] - XA[j * 64 + lane] * xp - XI[j * 64 + lane] * xe;
+            V[s + j] = v;
+            ok = ok && isfinite(v);
+        } else {
+            V[s + j] = xe;
+        }
+    }
+    return ok;
+}
+
 // Barrier across all workgroups of a cooperative launch (all resident).
 // Workgroup b counts itself into group counter b mod G (G = 32 counters on
 // separate cache lines, so about nblocks/G workgroups contend for each);
@@ -406,6 +535,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
     // offset of conductance half h (one buffer when the sums are carried)
     auto gofs = [&](uint32_t h) { return lay.carried ? 0u : h * ns; };
     double *sV = (double *)(L + lay.V), *sD = (double *)(L + lay.D), *sB = (double *)(L + lay.B);
+    double *sE = (double *)(L + lay.E);
     double *sAx = (double *)(L + lay.Ax), *sD0 = (double *)(L + lay.D0), *sCdt = (double *)(L + lay.Cdt);
     double *sGpe = (double *)(L + lay.Gpe), *sH = (double *)(L + lay.H), *sZ = (double *)(L + lay.Z);
     double *sErev = (double *)(L + lay.Erev);
@@ -732,7 +862,7 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             Bi = ((sCdt[i] * v + sGpe[i]) - I) + G * v;
         };
         for (uint32_t c = wc0 + lane; c < wc1; c += 64) sVold[c] = sV[sDet[c]];
-        if (!lay.lean) {
+        if (!lay.lean && !lay.chain) {
             for (uint32_t i = wva + lane; i < wvb; i += 64) row(i, sD[i], sB[i]);
         }
         wave_sync();
@@ -744,6 +874,14 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
             // solve by cyclic reduction or the partition method
             const bool ok = wvb - wva <= 64 ? pcr_cells(wva, wvb, wpcr, lane, sPar, sAx, row, sV)
                                             : part_cells<CHAIN_ROWS>(wva, wvb, wpcr, lane, sPar, sAx, row, sV);
+            if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + wc0);
+        } else if (lay.chain) {
+            // the same, a chunk's rows in LDS (this wavefront's scratch
+            // starts 64 doubles per solver wavefront beyond its share)
+            const uint32_t xb = wva + 64 * wave;
+            const bool ok = wvb - wva <= 64 ? pcr_cells(wva, wvb, wpcr, lane, sPar, sAx, row, sV)
+                                            : part_chain(wva, wvb, wpcr, lane, sPar, sAx, row, sV, sE + xb,
+                                                         sB + xb, sD + xb);
             if (!ok) raise_flag(d, FLAG_NONFINITE, c0 + wc0);
         } else {
             // Hines elimination level-scheduled over branch segments,

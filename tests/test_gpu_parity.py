@@ -279,13 +279,17 @@ def _passive_chains(lengths):
     dict(cells_per_block=2, block_threads=128, solver_waves=1),
     dict(cells_per_block=3, block_threads=256, solver_waves=2),
     dict(cells_per_block=4, block_threads=256, solver_waves=3),
+    dict(cells_per_block=8, block_threads=128, solver_waves=1),
+    dict(cells_per_block=12, block_threads=256, solver_waves=2),
+    dict(cells_per_block=12, block_threads=64),
 ])
 def test_mixed_chain_solve_matches_oracle(shape):
     """The mixed form's lane solves of unbranched cells (cyclic reduction up
     to 64 CVs a wavefront, the partition method with 2, 3 or 4 CVs a lane
-    above, cells sharing a lane's chunk, ragged last chunks; elimination for
-    workgroups over 256 CVs) against the FP64 oracle on passive chains: the
-    voltages agree to the FP64 bar."""
+    above, cells sharing a lane's chunk, ragged last chunks; workgroups over
+    256 CVs by the same method with a lane's chunk of up to 14 CVs in LDS)
+    against the FP64 oracle on passive chains: the voltages agree to the
+    FP64 bar."""
     lengths = [101, 130, 1, 2, 65, 64, 37, 255, 3, 90, 129, 5]
     net = _passive_chains(lengths)
     _say(f"mixed passive chains {shape}")
