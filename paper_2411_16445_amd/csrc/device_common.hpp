@@ -839,6 +839,51 @@ __device__ __forceinline__ SynOut<T> syn_compute(const DevNet &d, double p, bool
     return o;
 }
 
+// syn_compute of two synapses of one lane with one wavefront vote per
+// short form for both: a taken full form gives a synapse whose own lanes
+// would have taken the short form the same bits (its terms are signed
+// zeros), so the outputs equal two syn_compute calls, while the two
+// synapses' arithmetic stays interleaved between the votes.
+template <class T>
+__device__ __forceinline__ void syn_compute2(const DevNet &d, double p1, double p2, bool post, const SynIn<T> &x1,
+                                             const SynIn<T> &x2, SynOut<T> &o1, SynOut<T> &o2) {
+    const Stc &P = d.stc;
+    const double h0 = P.h0, ah = d.dt / P.tau_h, az = d.dt / P.tau_z;
+    o1.g = x1.g * x1.dec;
+    o2.g = x2.g * x2.dec;
+    const T c1 = post ? x1.c + (T)P.c_post : x1.c;
+    const T c2 = post ? x2.c + (T)P.c_post : x2.c;
+    const double h1 = x1.h, z1 = x1.z, h2 = x2.h, z2 = x2.z;
+    const double thp1 = (c1 - (T)P.theta_p > T(0)) ? 1.0 : 0.0, thd1 = (c1 - (T)P.theta_d > T(0)) ? 1.0 : 0.0;
+    const double thp2 = (c2 - (T)P.theta_p > T(0)) ? 1.0 : 0.0, thd2 = (c2 - (T)P.theta_d > T(0)) ? 1.0 : 0.0;
+    double drift1 = 0.1 * (h0 - h1), drift2 = 0.1 * (h0 - h2);
+    if (__any(thp1 + thd1 + thp2 + thd2 > 0.0)) {
+        drift1 = drift1 + P.gamma_p * (10.0 - h1) * thp1 - P.gamma_d * h1 * thd1;
+        drift2 = drift2 + P.gamma_p * (10.0 - h2) * thp2 - P.gamma_d * h2 * thd2;
+    }
+    o1.h = h1 + ah * drift1;
+    o2.h = h2 + ah * drift2;
+    o1.th = thp1 + thd1;
+    o2.th = thp2 + thd2;
+    const double tagp1 = ((h1 - h0) - P.theta_tag > 0.0) ? 1.0 : 0.0, tagd1 = ((h0 - h1) - P.theta_tag > 0.0) ? 1.0 : 0.0;
+    const double tagp2 = ((h2 - h0) - P.theta_tag > 0.0) ? 1.0 : 0.0, tagd2 = ((h0 - h2) - P.theta_tag > 0.0) ? 1.0 : 0.0;
+    o1.z = z1;
+    o2.z = z2;
+    if (__any(tagp1 + tagd1 + tagp2 + tagd2 > 0.0)) {
+        o1.z = z1 + az * p1 * P.f_int * ((1.0 - z1) * tagp1 - (z1 + 0.5) * tagd1);
+        o2.z = z2 + az * p2 * P.f_int * ((1.0 - z2) * tagp2 - (z2 + 0.5) * tagd2);
+    }
+    if constexpr (sizeof(T) == 8) {
+        o1.c = c1 * (T)d.r_c;
+        o2.c = c2 * (T)d.r_c;
+    } else {
+        o1.c = c1 * d.r_c_f;
+        o2.c = c2 * d.r_c_f;
+    }
+    o1.absdh = fabs(h1 - h0);
+    o2.absdh = fabs(h2 - h0);
+}
+
 // Noise increment of Eq. 18 added to the new h where a threshold is crossed.
 template <class T>
 __device__ __forceinline__ void syn_noise(const DevNet &d, uint32_t s, uint64_t n, SynOut<T> &o) {

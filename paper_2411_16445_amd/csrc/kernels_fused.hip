@@ -149,27 +149,66 @@ __device__ __forceinline__ void split_cells(const uint32_t *off, uint32_t nc, ui
     hi = part + 1 == parts ? nc : count_below(off, nc, (uint32_t)((uint64_t)tot * (part + 1) / parts), lane);
 }
 
-// One round of cyclic reduction across the lanes of a wavefront, lane l
-// holding row l (lower coupling ra, diagonal rd, upper coupling rc,
-// right-hand side rr) of a tridiagonal system of n rows: the row folds in
-// rows l - sft and l + sft, read from their lanes.  A zero coupling marks
-// the end of a cell, so rows never combine across cells.
-__device__ __forceinline__ void pcr_round(uint32_t lane, uint32_t n, uint32_t sft, double &ra, double &rd,
-                                          double &rc, double &rr) {
+// Value of x on lane l - 1 (wave_shr) or l + 1 (wave_shl) by a data-parallel
+// lane shift of the whole wavefront; a lane without a source keeps its own.
+template <int CTRL>
+__device__ __forceinline__ double wave_shift1(double x) {
+    const uint64_t u = __double_as_longlong(x);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)h2 << 32) | (uint32_t)l2));
+}
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+
+// Scales a row (lower coupling ra, diagonal rd, upper coupling rc,
+// right-hand side rr) to unit diagonal.
+__device__ __forceinline__ void pcr_unit(double rd, double &ra, double &rc, double &rr) {
+    const double inv = qdiv<false>(1.0, rd);
+    ra = ra * inv;
+    rc = rc * inv;
+    rr = rr * inv;
+}
+
+// One round of cyclic reduction across the lanes of a wavefront on rows of
+// unit diagonal, lane l holding row l (lower coupling ra, upper coupling rc,
+// right-hand side rr) of a tridiagonal system of n rows: the row subtracts
+// ra times row l - sft and rc times row l + sft, read from their lanes, and
+// is scaled back to unit diagonal.  A zero coupling marks the end of a
+// cell, so rows never combine across cells.  The first round (sft = 1)
+// reads its neighbours by lane shifts, the others by lane permutes.
+__device__ __forceinline__ void pcr_round(uint32_t lane, uint32_t n, uint32_t sft, double &ra, double &rc,
+                                          double &rr) {
     const bool act = lane < n;
     const bool hm = act && ra != 0.0 && lane >= sft;
     const bool hp = act && rc != 0.0 && lane + sft < n;
-    const double ri = qdiv<false>(1.0, rd);
-    const int lm = (int)(hm ? lane - sft : lane), lp = (int)(hp ? lane + sft : lane);
-    const double ima = __shfl(ri, lm), am = __shfl(ra, lm), cm = __shfl(rc, lm), rm = __shfl(rr, lm);
-    const double ipa = __shfl(ri, lp), ap = __shfl(ra, lp), cp = __shfl(rc, lp), rp = __shfl(rr, lp);
-    const double al = -ra * ima, ga = -rc * ipa;
-    const double d1 = hm ? rd + al * cm : rd;
-    const double r1 = hm ? rr + al * rm : rr;
-    rd = hp ? d1 + ga * ap : d1;
-    rr = hp ? r1 + ga * rp : r1;
-    ra = hm ? al * am : 0.0;
-    rc = hp ? ga * cp : 0.0;
+    double am, cm, rm, ap, cp, rp;
+    if (sft == 1) {
+        am = wave_shift1<DPP_WAVE_SHR1>(ra);
+        cm = wave_shift1<DPP_WAVE_SHR1>(rc);
+        rm = wave_shift1<DPP_WAVE_SHR1>(rr);
+        ap = wave_shift1<DPP_WAVE_SHL1>(ra);
+        cp = wave_shift1<DPP_WAVE_SHL1>(rc);
+        rp = wave_shift1<DPP_WAVE_SHL1>(rr);
+    } else {
+        const int lm = (int)(hm ? lane - sft : lane), lp = (int)(hp ? lane + sft : lane);
+        am = __shfl(ra, lm);
+        cm = __shfl(rc, lm);
+        rm = __shfl(rr, lm);
+        ap = __shfl(ra, lp);
+        cp = __shfl(rc, lp);
+        rp = __shfl(rr, lp);
+    }
+    const double d1 = hm ? 1.0 - ra * cm : 1.0;
+    const double r1 = hm ? rr - ra * rm : rr;
+    const double dn = hp ? d1 - rc * ap : d1;
+    const double rn = hp ? r1 - rc * rp : r1;
+    const double an = hm ? -(ra * am) : 0.0;
+    const double cn = hp ? -(rc * cp) : 0.0;
+    ra = an;
+    rc = cn;
+    rr = rn;
+    pcr_unit(dn, ra, rc, rr);
 }
 
 // Mixed-form parallel cyclic reduction of the tridiagonal systems of the
@@ -188,9 +227,10 @@ __device__ __forceinline__ bool pcr_cells(uint32_t va, uint32_t vb, uint32_t lev
     double rc = up ? -ax[i + 1] : 0.0;
     double rd = 1.0, rr = 0.0;
     if (act) row(i, rd, rr);
-    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, n, sft, ra, rd, rc, rr);
+    pcr_unit(rd, ra, rc, rr);
+    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, n, sft, ra, rc, rr);
     if (!act) return true;
-    const double v = qdiv<false>(rr, rd);
+    const double v = rr;
     V[i] = v;
     return isfinite(v);
 }
@@ -265,8 +305,9 @@ __device__ __forceinline__ bool part_cells(uint32_t va, uint32_t vb, uint32_t le
     double rc = act ? -(ce * cn1) : 0.0;
     double rd = act ? de - ce * an1 : 1.0;
     double rr = act ? re - ce * rn1 : 0.0;
-    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, nact, sft, ra, rd, rc, rr);
-    const double xe = qdiv<false>(rr, rd);
+    pcr_unit(rd, ra, rc, rr);
+    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, nact, sft, ra, rc, rr);
+    const double xe = rr;
     const double xp0 = __shfl_up(xe, 1);
     const double xp = lane > 0 ? xp0 : 0.0;
     bool ok = !act || isfinite(xe);
@@ -389,8 +430,9 @@ __device__ __forceinline__ bool part_chain(uint32_t va, uint32_t vb, uint32_t le
     double rc = act ? -(ce * cn1) : 0.0;
     double rd = act ? de - ce * an1 : 1.0;
     double rr = act ? re - ce * rn1 : 0.0;
-    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, nact, sft, ra, rd, rc, rr);
-    const double xe = qdiv<false>(rr, rd);
+    pcr_unit(rd, ra, rc, rr);
+    for (uint32_t k = 0, sft = 1; k < levels; ++k, sft <<= 1) pcr_round(lane, nact, sft, ra, rc, rr);
+    const double xe = rr;
     const double xp0 = __shfl_up(xe, 1);
     const double xp = lane > 0 ? xp0 : 0.0;
     bool ok = !act || isfinite(xe);
@@ -958,8 +1000,8 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
                 const bool k1 = kd1 == 1, k2 = kd2 == 1;
                 // with diffusion, z takes the protein of the synapse's CV
                 const double p1 = dif ? sPrp[sSynCv[s]] : p, p2 = dif ? sPrp[sSynCv[s2]] : p;
-                SynOut<T> o1 = syn_compute<T>(d, p1, post, x1);
-                SynOut<T> o2 = syn_compute<T>(d, p2, post, x2);
+                SynOut<T> o1, o2;
+                syn_compute2<T>(d, p1, p2, post, x1, x2, o1, o2);
                 if (k1) syn_noise<T>(d, s0 + s, n, o1);
                 if (two && k2) syn_noise<T>(d, s0 + s2, n, o2);
                 if (kd1 == 2) stdp_compute<T>(d, post, x1, o1);
