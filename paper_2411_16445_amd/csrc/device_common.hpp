@@ -325,11 +325,13 @@ __device__ __forceinline__ U ld_ring(const U *p) {
 }
 template <bool COH, class F>
 __device__ __forceinline__ void conn_events(const DevNet &d, uint64_t q, uint64_t n0, uint32_t nst, F &&emit) {
+    // the source's counters and the connection's constants are loaded
+    // together, and both words of a ring entry at once
     const uint32_t src = d.in_src[q];
     const uint32_t last = ld_ring<COH>(d.spk_last + src);
+    const uint32_t cnt = ld_ring<COH>(d.spk_n + src);
     const int64_t lo = (int64_t)n0 - (int64_t)d.in_lag[q];
     if (last == 0 || (int64_t)last - 1 < lo) return;
-    const uint32_t cnt = ld_ring<COH>(d.spk_n + src);
     const uint32_t stop = cnt > d.H ? cnt - d.H : 0u;
     const uint8_t ports = d.in_ports[q];
     const double dly = d.in_d[q];
@@ -342,11 +344,12 @@ __device__ __forceinline__ void conn_events(const DevNet &d, uint64_t q, uint64_
     for (uint32_t k = cnt; k-- > stop;) {
         const uint64_t *r = (const uint64_t *)(d.spk + (uint64_t)src * d.H + (k & (d.H - 1)));
         const uint64_t w1 = ld_ring<COH>(r + 1);
+        const uint64_t w0 = ld_ring<COH>(r);
         if ((uint32_t)(w1 >> 32) != k) continue;
         const uint64_t ns = (uint32_t)w1;
         if (ns >= n0) continue;
         if ((int64_t)ns < lo) break;
-        const double ts = __longlong_as_double((long long)ld_ring<COH>(r));
+        const double ts = __longlong_as_double((long long)w0);
         const double te = ts + dly;
         if (ports & 1) {
             const uint64_t s = (uint64_t)floor(te / d.dt);
