@@ -4,15 +4,18 @@ Two uses:
 
 * ``python -m paper_2411_16445_amd.profiling counters FETCH_DIR WRITE_DIR
   --kernel k_epoch --copy-mib 256 --steps-per-dispatch N --workload W
-  --command "..." > profiles/<name>.md``
+  [--last L] --command "..." > profiles/<name>.md``
   turns two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
   ``bench.py --copy-probe-mib 256`` into the HBM traffic per launch of the
   kernel.  Both counters are in KiB per dispatch; each is scaled by what it
   reads for the plain device copy of known size that the same run performs
   (the copy moves exactly ``copy-mib`` MiB each way), so the figure is in
   true bytes.
-* ``python -m paper_2411_16445_amd.profiling trace STATS_CSV --command "..."``
-  formats a ``--kernel-trace --stats`` kernel_stats.csv as a table.
+* ``python -m paper_2411_16445_amd.profiling trace STATS_CSV --command "..."
+  [--kernel K --last L]`` formats a ``--kernel-trace --stats``
+  kernel_stats.csv as a table, with the mean duration of the kernel's last L
+  dispatches (a bench run's timed launches) from the kernel_trace.csv beside
+  it.
 
 ``traffic_for_bench`` reads a counters summary back for ``bench.py``; it
 returns None when the kernel sources changed since the counters were taken
@@ -54,23 +57,29 @@ def _rows(d: str):
 
 
 def _per_dispatch(rows, counter, pick):
-    """Counter value per dispatch of the kernels selected by pick(row)."""
+    """Counter value per dispatch of the kernels selected by pick(row), in
+    dispatch order."""
     out = {}
     for r in rows:
         if r["Counter_Name"] != counter or not pick(r):
             continue
-        key = r["Dispatch_Id"]
+        key = int(r["Dispatch_Id"])
         out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
-    return list(out.values())
+    return [out[k] for k in sorted(out)]
 
 
-def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_dispatch, workload):
+def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_dispatch, workload, last=0):
+    """last > 0: only the kernel's last `last` dispatches count (a bench
+    run's timed launches come after its plan trials, settling and warm-up),
+    and steps_per_dispatch is their mean step count."""
     copy_bytes = copy_mib * 1024 * 1024
     lines = []
     res = {}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _rows(d)
         kern = _per_dispatch(rows, name, lambda r: kernel in r["Kernel_Name"])
+        if last > 0:
+            kern = kern[-last:]
         # the copy probe: the largest device-to-device copy dispatch of the run
         copies = [r for r in rows if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"]]
         if not kern or not copies:
@@ -101,7 +110,11 @@ def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_
                      f"{r['bytes']:.0f} |")
     total = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
     lines.append("")
-    lines.append(f"Each dispatch advances {steps_per_dispatch} steps.")
+    if last > 0:
+        lines.append(f"Only the kernel's last {last} dispatches (the timed launches) count; they advance "
+                     f"{steps_per_dispatch} steps each on average.")
+    else:
+        lines.append(f"Each dispatch advances {steps_per_dispatch} steps.")
     lines.append("")
     lines.append(f"traffic_bytes_per_launch: {total:.0f}")
     lines.append(f"traffic_bytes_per_step: {total / steps_per_dispatch:.1f}")
@@ -111,7 +124,16 @@ def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_
     return "\n".join(lines) + "\n"
 
 
-def trace_summary(stats_csv, command, title):
+def timed_launches(trace_csv, kernel, last):
+    """Durations (us) of the last `last` dispatches of the kernel whose name
+    contains `kernel`, from a --kernel-trace kernel_trace.csv."""
+    with open(trace_csv) as f:
+        rows = [r for r in csv.DictReader(f) if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[-last:]]
+
+
+def trace_summary(stats_csv, command, title, kernel=None, last=0):
     with open(stats_csv) as f:
         rows = list(csv.DictReader(f))
     lines = [f"# Kernel trace: {title}", "", "Command (repository root on the MI355X box):", ""]
@@ -128,6 +150,13 @@ def trace_summary(stats_csv, command, title):
         mx = float(r.get("MaxNs", 0)) / 1e3
         pct = float(r.get("Percentage", 0))
         lines.append(f"| {name} | {calls} | {tot:.1f} | {avg:.3f} | {mn:.3f} | {mx:.3f} | {pct:.2f} |")
+    if kernel and last > 0:
+        trace_csv = os.path.join(os.path.dirname(stats_csv), os.path.basename(stats_csv).replace(
+            "kernel_stats", "kernel_trace"))
+        dur = timed_launches(trace_csv, kernel, last)
+        lines += ["", f"Timed launches (the last {len(dur)} dispatches of `{kernel}`): "
+                      + ", ".join(f"{x:.1f}" for x in dur) + f" us; mean {sum(dur) / len(dur):.1f} us.",
+                  "", f"timed_launch_mean_us: {sum(dur) / len(dur):.3f}"]
     return "\n".join(lines) + "\n"
 
 
@@ -171,17 +200,20 @@ def main(argv=None):
     c.add_argument("--steps-per-dispatch", type=int, required=True)
     c.add_argument("--workload", required=True)
     c.add_argument("--command", action="append", default=[])
+    c.add_argument("--last", type=int, default=0, help="count only the kernel's last N dispatches")
     t = sub.add_parser("trace")
     t.add_argument("stats_csv")
     t.add_argument("--title", default="")
     t.add_argument("--command", action="append", default=[])
+    t.add_argument("--kernel", default=None)
+    t.add_argument("--last", type=int, default=0, help="report the mean of the kernel's last N dispatches")
     sub.add_parser("fingerprint")
     a = ap.parse_args(argv)
     if a.cmd == "counters":
         sys.stdout.write(counters_summary(a.fetch_dir, a.write_dir, a.kernel, a.copy_mib, a.command,
-                                          a.steps_per_dispatch, a.workload))
+                                          a.steps_per_dispatch, a.workload, a.last))
     elif a.cmd == "trace":
-        sys.stdout.write(trace_summary(a.stats_csv, a.command, a.title))
+        sys.stdout.write(trace_summary(a.stats_csv, a.command, a.title, a.kernel, a.last))
     else:
         print(source_fingerprint())
 
