@@ -80,10 +80,14 @@ def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_
         kern = _per_dispatch(rows, name, lambda r: kernel in r["Kernel_Name"])
         if last > 0:
             kern = kern[-last:]
-        # the copy probe: the largest device-to-device copy dispatch of the run
-        copies = [r for r in rows if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"]]
+        # the copy probe: the largest device-to-device copies after the
+        # kernel's last dispatch (earlier copies of the same grid size, such
+        # as the network's upload, move other amounts)
+        last_k = max((int(r["Dispatch_Id"]) for r in rows if kernel in r["Kernel_Name"]), default=-1)
+        copies = [r for r in rows if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"]
+                  and int(r["Dispatch_Id"]) > last_k]
         if not kern or not copies:
-            raise SystemExit(f"{name}: no dispatches of {kernel} or of the copy probe in {d}")
+            raise SystemExit(f"{name}: no dispatches of {kernel} or of the copy probe after them in {d}")
         big = max(int(r["Grid_Size"]) for r in copies)
         cp = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big]
         cp_kib = sum(cp) / len(cp)
@@ -99,7 +103,7 @@ def counters_summary(fetch_dir, write_dir, kernel, copy_mib, command, steps_per_
     for c in command:
         lines.append(f"    {c}")
     lines.append("")
-    lines.append(f"The same run copies {copy_mib} MiB device to device (a plain copy kernel); the")
+    lines.append(f"The same run then copies {copy_mib} MiB device to device (a plain copy kernel); the")
     lines.append("factor scales each counter so that it reads that copy's true size.")
     lines.append("")
     lines.append("| counter | dispatches | KiB per dispatch | copy probe KiB | scale factor | bytes per launch |")
@@ -197,7 +201,7 @@ def main(argv=None):
     c.add_argument("write_dir")
     c.add_argument("--kernel", default="k_epoch")
     c.add_argument("--copy-mib", type=int, default=256)
-    c.add_argument("--steps-per-dispatch", type=int, required=True)
+    c.add_argument("--steps-per-dispatch", type=float, required=True)
     c.add_argument("--workload", required=True)
     c.add_argument("--command", action="append", default=[])
     c.add_argument("--last", type=int, default=0, help="count only the kernel's last N dispatches")
