@@ -416,7 +416,9 @@ pa_status pa_kernel_time(pa_sim *sim, double *total_ms, uint64_t *launches, cons
  * diag, off and rhs are not modified.  The elimination runs from a cell's
  * last row towards its root, then substitution from the root, in the
  * sequential algorithm's order (IEEE FP64, no fused multiply-add).  A cell
- * whose range or parents break the rules above gets NaN in its rows of x.
+ * whose range or parents break the rules above gets NaN in its rows of x;
+ * where a decreasing cv_off makes two cells' ranges overlap, the shared
+ * rows are written by both and their contents are unspecified.
  * Work is enqueued on hip_stream (NULL: the null stream); the call returns
  * after it has completed.  The elimination workspace (16 bytes per row) is
  * allocated with hipMalloc for the call.  Errors: PA_EINVAL (NULL array
