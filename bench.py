@@ -121,6 +121,27 @@ def _oracle_rate(net, budget_s, threaded, min_steps=1):
     return o.n_cv * done / el, done, el, int(o.spikes()[0].size)
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """Measured HBM bandwidth of a plain device-to-device copy (bytes read
+    plus bytes written over the copy's time, best of reps), the practical
+    ceiling beside the 8 TB/s peak.  Runs before any simulation kernel, so a
+    profiled run's copy probe (after the timed launches) stays apart."""
+    import torch
+    x = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del x, y
+    return 2 * mib * 1024 * 1024 / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(net, budget_s):
     """The plain FP64 oracle on the host: single-threaded (the oracle as it
     stands) and, as a second figure, its OpenMP build on every host core
@@ -144,6 +165,22 @@ WORKLOADS = {"ei2000x21": ("ei-ball-and-stick-2000x21cv", "config2"),
              "morpho2000": ("ei-table6-neurons-2000x31cv-sps-prp-diffusion", "stc_morpho_network"),
              "busyring": ("busyring", "busyring"),
              "dpcurve": ("graupner-brunel-dp-curve-41x4000-trials", None)}
+
+DATA = {
+    "ei2000x21": "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network, 20-CV dendrites; "
+                 "{settle} untimed settling steps from rest)",
+    "ei2000x101": "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network, 100-CV dendrites; "
+                  "{settle} untimed settling steps from rest)",
+    "trees4096": "synthetic (seeded random trees of 10-300 CVs with HH somata, 100 plastic synapses per cell; "
+                 "{settle} untimed settling steps from rest)",
+    "large1e5": "synthetic (seeded random trees of 10-60 CVs, in-degree 100 onto plastic synapses, device Poisson "
+                "input; {settle} untimed settling steps from rest)",
+    "morpho2000": "synthetic (seeded E/I network of the paper's Table 6 neurons with SPS/PRP diffusion; "
+                  "{settle} untimed settling steps from rest)",
+    "busyring": "synthetic (seeded busyring of {cells} cells, tree depth {depth}, {kind} synapses on 1000 "
+                "zero-weight connections per cell)",
+    "dpcurve": "synthetic (Graupner-Brunel pairing protocol trials)",
+}
 
 # The paper's own propagation times of the busyring benchmark over 200 ms
 # (Table 9, one NVIDIA T1000 GPU; context only, other hardware), seconds:
@@ -230,6 +267,7 @@ def main():
     if args.workload == "dpcurve":
         dp_curve_bench(args)
         return
+    copy_gbs = copy_bandwidth()
     import netgen
     # inputs over everything that runs: settle, warmup, timed steps and the
     # oracle's sample
@@ -284,11 +322,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32" if args.form.endswith("mixed") else "f64",
-        "data": (f"synthetic (seeded busyring of {args.ring_cells} cells, tree depth {args.ring_depth}, "
-                 f"{'STDP' if args.ring_stdp else 'exponential'} synapses on 1000 zero-weight connections per cell)"
-                 if args.workload == "busyring" else
-                 "synthetic (seeded E/I network shaped like the paper's 2000-neuron STC network; "
-                 f"{args.settle} untimed settling steps from rest)"),
+        "data": DATA[args.workload].format(settle=args.settle, cells=args.ring_cells, depth=args.ring_depth,
+                                           kind="STDP" if args.ring_stdp else "exponential"),
         "config": {"workload": wname, "cells": head["stats"]["n_cells"],
                    "cvs": head["stats"]["n_cv"], "synapses": head["stats"]["n_syn"],
                    "stc_synapses": head["stats"]["n_stc"], "dt_ms": net["dt"], "form": args.form,
@@ -308,6 +343,7 @@ def main():
             "alg_bytes_per_launch": k.get("alg_bytes_per_launch"),
             "alg_bytes_per_step": k.get("alg_bytes_per_step"),
             "kernel_share_of_step_time": k.get("share_of_time"),
+            "copy_gbs": copy_gbs,
         },
         "cpu_baseline": cpu,
     }
