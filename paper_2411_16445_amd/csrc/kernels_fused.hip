@@ -1248,9 +1248,11 @@ struct Offsets {
 };
 
 // Packs consecutive cells, at most cpb per workgroup, within an LDS budget
-// that leaves room for several resident workgroups per CU.
+// that leaves room for at least two resident workgroups per CU (160 KB of
+// LDS); the autotuned cells per workgroup then choose between more, smaller
+// workgroups and fewer, larger ones.
 bool pack(const Offsets &o, uint32_t cpb, uint32_t threads, std::vector<uint32_t> &blk, size_t &lds) {
-    const size_t budget = threads == 64 ? 32 * 1024 : (threads == 128 ? 48 * 1024 : 64 * 1024);
+    const size_t budget = threads == 64 ? 32 * 1024 : 80 * 1024;
     const uint32_t nc = (uint32_t)o.cv.size() - 1;
     auto bytes = [&](uint32_t a, uint32_t e) {
         return (size_t)FusedLayout(o.cv[e] - o.cv[a], o.syn[e] - o.syn[a], o.hh[e] - o.hh[a], e - a, o.K,
@@ -1389,16 +1391,18 @@ pa_status batched_setup(pa_sim *s) {
             break;
         }
         if (upload_plan(s, P) != PA_OK) return PA_EDEVICE;
-        // trial: 1 warm epoch, then time 4 epochs of K steps
+        // trial: 1 warm epoch in the trial's own form, then time 4 epochs
+        // of K steps
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
             return pa_fail(s, PA_EDEVICE, "event");
-        int r = enqueue_epoch(d, P, d.K, st, nullptr, nullptr);
-        r |= (int)hipEventRecord(a, st);
+        int r = 0;
         if (tr.multi) {
             // a cooperative launch the device refuses (too many workgroups to
             // be resident) only rules this trial out
-            if (enqueue_resident(d, P, 4 * d.K, st, nullptr, nullptr) != 0) {
+            const bool refused = enqueue_resident(d, P, d.K, st, nullptr, nullptr) != 0;
+            if (!refused) r |= (int)hipEventRecord(a, st);
+            if (refused || enqueue_resident(d, P, 4 * d.K, st, nullptr, nullptr) != 0) {
                 (void)hipGetLastError();
                 (void)hipEventDestroy(a);
                 (void)hipEventDestroy(b);
@@ -1407,6 +1411,8 @@ pa_status batched_setup(pa_sim *s) {
                 continue;
             }
         } else {
+            r |= enqueue_epoch(d, P, d.K, st, nullptr, nullptr);
+            r |= (int)hipEventRecord(a, st);
             for (int e = 0; e < 4; ++e) r |= enqueue_epoch(d, P, d.K, st, nullptr, nullptr);
         }
         r |= (int)hipEventRecord(b, st);
