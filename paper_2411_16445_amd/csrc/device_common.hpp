@@ -22,8 +22,22 @@ namespace pa {
 // fourth round injects the next key-schedule word set, whose fifth word is
 // the xor of the key words and the parity constant 0x1BD11BDAA9FC1A22, plus
 // the injection count in the last word.
+// 64-bit left rotation by a constant r in (0, 64) as two 32-bit funnel
+// shifts of the halves (v_alignbit), instead of two 64-bit shifts and ors.
 __device__ __forceinline__ uint64_t rotl(uint64_t x, uint32_t r) {
-    return (x << r) | (x >> (64u - r));
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    uint32_t nhi, nlo;
+    if (r == 32) {
+        nhi = lo;
+        nlo = hi;
+    } else if (r < 32) {
+        nhi = __builtin_amdgcn_alignbit(hi, lo, 32u - r);
+        nlo = __builtin_amdgcn_alignbit(lo, hi, 32u - r);
+    } else {
+        nhi = __builtin_amdgcn_alignbit(lo, hi, 64u - r);
+        nlo = __builtin_amdgcn_alignbit(hi, lo, 64u - r);
+    }
+    return ((uint64_t)nhi << 32) | nlo;
 }
 
 __device__ inline void threefry4x64_12(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
