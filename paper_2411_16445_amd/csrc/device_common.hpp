@@ -101,8 +101,7 @@ static __device__ __attribute__((noinline)) double noise_increment(uint64_t seed
 // square root and sine or cosine in FP32 (the hardware's approximations);
 // it differs from the FP64 normal by FP32 rounding, far below the noise's
 // own scale in the FP64 early-phase weight.
-static __device__ __attribute__((noinline)) double noise_increment_f32(uint64_t seed, uint64_t sid, uint64_t n,
-                                                               double sigma, double th, double ah) {
+__device__ __forceinline__ float std_normal_f32(uint64_t seed, uint64_t sid, uint64_t n) {
     uint64_t x[4];
     threefry4x64_12(n >> 2, 0, 0, 0, seed, sid, NOISE_TAG, 0, x);
     const uint32_t lane = (uint32_t)(n & 3);
@@ -112,8 +111,31 @@ static __device__ __attribute__((noinline)) double noise_increment_f32(uint64_t 
     const float ub = ((float)(uint32_t)(xb >> 40) + 0.5f) * 0x1.0p-24f;
     const float r = __fsqrt_rn(-2.0f * __logf(ua));
     const float ang = 6.28318530717958648f * ub;
-    const float nrm = (lane & 1) ? r * __sinf(ang) : r * __cosf(ang);
-    return sigma * sqrt(th * ah) * (double)nrm;
+    return (lane & 1) ? r * __sinf(ang) : r * __cosf(ang);
+}
+
+// The mixed form's increment sigma sqrt((Theta_p + Theta_d) dt / tau_h) N
+// with the factor, like the normal, in FP32.
+__device__ __forceinline__ double noise_f32(uint64_t seed, uint64_t sid, uint64_t n, double sigma, double th,
+                                            double ah) {
+    const float k = (float)sigma * __fsqrt_rn((float)(th * ah));
+    return (double)(k * std_normal_f32(seed, sid, n));
+}
+
+static __device__ __attribute__((noinline)) double noise_increment_f32(uint64_t seed, uint64_t sid, uint64_t n,
+                                                               double sigma, double th, double ah) {
+    return noise_f32(seed, sid, n, sigma, th, ah);
+}
+
+// noise_increment_f32 of two synapses (ids sid1, sid2, threshold sums th1,
+// th2) in one call, the two generators' arithmetic interleaved.
+struct NoisePair {
+    double a, b;
+};
+static __device__ __attribute__((noinline)) NoisePair noise_increment2_f32(uint64_t seed, uint64_t sid1,
+                                                                         uint64_t sid2, uint64_t n, double sigma,
+                                                                         double th1, double th2, double ah) {
+    return {noise_f32(seed, sid1, n, sigma, th1, ah), noise_f32(seed, sid2, n, sigma, th2, ah)};
 }
 
 constexpr uint64_t POIS_TAG = 0x706f6973736f6e21ull;
