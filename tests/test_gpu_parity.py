@@ -183,6 +183,47 @@ def test_noise_path_matches_bitwise_generator():
         assert np.abs(ho - h).max() > 1e-6  # the noise is there
 
 
+def test_mixed_noise_of_paired_synapses_matches_single_draws():
+    """The mixed form draws the noise of a lane's two synapses in one call in
+    256-lane workgroups and with one call per synapse in smaller ones: the
+    same bits either way, for synapses above one calcium threshold, both or
+    none.  Against the oracle's FP64 normal the FP32 normal and factor stay
+    within 5e-3 of the largest increment (a wrong threshold sum is off by
+    41 %, a wrong word pair by the whole increment)."""
+    b = netgen._Builder()
+    b.add_cell([-1], [20.0], [20.0], [netgen.MECH_PAS])
+    n = 3000
+    for _ in range(n):
+        b.add_syn(0, 0, netgen.KIND_STC, 5.0, 0.0)
+    net = b.finish("noise", 0.2, 10.0, 123456789, netgen.STC_TABLE5)
+    o = oracle.Oracle(net)
+    sims = []
+    for bt, sw in ((128, 1), (256, 3)):
+        s = Simulation(net, mode="batched", precision="mixed", exchange="kernel", cells_per_block=1,
+                       block_threads=bt, solver_waves=sw)
+        assert s.stats()["block_threads"] == bt
+        sims.append(s)
+    rng = np.random.default_rng(1)
+    for k in range(4):
+        _say(f"mixed paired noise step {k}")
+        h = rng.uniform(3.0, 5.0, n)
+        c = rng.choice([0.5, 2.0, 50.0], n)
+        for x in [o] + sims:
+            x.write("h", h)
+            x.write("c", c)
+        o.run(1)
+        for s in sims:
+            s.advance_steps(1)
+        ho = o.read("h")
+        h128, h256 = (s.read("h") for s in sims)
+        np.testing.assert_array_equal(h128, h256)
+        inc = np.abs(ho - h)
+        assert np.abs(h256 - ho).max() <= 5e-3 * inc.max()
+        drawn = c > 1.2
+        assert np.abs(h256 - h)[drawn].min() > 0.0
+        assert np.abs(h256 - ho)[~drawn].max() <= 1e-12 * np.abs(ho).max()
+
+
 def test_gpu_runs_are_deterministic():
     net = netgen.tiny(seed=21, n_cells=17, t_end=150.0)
     _say("determinism tiny seed=21")
