@@ -934,6 +934,16 @@ __device__ __forceinline__ void syn_noise(const DevNet &d, uint32_t s, uint64_t 
     }
 }
 
+// Whether a synapse with step-start calcium c draws noise at this step:
+// the calcium after the post-synaptic jump above either threshold, the
+// comparisons of syn_compute in the same precision (its threshold sum is
+// then positive).
+template <class T>
+__device__ __forceinline__ bool syn_draws(const Stc &P, bool post, T c) {
+    const T cc = post ? c + (T)P.c_post : c;
+    return (cc - (T)P.theta_p > T(0)) || (cc - (T)P.theta_d > T(0));
+}
+
 // The STDP synapse's step in place of the tagging-and-capture outputs: the
 // post-synaptic hook (a_post += A_post, w += a_pre), then both traces decay.
 template <class T>

@@ -1000,17 +1000,28 @@ __global__ PA_EPOCH_BOUNDS(BS) void k_epoch(DevNet d, const uint32_t *__restrict
                 const bool k1 = kd1 == 1, k2 = kd2 == 1;
                 // with diffusion, z takes the protein of the synapse's CV
                 const double p1 = dif ? sPrp[sSynCv[s]] : p, p2 = dif ? sPrp[sSynCv[s2]] : p;
+                // 256-lane workgroups draw both synapses' noise in one call,
+                // the ids that key it requested before the update so that its
+                // arithmetic covers the loads' latency; the smaller
+                // workgroups keep a call per synapse, which measured faster
+                // on networks whose synapses rarely draw noise
+                constexpr bool pairs = sizeof(T) == 4 && BS == 256;
+                bool dr1 = false, dr2 = false;
+                uint32_t id1 = 0, id2 = 0;
+                if constexpr (pairs) {
+                    dr1 = k1 && syn_draws<T>(d.stc, post, x1.c);
+                    dr2 = two && k2 && syn_draws<T>(d.stc, post, x2.c);
+                    if (dr1 || dr2) {
+                        id1 = d.syn_sid[s0 + s];
+                        id2 = d.syn_sid[s0 + s2];
+                    }
+                }
                 SynOut<T> o1, o2;
                 syn_compute2<T>(d, p1, p2, post, x1, x2, o1, o2);
-                if constexpr (sizeof(T) == 4 && BS == 256) {
-                    // both synapses' noise in one call (both id loads and
-                    // both generators at once); the smaller workgroups keep
-                    // a call per synapse, which measured faster on networks
-                    // whose synapses rarely draw noise
-                    const bool dr1 = k1 && o1.th > 0.0, dr2 = two && k2 && o2.th > 0.0;
+                if constexpr (pairs) {
                     if (dr1 || dr2) {
-                        const NoisePair r = noise_increment2_f32(d.seed, d.syn_sid[s0 + s], d.syn_sid[s0 + s2], n,
-                                                                 d.stc.sigma_pl, o1.th, o2.th, d.dt / d.stc.tau_h);
+                        const NoisePair r = noise_increment2_f32(d.seed, id1, id2, n, d.stc.sigma_pl, o1.th, o2.th,
+                                                                 d.dt / d.stc.tau_h);
                         if (dr1) o1.h += r.a;
                         if (dr2) o2.h += r.b;
                     }
