@@ -392,6 +392,22 @@ pa_status pa_state_load(pa_sim *sim, const void *buf, uint64_t bytes);
 /* Sizes and counters. */
 pa_status pa_stats_get(const pa_sim *sim, pa_stats *out);
 
+/* Batched form: choose the plan again (workgroup shape, cells per
+ * workgroup, solver wavefronts, spike exchange; within the limits the
+ * configuration fixes) by timing trial epochs from the present state, which
+ * is restored after each trial, as pa_finalize does from the initial
+ * state.  The work of a step depends on the network's regime (a network at
+ * rest draws no weight noise; one whose synapses carry calcium above a
+ * threshold draws it on most of them every step), so a plan chosen at rest
+ * can be slow later.  No step is advanced and no spike is recorded.  The
+ * replaced plan's block table (a few bytes per workgroup) stays allocated
+ * until pa_sim_destroy.  Results may change in the last bits of the mixed
+ * form's FP32 arithmetic with the plan; the FP64 batched form gives the
+ * same bits under every plan.
+ * Errors: PA_EINVAL (plain form), PA_ESTATE (not finalized, or failed),
+ * PA_ENOMEM, PA_EDEVICE; after an error the simulation is failed. */
+pa_status pa_retune(pa_sim *sim);
+
 /* Per-launch timing of the dominant kernel (the per-step synapse and
  * plasticity kernel in the plain form, the fused epoch kernel in the
  * batched form) with HIP events on the simulation's stream.  When enabled,

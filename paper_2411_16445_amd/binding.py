@@ -35,7 +35,7 @@ EXPORTS = [
     "pa_synapses_add", "pa_connect", "pa_trains_add", "pa_poisson_add", "pa_clamps_add", "pa_probes_add",
     "pa_finalize", "pa_advance", "pa_advance_steps", "pa_spikes_count", "pa_spikes_read",
     "pa_probe_count", "pa_probe_read", "pa_state_read", "pa_state_read_device", "pa_state_write",
-    "pa_stats_get", "pa_fast_forward", "pa_state_size", "pa_state_save", "pa_state_load",
+    "pa_stats_get", "pa_retune", "pa_fast_forward", "pa_state_size", "pa_state_save", "pa_state_load",
     "pa_kernel_timing", "pa_kernel_time", "pa_tree_solve", "pa_tree_solve_noalloc", "pa_gb_trials", "pa_last_error",
     "pa_status_str",
 ]
@@ -143,6 +143,7 @@ def load_library(path: str = None):
         "pa_state_read_device": (st, [_P, C.c_int32, _P, C.c_uint64]),
         "pa_state_write": (st, [_P, C.c_int32, _P, C.c_uint64]),
         "pa_stats_get": (st, [_P, C.POINTER(pa_stats)]),
+        "pa_retune": (st, [_P]),
         "pa_fast_forward": (st, [_P, C.c_uint64, C.c_double]),
         "pa_state_size": (st, [_P, C.POINTER(C.c_uint64)]),
         "pa_state_save": (st, [_P, _P, C.c_uint64]),
@@ -354,6 +355,10 @@ class Simulation:
 
     def advance_steps(self, n: int):
         self._check(self._lib.pa_advance_steps(self._h, int(n)))
+
+    def retune(self):
+        """Batched form: choose the plan again from the present state."""
+        self._check(self._lib.pa_retune(self._h))
 
     def fast_forward(self, n_long: int, dt_long: float):
         """n_long long steps of the slow plasticity variables only (spiking

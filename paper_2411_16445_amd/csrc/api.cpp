@@ -1226,6 +1226,21 @@ extern "C" pa_status pa_advance(pa_sim *s, double t_until) {
 
 // ----------------------------------------------------------------------
 // Fast-forward and the device state dump.
+extern "C" pa_status pa_retune(pa_sim *s) {
+    if (!s) return PA_EINVAL;
+    if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
+    if (s->state == 2) return fail(s, PA_ESTATE, "simulation failed earlier: %s", s->err.c_str());
+    if (s->cfg.mode != PA_BATCHED) return fail(s, PA_EINVAL, "only the batched form has a plan to tune");
+    HIPCHECK(s, hipStreamSynchronize(s->stream), "retune");
+    // the trials run from the present state and restore it (as at
+    // pa_finalize); the old plan's block table stays allocated with the
+    // simulation's other memory
+    batched_release(s);
+    const pa_status st = batched_setup(s);
+    if (st != PA_OK) s->state = 2;
+    return st;
+}
+
 extern "C" pa_status pa_fast_forward(pa_sim *s, uint64_t n_long, double dt_long) {
     if (!s) return PA_EINVAL;
     if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");

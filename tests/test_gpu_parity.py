@@ -285,6 +285,42 @@ def test_workgroup_shapes_and_exchange_modes_are_bitwise_identical():
             np.testing.assert_array_equal(a, b)
 
 
+def test_retune_keeps_the_state_and_the_fp64_bits():
+    """pa_retune re-times the plans from the present state and restores it:
+    no step advances, the state reads the same, and the FP64 batched form
+    continues with the bits of a run that was never retuned (the same bits
+    under every plan).  The plain form has no plan to tune."""
+    net = netgen.tiny(seed=8, n_cells=23, t_end=150.0)
+    _say("retune tiny seed=8")
+    ref = Simulation(net, mode="batched")
+    ref.advance_steps(700)
+    s = Simulation(net, mode="batched")
+    s.advance_steps(350)
+    before = [s.read(k) for k in ("V", "h", "z", "g", "c", "p")]
+    steps = s.stats()["steps"]
+    s.retune()
+    assert s.stats()["steps"] == steps
+    for a, k in zip(before, ("V", "h", "z", "g", "c", "p")):
+        np.testing.assert_array_equal(a, s.read(k), err_msg=k)
+    s.advance_steps(350)
+    for a, b in zip(ref.spikes(), s.spikes()):
+        np.testing.assert_array_equal(a, b)
+    for k in ("V", "h", "z", "g", "c", "p"):
+        np.testing.assert_array_equal(ref.read(k), s.read(k), err_msg=k)
+    for a, b in zip(ref.event_stats(), s.event_stats()):
+        np.testing.assert_array_equal(a, b)
+    m = Simulation(net, mode="batched", precision="mixed")
+    m.advance_steps(200)
+    vm = m.read("V")
+    m.retune()
+    np.testing.assert_array_equal(vm, m.read("V"))
+    m.advance_steps(100)
+    assert np.isfinite(m.read("V")).all()
+    p = Simulation(net, mode="plain")
+    with pytest.raises(PAError):
+        p.retune()
+
+
 def test_mixed_exchange_modes_are_bitwise_identical():
     net = netgen.config2(t_end=100.0)
     out = []
