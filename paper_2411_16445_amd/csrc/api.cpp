@@ -1231,6 +1231,11 @@ extern "C" pa_status pa_retune(pa_sim *s) {
     if (s->state == 0) return fail(s, PA_ESTATE, "pa_finalize first");
     if (s->state == 2) return fail(s, PA_ESTATE, "simulation failed earlier: %s", s->err.c_str());
     if (s->cfg.mode != PA_BATCHED) return fail(s, PA_EINVAL, "only the batched form has a plan to tune");
+    // the grid barrier counts the barriers of the present plan (per
+    // workgroup, per group of workgroups): a new plan starts them at zero,
+    // as pa_finalize's allocation does
+    HIPCHECK(s, hipMemsetAsync(s->d.bar_grp, 0, 34 * 32 * sizeof(uint32_t), s->stream), "retune");
+    HIPCHECK(s, hipMemsetAsync(s->d.blk_done, 0, (size_t)s->d.n_cells * sizeof(uint64_t), s->stream), "retune");
     HIPCHECK(s, hipStreamSynchronize(s->stream), "retune");
     // the trials run from the present state and restore it (as at
     // pa_finalize); the old plan's block table stays allocated with the

@@ -316,6 +316,16 @@ def test_retune_keeps_the_state_and_the_fp64_bits():
     np.testing.assert_array_equal(vm, m.read("V"))
     m.advance_steps(100)
     assert np.isfinite(m.read("V")).all()
+    # resident plans only: the grid barrier's counts start again with the
+    # new plan, whatever its number of workgroups
+    r = Simulation(net, mode="batched", exchange="resident", block_threads=128)
+    r.advance_steps(350)
+    r.retune()
+    assert r.stats()["exchange"] == 2
+    r.advance_steps(350)
+    for a, b in zip(ref.spikes(), r.spikes()):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(ref.read("V"), r.read("V"))
     p = Simulation(net, mode="plain")
     with pytest.raises(PAError):
         p.retune()
